@@ -1,0 +1,222 @@
+/*
+ * discomatch.h -- C ABI of the MI355X (gfx950) dual solver for the
+ * geometrically consistent product-triangle ILP of DiscoMatch
+ * (arXiv 2310.08230).
+ *
+ * The problem (Sec. 3.1, Eq. (P)):  min c^T x  s.t.  A x = b,  x in {0,1}^|P|,
+ * where P is the product space of triangle-triangle, triangle-edge and
+ * triangle-vertex matching elements, A stacks the closedness rows
+ * (A^d x = 0) and the projection rows of both shapes (A^M x = 1, A^N x = 1),
+ * and c is built from per-vertex descriptors and mixed areas (Sec. 4.2,
+ * Eq. (cost)).  The solver works on its Lagrangean decomposition dual
+ * (Sec. 3.2, Eq. (D)): one subproblem per row, multipliers lambda^j_i with
+ * sum_{j in J_i} lambda^j_i = c_i.
+ *
+ * Conventions for every entry point:
+ *  - Pointers marked [device] are device memory of the context's GPU, owned by
+ *    the caller, read or written on the context's stream in stream order.
+ *    Pointers marked [host] are host memory owned by the caller.
+ *  - Functions that return host values (sizes, bounds, flags) synchronise the
+ *    context's stream before returning; the others only enqueue work.
+ *  - Nothing throws or exits.  A negative return is an error; its message is
+ *    in dm_last_error(ctx).  A context is not thread-safe; use one per stream.
+ *  - The context owns the product space, the incidence and the solver state
+ *    it builds (device memory it allocates itself, released by dm_destroy).
+ */
+#ifndef DISCOMATCH_H
+#define DISCOMATCH_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t dm_status;
+
+enum {
+  DM_OK = 0,
+  DM_ERR_INVALID_ARG = -1, /* bad pointer, size, index or order of calls     */
+  DM_ERR_MESH = -2,        /* not a closed, oriented 2-manifold             */
+  DM_ERR_GENUS = -3,       /* Euler characteristics of X and Y differ       */
+  DM_ERR_INFEASIBLE = -4,  /* A x = b has no 0/1 solution (proved by presolve) */
+  DM_ERR_NONFINITE = -5,   /* NaN or Inf in vertices or descriptors         */
+  DM_ERR_WORKSPACE = -6,   /* a size exceeds what the kernels support       */
+  DM_ERR_HIP = -7,         /* HIP runtime error                             */
+  DM_ERR_STATE = -8        /* a prerequisite step has not been run          */
+};
+
+enum { DM_PREC_FP64 = 0, DM_PREC_FP32 = 1, DM_PREC_BF16 = 2 };
+
+typedef struct dm_ctx dm_ctx;
+
+/* A triangle mesh (Table "notation": V in R^{|V| x 3}, T in N^{|T| x 3}).
+ * verts [device] float32 [nv*3]; faces [device] int32 [nf*3], counter-
+ * clockwise seen from outside. */
+typedef struct {
+  int32_t nv, nf;
+  const float* verts;
+  const int32_t* faces;
+} dm_mesh;
+
+/* Sizes of a built product space (all counts after K-candidate pruning). */
+typedef struct {
+  int64_t n_prod_tri;  /* |P|: kept product triangles                       */
+  int64_t n_rows_full; /* rows of A before presolve                         */
+  int64_t nnz_full;    /* nonzeros of A before presolve                     */
+  int64_t n_closed_full; /* closedness rows before presolve                 */
+  int64_t n_free;      /* variables left free by presolve                   */
+  int64_t n_fixed1;    /* variables presolve fixed to 1                     */
+  int64_t n_rows;      /* rows of the presolved problem (the subproblems)   */
+  int64_t nnz;         /* its nonzeros = number of multipliers lambda^j_i   */
+  int64_t n_short_rows;/* closedness rows in the presolved problem          */
+  int64_t n_edges_x, n_edges_y;
+  int64_t n_cand;      /* |C|: candidate vertex pairs                       */
+  int32_t presolve_rounds;
+  int32_t max_short_row;
+} dm_space_info;
+
+/* Create a context on HIP device `device`; work is enqueued on `hip_stream`
+ * (a hipStream_t, may be NULL for the default stream). */
+dm_status dm_create(int32_t device, void* hip_stream, dm_ctx** out);
+dm_status dm_destroy(dm_ctx* ctx);
+/* Message of the last error on ctx (empty string if none); owned by ctx. */
+const char* dm_last_error(const dm_ctx* ctx);
+/* Rebind the stream used by later calls. */
+dm_status dm_set_stream(dm_ctx* ctx, void* hip_stream);
+
+/* Candidate vertex pairs (A2).  Distances d(m,n) = ||F_X(m) - F_Y(n)||_2 from
+ * a tiled GEMM (prec = DM_PREC_BF16: BF16 MFMA on descriptors rounded to BF16
+ * with FP32 accumulation; DM_PREC_FP32: FP32), then for every vertex of X the
+ * K nearest vertices of Y by (d, index), and the converse.  The paper prunes
+ * its product spaces only in the coarse-to-fine scheme (Sec. 5.2); the rule
+ * here is the library's.
+ *  FX [device] float32 [nvx*D] row-major; FY [device] float32 [nvy*D];
+ *  cand_xy [device] int32 [nvx*K] out; cand_yx [device] int32 [nvy*K] out.
+ *  Errors: K < 1, K > nvx or nvy, nvx or nvy > 4096, D < 1. */
+dm_status dm_knn_candidates(dm_ctx* ctx, const float* FX, int32_t nvx, const float* FY,
+                            int32_t nvy, int32_t D, int32_t K, int32_t prec, int32_t* cand_xy,
+                            int32_t* cand_yx);
+
+/* Product space, constraints and presolve (A1, A3; Sec. 3.1, Eq. (P)).
+ * Validates both meshes, enumerates every product triangle whose three
+ * product vertices (m, n) lie in the candidate set C (the union of cand_xy and
+ * cand_yx), builds the rows of A (closedness rows per undirected product edge
+ * sorted by key, then one projection row per face of X, then per face of Y)
+ * and runs integer unit propagation to a fixpoint.  Replaces any previous
+ * space on ctx.  Synchronises; fills *info.
+ *  X, Y [host] descriptors of device meshes; cand_* [device] as above.
+ *  Errors: DM_ERR_MESH, DM_ERR_GENUS, DM_ERR_INFEASIBLE, DM_ERR_WORKSPACE. */
+dm_status dm_build_product_space(dm_ctx* ctx, const dm_mesh* X, const dm_mesh* Y,
+                                 const int32_t* cand_xy, const int32_t* cand_yx, int32_t K,
+                                 dm_space_info* info);
+
+/* Export arrays of the built space (for checks) into caller buffers [device]:
+ *  DM_ARR_PV      int32 [n_prod_tri*3]  product-vertex ids m*nvy+n per corner
+ *  DM_ARR_CODE    int32 [n_prod_tri*4]  (x class, x id, y class*8+pattern, y id),
+ *                 class 0 face, 1 edge, 2 vertex
+ *  DM_ARR_STATE   int8  [n_prod_tri]    -1 free, 0 or 1 fixed by presolve
+ *  DM_ARR_ROW_KEY int64 [n_rows_full]   closedness: min*NPV+max (NPV = nvx*nvy);
+ *                                       projection rows: face id
+ *  DM_ARR_ROW_PTR int64 [n_rows_full+1], DM_ARR_ENT_VAR int64 [nnz_full],
+ *  DM_ARR_ENT_COEF int32 [nnz_full], DM_ARR_ROW_B int32 [n_rows_full]
+ *  DM_ARR_FREE_VAR int64 [n_free]       element of each free variable
+ *  DM_ARR_RROW_ORIG int64 [n_rows], DM_ARR_RROW_PTR int64 [n_rows+1],
+ *  DM_ARR_RENT_VAR int64 [nnz], DM_ARR_RENT_COEF int32 [nnz], DM_ARR_RROW_B int32 [n_rows]
+ *  DM_ARR_EDGES_X / _Y int32 [n_edges*2] sorted (min, max) vertex pairs
+ *  DM_ARR_CAND    uint8 [nvx*nvy]        1 where (m, n) is in C */
+enum {
+  DM_ARR_PV = 0, DM_ARR_CODE, DM_ARR_STATE, DM_ARR_ROW_KEY, DM_ARR_ROW_PTR, DM_ARR_ENT_VAR,
+  DM_ARR_ENT_COEF, DM_ARR_ROW_B, DM_ARR_FREE_VAR, DM_ARR_RROW_ORIG, DM_ARR_RROW_PTR,
+  DM_ARR_RENT_VAR, DM_ARR_RENT_COEF, DM_ARR_RROW_B, DM_ARR_EDGES_X, DM_ARR_EDGES_Y, DM_ARR_CAND
+};
+dm_status dm_get_space(dm_ctx* ctx, int32_t which, void* dst);
+
+/* Costs, Eq. (cost) (A4; Sec. 4.2): c_p = sum over the three product vertices
+ * (m_v, n_v) of p of (A_X(m_v) + A_Y(n_v)) * d(m_v, n_v), with mixed vertex
+ * areas (Meyer et al. 2003) of the posed meshes and the Euclidean descriptor
+ * distance d, computed in FP64 (DM_PREC_FP64), FP32 (DM_PREC_FP32) or from a
+ * BF16 MFMA GEMM with FP32 accumulation (DM_PREC_BF16).  Also sets the
+ * solver's costs (stored in the message precision chosen later) and the
+ * constant from variables fixed to 1.
+ *  FX, FY [device] float32 as in dm_knn_candidates (same nvx, nvy as the space).
+ *  cost [device] float32 [n_prod_tri] out, or NULL. */
+dm_status dm_build_costs(dm_ctx* ctx, const float* FX, const float* FY, int32_t D, int32_t prec,
+                         float* cost);
+
+/* Initial multipliers lambda^j_i = c_i / |J_i| (A5; feasible for Eq. (D)).
+ *  lambda [device] float32 or float64 (per msg_prec) [nnz], CSR order of the
+ *  presolved rows (DM_ARR_RROW_PTR). */
+dm_status dm_init_lambda(dm_ctx* ctx, int32_t msg_prec, void* lambda);
+
+/* Jacobi min-marginal averaging (A6-A8; Sec. 3.2, the MMA step of Alg. 1):
+ * per iteration every row computes its minimum and its min-marginal
+ * differences M^j_i at the current lambda, the bound offset + sum of row
+ * minima goes to lb_trace[t] (FP64, fixed summation order), and
+ *   lambda^j_i <- lambda^j_i - omega * (M^j_i - mean_{k in J_i} M^k_i).
+ * temperature > 0 replaces every min by the soft-min -T log sum exp(-./T)
+ * (smoothed dual).  lambda is updated in place and must satisfy
+ * sum_j lambda^j_i = c_i on entry (e.g. from dm_init_lambda).
+ *  msg_prec DM_PREC_FP32 (lambda float32) or DM_PREC_FP64 (float64).
+ *  lb_trace [device] double [iters] out, or NULL.  Enqueue only. */
+dm_status dm_dual_solve(dm_ctx* ctx, int32_t iters, float omega, float temperature,
+                        int32_t msg_prec, void* lambda, double* lb_trace);
+
+/* Dual objective (A8; Eq. (D)) at lambda: offset + sum over rows of the row
+ * minimum (soft-min for temperature > 0).  Synchronises; *lb [host]. */
+dm_status dm_lower_bound(dm_ctx* ctx, const void* lambda, float temperature, int32_t msg_prec,
+                         double* lb);
+
+/* Primal rounding (A9, A10).  On a copy of (c, lambda): sweep all rows; when
+ * every free variable's min-marginal differences share one strict sign, take
+ * that assignment (M < 0 -> 1, M > 0 -> 0; Appendix "Coarse-to-fine",
+ * min-marginal equation) and check A x = b exactly in integers; otherwise
+ * perturb the copied costs (agreeing variables pushed towards their value by
+ * delta, the others by delta*u, u in [-1,1) from splitmix64(seed, round,
+ * variable)), run iters_per_round Jacobi iterations and grow delta by gamma.
+ * delta0 <= 0 means 0.1 * mean |M| at the first sweep.
+ *  x [device] uint8 [n_prod_tri] out (fixed variables included);
+ *  primal_obj, feasible, rounds_used [host] out.  A failed rounding is not an
+ *  error: it returns DM_OK with *feasible = 0.  Synchronises. */
+typedef struct {
+  int32_t rounds;
+  int32_t iters_per_round;
+  double delta0;
+  double gamma;
+  uint64_t seed;
+  float omega;
+  int32_t msg_prec;
+} dm_round_params;
+dm_status dm_round_primal(dm_ctx* ctx, const dm_round_params* params, const void* lambda,
+                          uint8_t* x, double* primal_obj, int32_t* feasible, int32_t* rounds_used);
+
+/* Exact integer check of A x = b over every row of the full ILP; returns the
+ * number of violated rows in *violations [host].  Synchronises. */
+dm_status dm_check_primal(dm_ctx* ctx, const uint8_t* x, int64_t* violations);
+
+/* Gradient of the smoothed bound L_T(lambda) (A11).  With
+ * lambda^j_i = c_i/|J_i| + phi^j_i and phi held fixed:
+ *   dL/dc_i = mean_j mu^j_i (free), 1 (fixed to 1), 0 (fixed to 0),
+ * where mu^j_i is the probability of s_i = 1 under exp(-s^T lambda^j / T);
+ * chained through Eq. (cost) to the descriptors with areas and candidates
+ * constant.  grad_out scales the result.  gcost [device] float32
+ * [n_prod_tri] out or NULL; gFX [device] float32 [nvx*D], gFY [nvy*D] out;
+ * *value [host] out (L_T) or NULL.  Synchronises when value is not NULL. */
+dm_status dm_smoothed_backward(dm_ctx* ctx, const void* lambda, float temperature,
+                               int32_t msg_prec, double grad_out, const float* FX,
+                               const float* FY, int32_t D, float* gcost, float* gFX, float* gFY,
+                               double* value);
+
+/* Mixed vertex areas (Meyer et al. 2003) of a device mesh, for checks.
+ *  out [device] double [nv]. */
+dm_status dm_mixed_areas(dm_ctx* ctx, const dm_mesh* M, double* out);
+
+/* Version string of the library build. */
+const char* dm_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* DISCOMATCH_H */

@@ -1,0 +1,286 @@
+"""ctypes wrapper of the FP64 CPU oracle (oracle.cpp).
+
+Test infrastructure only: the tests, the smoke check and the benchmark's
+CPU-baseline leg may import it; the library never does.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB = None
+
+OK, E_ARG, E_MESH, E_GENUS, E_INFEASIBLE, E_NONFINITE = 0, -1, -2, -3, -4, -5
+
+
+def lib():
+    global _LIB
+    if _LIB is None:
+        path = os.path.join(_HERE, "liboracle.so")
+        if not os.path.exists(path):
+            from . import build as _b  # noqa: F401  (package import)
+        _LIB = C.CDLL(path)
+        L = _LIB
+        P = C.c_void_p
+        L.or_mesh_check.argtypes = [C.c_int, C.c_int, P, P]
+        L.or_mesh_edges.argtypes = [C.c_int, C.c_int, P, P, P]
+        L.or_mixed_areas.argtypes = [C.c_int, C.c_int, P, P, P]
+        L.or_knn.argtypes = [C.c_int, P, C.c_int, P, C.c_int, C.c_int, P, P]
+        L.or_desc_dist.argtypes = [C.c_int, P, P, P, P, C.c_int, P]
+        L.or_space_build.argtypes = [C.c_int, C.c_int, P, P, C.c_int, C.c_int, P, P, P, P,
+                                     C.c_int, P]
+        L.or_space_build.restype = C.c_void_p
+        L.or_space_free.argtypes = [P]
+        L.or_space_info.argtypes = [P, P]
+        L.or_space_get.argtypes = [P, C.c_int, P]
+        L.or_space_costs.argtypes = [P, P, P, C.c_int]
+        L.or_space_set_costs.argtypes = [P, P]
+        L.or_init_lambda.argtypes = [P, P]
+        L.or_dual_solve.argtypes = [P, C.c_int, C.c_double, C.c_double, P, P, C.c_int]
+        L.or_lower_bound.argtypes = [P, P, C.c_double]
+        L.or_lower_bound.restype = C.c_double
+        L.or_min_marginals.argtypes = [P, P, C.c_double, P, P, P]
+        L.or_row_dp.argtypes = [C.c_int, P, C.c_int, P, C.c_double, P, P]
+        L.or_row_dp.restype = C.c_double
+        L.or_check_primal.argtypes = [P, P]
+        L.or_check_primal.restype = C.c_int64
+        L.or_round.argtypes = [P, P, C.c_int, C.c_int, C.c_double, C.c_double, C.c_uint64,
+                               C.c_double, P, P, P, P]
+        L.or_uniform_pm1.argtypes = [C.c_uint64, C.c_uint32, C.c_uint32]
+        L.or_uniform_pm1.restype = C.c_double
+        L.or_smoothed_grad.argtypes = [P, P, C.c_double, P, P, C.c_int, P, P, P, P]
+        L.or_smoothed_value_phi.argtypes = [P, P, P, C.c_double]
+        L.or_smoothed_value_phi.restype = C.c_double
+        L.or_costs_for.argtypes = [P, P, P, C.c_int, P]
+    return _LIB
+
+
+def _p(a):
+    return a.ctypes.data_as(C.c_void_p)
+
+
+def _c(a, dt):
+    return np.ascontiguousarray(a, dtype=dt)
+
+
+class OracleError(RuntimeError):
+    def __init__(self, code):
+        super().__init__(f"oracle status {code}")
+        self.code = code
+
+
+def mesh_check(F, nv):
+    F = _c(F, np.int32)
+    ne = C.c_int(0)
+    st = lib().or_mesh_check(nv, len(F), _p(F), C.byref(ne))
+    return st, ne.value
+
+
+def mesh_edges(F, nv):
+    F = _c(F, np.int32)
+    st, ne = mesh_check(F, nv)
+    if st:
+        raise OracleError(st)
+    E = np.zeros((ne, 2), np.int32)
+    FE = np.zeros((len(F), 3), np.int32)
+    lib().or_mesh_edges(nv, len(F), _p(F), _p(E), _p(FE))
+    return E, FE
+
+
+def mixed_areas(V, F):
+    V = _c(V, np.float32)
+    F = _c(F, np.int32)
+    out = np.zeros(len(V), np.float64)
+    st = lib().or_mixed_areas(len(V), len(F), _p(V), _p(F), _p(out))
+    if st:
+        raise OracleError(st)
+    return out
+
+
+def knn(DX, DY, K):
+    DX = _c(DX, np.float32)
+    DY = _c(DY, np.float32)
+    cxy = np.zeros((len(DX), K), np.int32)
+    cyx = np.zeros((len(DY), K), np.int32)
+    st = lib().or_knn(len(DX), _p(DX), len(DY), _p(DY), DX.shape[1], K, _p(cxy), _p(cyx))
+    if st:
+        raise OracleError(st)
+    return cxy, cyx
+
+
+def desc_dist(DX, DY, m_idx, n_idx):
+    DX = _c(DX, np.float32)
+    DY = _c(DY, np.float32)
+    m_idx = _c(m_idx, np.int32)
+    n_idx = _c(n_idx, np.int32)
+    out = np.zeros(len(m_idx), np.float64)
+    lib().or_desc_dist(len(m_idx), _p(m_idx), _p(n_idx), _p(DX), _p(DY), DX.shape[1], _p(out))
+    return out
+
+
+def row_dp(coef, b, lam, T=0.0):
+    coef = _c(coef, np.int32)
+    lam = _c(lam, np.float64)
+    M = np.zeros(len(lam))
+    mu = np.zeros(len(lam))
+    v = lib().or_row_dp(len(lam), _p(coef), int(b), _p(lam), float(T), _p(M), _p(mu))
+    return v, M, mu
+
+
+def uniform_pm1(seed, r, i):
+    return lib().or_uniform_pm1(seed, r, i)
+
+
+class Space:
+    """Product space + presolved ILP + costs, held by the oracle."""
+
+    INFO = ("nP", "n_rows_full", "nnz_full", "n_closed_full", "n_free", "n_fixed1",
+            "n_rows", "nnz")
+
+    def __init__(self, VX, FX, VY, FY, cand_xy, cand_yx):
+        self._keep = [_c(VX, np.float32), _c(FX, np.int32), _c(VY, np.float32),
+                      _c(FY, np.int32), _c(cand_xy, np.int32), _c(cand_yx, np.int32)]
+        VX, FX, VY, FY, cxy, cyx = self._keep
+        st = C.c_int(0)
+        self.h = lib().or_space_build(len(VX), len(FX), _p(VX), _p(FX), len(VY), len(FY),
+                                      _p(VY), _p(FY), _p(cxy), _p(cyx), cxy.shape[1],
+                                      C.byref(st))
+        if not self.h:
+            raise OracleError(st.value)
+        info = np.zeros(8, np.int64)
+        lib().or_space_info(self.h, _p(info))
+        self.info = dict(zip(self.INFO, (int(x) for x in info)))
+        self.nvx, self.nvy = len(VX), len(VY)
+        self.nfx, self.nfy = len(FX), len(FY)
+
+    def __del__(self):
+        if getattr(self, "h", None):
+            lib().or_space_free(self.h)
+            self.h = None
+
+    def get(self, name):
+        i = self.info
+        spec = {
+            "pv": (0, np.int32, (i["nP"], 3)),
+            "code": (1, np.int32, (i["nP"], 4)),
+            "state": (2, np.int8, (i["nP"],)),
+            "row_key": (3, np.int64, (i["n_rows_full"],)),
+            "row_ptr": (4, np.int64, (i["n_rows_full"] + 1,)),
+            "ent_var": (5, np.int64, (i["nnz_full"],)),
+            "ent_coef": (6, np.int32, (i["nnz_full"],)),
+            "row_b": (7, np.int32, (i["n_rows_full"],)),
+            "free_var": (8, np.int64, (i["n_free"],)),
+            "rrow_orig": (9, np.int64, (i["n_rows"],)),
+            "rrow_ptr": (10, np.int64, (i["n_rows"] + 1,)),
+            "rent_var": (11, np.int64, (i["nnz"],)),
+            "rent_coef": (12, np.int32, (i["nnz"],)),
+            "rrow_b": (13, np.int32, (i["n_rows"],)),
+            "deg": (14, np.int32, (i["n_free"],)),
+            "cost": (15, np.float64, (i["nP"],)),
+            "offset": (16, np.float64, (1,)),
+            "cand": (17, np.uint8, (self.nvx, self.nvy)),
+        }[name]
+        out = np.zeros(spec[2], spec[1])
+        st = lib().or_space_get(self.h, spec[0], _p(out))
+        if st:
+            raise OracleError(st)
+        return out
+
+    def costs(self, DX, DY):
+        DX = _c(DX, np.float32)
+        DY = _c(DY, np.float32)
+        st = lib().or_space_costs(self.h, _p(DX), _p(DY), DX.shape[1])
+        if st:
+            raise OracleError(st)
+        return self.get("cost")
+
+    def costs_for(self, DX, DY):
+        """Element costs for other descriptors, without changing the state."""
+        DX = _c(DX, np.float32)
+        DY = _c(DY, np.float32)
+        out = np.zeros(self.info["nP"])
+        st = lib().or_costs_for(self.h, _p(DX), _p(DY), DX.shape[1], _p(out))
+        if st:
+            raise OracleError(st)
+        return out
+
+    def set_costs(self, cost):
+        cost = _c(cost, np.float64)
+        lib().or_space_set_costs(self.h, _p(cost))
+
+    @property
+    def offset(self):
+        return float(self.get("offset")[0])
+
+    def init_lambda(self):
+        lam = np.zeros(self.info["nnz"])
+        st = lib().or_init_lambda(self.h, _p(lam))
+        if st:
+            raise OracleError(st)
+        return lam
+
+    def dual_solve(self, iters, omega=0.5, T=0.0, lam=None):
+        init = lam is None
+        lam = np.zeros(self.info["nnz"]) if init else _c(lam, np.float64).copy()
+        trace = np.zeros(max(iters, 1))
+        st = lib().or_dual_solve(self.h, iters, omega, T, _p(lam), _p(trace), int(init))
+        if st:
+            raise OracleError(st)
+        return lam, trace[:iters]
+
+    def lower_bound(self, lam, T=0.0):
+        lam = _c(lam, np.float64)
+        return lib().or_lower_bound(self.h, _p(lam), float(T))
+
+    def min_marginals(self, lam, T=0.0):
+        lam = _c(lam, np.float64)
+        M = np.zeros(self.info["nnz"])
+        rm = np.zeros(self.info["n_rows"])
+        mu = np.zeros(self.info["nnz"])
+        lib().or_min_marginals(self.h, _p(lam), float(T), _p(M), _p(rm), _p(mu))
+        return M, rm, mu
+
+    def check_primal(self, x):
+        x = _c(x, np.uint8)
+        return int(lib().or_check_primal(self.h, _p(x)))
+
+    def round(self, lam, R=30, T_iters=25, delta0=0.0, gamma=1.5, seed=0, omega=0.5):
+        lam = _c(lam, np.float64)
+        x = np.zeros(self.info["nP"], np.uint8)
+        p = C.c_double(0)
+        feas = C.c_int(0)
+        rounds = C.c_int(0)
+        st = lib().or_round(self.h, _p(lam), R, T_iters, float(delta0), float(gamma),
+                            C.c_uint64(seed), float(omega), _p(x), C.byref(p), C.byref(feas),
+                            C.byref(rounds))
+        if st:
+            raise OracleError(st)
+        return x, p.value, bool(feas.value), rounds.value
+
+    def smoothed_grad(self, lam, T, DX, DY):
+        lam = _c(lam, np.float64)
+        DX = _c(DX, np.float32)
+        DY = _c(DY, np.float32)
+        gc = np.zeros(self.info["nP"])
+        gX = np.zeros(DX.shape)
+        gY = np.zeros(DY.shape)
+        v = C.c_double(0)
+        st = lib().or_smoothed_grad(self.h, _p(lam), float(T), _p(DX), _p(DY), DX.shape[1],
+                                    _p(gc), _p(gX), _p(gY), C.byref(v))
+        if st:
+            raise OracleError(st)
+        return v.value, gc, gX, gY
+
+    def smoothed_value_phi(self, cost, phi, T):
+        cost = _c(cost, np.float64)
+        phi = _c(phi, np.float64)
+        return lib().or_smoothed_value_phi(self.h, _p(cost), _p(phi), float(T))
+
+
+def unpruned_count(nvx, nex, nfx, nvy, ney, nfy):
+    """Closed-form size of the unpruned product space (tri-tri 3 FxFy,
+    tri-edge / edge-tri 6 per pair, tri-vertex / vertex-tri 1 per pair)."""
+    return 3 * nfx * nfy + 6 * (nfx * ney + nex * nfy) + nfx * nvy + nvx * nfy

@@ -1,0 +1,276 @@
+"""Pins of the oracle's subproblem minima, min-marginals, Jacobi dual ascent,
+rounding and smoothed dual: exhaustive enumeration, exact LP/ILP optima
+(HiGHS), invariants and finite differences."""
+import itertools
+
+import numpy as np
+import pytest
+
+from helpers import enumerate_ilp, matching_violations, reduced_rows
+from oracle import oracle as O
+from synth import make_pair, tiny_pair
+
+
+def _enum_row(coef, b, lam, T=0.0):
+    """Minimum / soft-minimum and min-marginals of one row by listing all
+    2^n assignments (the definition of the subproblem S_j and of M_i)."""
+    n = len(lam)
+    sols = [np.array(s) for s in itertools.product((0, 1), repeat=n) if np.dot(s, coef) == b]
+    vals = np.array([np.dot(s, lam) for s in sols])
+    S = np.array(sols)
+
+    def smin(v):
+        if len(v) == 0:
+            return np.inf
+        if T == 0:
+            return v.min()
+        m = v.min()
+        return m - T * np.log(np.exp(-(v - m) / T).sum())
+
+    tot = smin(vals)
+    M = np.array([smin(vals[S[:, i] == 1]) - smin(vals[S[:, i] == 0]) for i in range(n)])
+    mu = (np.array([np.exp(-(smin(vals[S[:, i] == 1]) - tot) / T) for i in range(n)])
+          if T > 0 else None)
+    return tot, M, mu
+
+
+@pytest.mark.parametrize("seed", range(12))
+def test_row_dp_matches_enumeration(seed):
+    rng = np.random.default_rng(seed)
+    n = int(rng.integers(2, 13))
+    coef = rng.choice([-1, 1], size=n)
+    P, N = int((coef > 0).sum()), int((coef < 0).sum())
+    b = int(rng.integers(-N, P + 1))
+    lam = rng.normal(size=n) * rng.choice([0.1, 1.0, 10.0])
+    if seed % 3 == 0:
+        lam[rng.integers(n)] = lam[0]    # ties
+    for T in (0.0, 0.3):
+        tot, M, mu = O.row_dp(coef, b, lam, T)
+        rtot, rM, rmu = _enum_row(coef, b, lam, T)
+        finite = np.isfinite(rM)
+        assert np.isclose(tot, rtot, rtol=1e-12, atol=1e-12)
+        assert np.allclose(M[finite], rM[finite], rtol=1e-10, atol=1e-10)
+        if T > 0:
+            assert np.allclose(mu[finite], rmu[finite], rtol=1e-10, atol=1e-12)
+
+
+def test_exactly_one_row_closed_form():
+    rng = np.random.default_rng(5)
+    for n in (2, 3, 17, 300):
+        lam = rng.normal(size=n)
+        tot, M, _ = O.row_dp(np.ones(n, int), 1, lam)
+        assert tot == lam.min()
+        others = np.array([np.min(np.delete(lam, i)) for i in range(n)])
+        assert np.array_equal(M, lam - others)
+        # soft version: softmax marginals
+        T = 0.2
+        tot, M, mu = O.row_dp(np.ones(n, int), 1, lam, T)
+        w = np.exp(-(lam - lam.min()) / T)
+        assert np.allclose(mu, w / w.sum(), rtol=1e-10)
+        assert np.isclose(tot, lam.min() - T * np.log(w.sum()), rtol=1e-12)
+
+
+def test_damped_update_never_lowers_exactly_one_row():
+    rng = np.random.default_rng(7)
+    for _ in range(50):
+        lam = rng.normal(size=int(rng.integers(2, 20)))
+        _, M, _ = O.row_dp(np.ones(len(lam), int), 1, lam)
+        for w in (0.25, 0.5, 1.0):
+            new, _, _ = O.row_dp(np.ones(len(lam), int), 1, lam - w * M)
+            assert new >= lam.min() - 1e-15
+
+
+def _space(p, K):
+    cxy, cyx = O.knn(p.DX, p.DY, K)
+    S = O.Space(p.VX, p.FX, p.VY, p.FY, cxy, cyx)
+    S.costs(p.DX, p.DY)
+    return S
+
+
+def _lp_ilp(S, integral):
+    from scipy.optimize import Bounds, LinearConstraint, linprog, milp
+    from scipy.sparse import csr_matrix
+    rows = reduced_rows(S)
+    n = S.info["n_free"]
+    c = S.get("cost")[S.get("free_var")]
+    r = np.concatenate([[j] * len(vs) for j, (vs, _, _) in enumerate(rows)])
+    A = csr_matrix((np.concatenate([cs for _, cs, _ in rows]).astype(float),
+                    (r, np.concatenate([vs for vs, _, _ in rows]))), shape=(len(rows), n))
+    b = np.array([b for _, _, b in rows], float)
+    if integral:
+        res = milp(c, constraints=LinearConstraint(A, b, b), integrality=np.ones(n),
+                   bounds=Bounds(0, 1))
+    else:
+        res = linprog(c, A_eq=A, b_eq=b, bounds=(0, 1), method="highs")
+    assert res.status == 0
+    return res.fun + S.offset
+
+
+def test_dual_feasibility_and_weak_duality_hard_instance():
+    p = make_pair(1, 0, desc_noise=1.0)
+    S = _space(p, 16)
+    lam, tr = S.dual_solve(60)
+    # sum_j lambda^j_i = c_i (constraint of Eq. (D))
+    rp, rv = S.get("rrow_ptr"), S.get("rent_var")
+    sums = np.bincount(rv, weights=lam, minlength=S.info["n_free"])
+    c = S.get("cost")[S.get("free_var")]
+    assert np.all(np.abs(sums - c) <= 1e-12 * (1 + c))
+    lp = _lp_ilp(S, integral=False)
+    # the dual optimum of (D) equals the LP relaxation: every row polytope is
+    # integral, so no bound may exceed it
+    assert np.all(tr <= lp + 1e-9 * abs(lp))
+    assert S.lower_bound(lam) <= lp + 1e-9 * abs(lp)
+    assert tr[-1] > tr[0]
+    # trace entry t is the bound at the t-th iterate
+    lam5, tr5 = S.dual_solve(5)
+    assert np.isclose(S.lower_bound(lam5), S.dual_solve(6)[1][5], rtol=0, atol=1e-12)
+    assert np.array_equal(tr5, tr[:5])
+
+
+def test_bound_reaches_lp_on_small_config():
+    p = make_pair(1, 0)
+    S = _space(p, 6)
+    lam, tr = S.dual_solve(200)
+    lp = _lp_ilp(S, integral=False)
+    ilp = _lp_ilp(S, integral=True)
+    assert tr.max() <= lp + 1e-9 * abs(lp) and lp <= ilp + 1e-9
+    assert (lp - tr.max()) / lp < 1e-6
+
+
+@pytest.mark.parametrize("kind,K,dn", [("tetra", 2, 0.3), ("icosa", 3, 0.5), ("octa", 3, 0.3)])
+def test_bruteforce_optimum_vs_dual_and_rounding(kind, K, dn):
+    p = tiny_pair(kind, kind, desc_noise=dn)
+    S = _space(p, K)
+    c = S.get("cost")
+    fv = S.get("free_var")
+    opt, nopt, nfeas, _ = enumerate_ilp(reduced_rows(S), S.info["n_free"], c[fv])
+    opt += S.offset
+    assert nfeas >= 1
+    milp_opt = _lp_ilp(S, integral=True)
+    assert np.isclose(opt, milp_opt, rtol=1e-9)
+    lam, tr = S.dual_solve(100)
+    assert np.all(tr <= opt + 1e-9)          # weak duality
+    x, pobj, feas, _ = S.round(lam, seed=3)
+    if feas:
+        assert S.check_primal(x) == 0
+        assert matching_violations(S.get("pv"), S.get("code"), len(p.FX), len(p.FY), x) == 0
+        assert pobj >= opt - 1e-9
+        assert np.isclose(pobj, float(c @ x), rtol=1e-12)
+
+
+@pytest.mark.parametrize("cfg,seed", [(1, 0), (1, 1), (1, 2), (1, 3), (1, 4)])
+def test_rounding_small_config(cfg, seed):
+    p = make_pair(cfg, seed)
+    S = _space(p, p.spec.k)
+    lam, tr = S.dual_solve(p.spec.iters)
+    x, pobj, feas, rounds = S.round(lam, seed=seed)
+    assert feas
+    assert S.check_primal(x) == 0
+    assert matching_violations(S.get("pv"), S.get("code"), len(p.FX), len(p.FY), x) == 0
+    ilp = _lp_ilp(S, integral=True)
+    assert pobj >= ilp - 1e-9
+    gap = (pobj - tr.max()) / pobj
+    assert gap <= 1e-2
+
+
+def test_rounding_perturbs_hard_instance():
+    # a harder instance: rounding needs perturbation rounds, and whatever it
+    # returns as feasible is exactly feasible
+    p = make_pair(1, 0, desc_noise=0.3)
+    S = _space(p, 6)
+    lam, _ = S.dual_solve(3)
+    x, pobj, feas, rounds = S.round(lam, R=30, T_iters=25, seed=11)
+    assert feas and S.check_primal(x) == 0
+
+
+def test_splitmix64_reference_value():
+    # splitmix64 of state 0 (one step of the published generator): 0xE220A8397B1DCDAF
+    # uniform_pm1 maps (splitmix64(splitmix64(seed) ^ (r<<32 | i)) >> 11) to [-1, 1)
+    u = O.uniform_pm1(0, 0, 0)
+    z = 0xE220A8397B1DCDAF  # splitmix64(0)
+    # second step applied to z ^ 0
+    def mix(z):
+        m = (1 << 64) - 1
+        z = (z + 0x9E3779B97F4A7C15) & m
+        z = ((z ^ (z >> 30)) * 0xBF58476D1CE4E5B9) & m
+        z = ((z ^ (z >> 27)) * 0x94D049BB133111EB) & m
+        return z ^ (z >> 31)
+    assert mix(0) == z
+    assert u == (mix(z) >> 11) * 2.0 ** -53 * 2 - 1
+    vals = np.array([O.uniform_pm1(9, r, i) for r in range(3) for i in range(2000)])
+    assert vals.min() >= -1 and vals.max() < 1 and abs(vals.mean()) < 0.05
+
+
+# ---------------------------------------------------------------- smoothed dual
+def test_smoothed_bound_brackets_hard_bound():
+    p = make_pair(1, 0, desc_noise=0.3)
+    S = _space(p, 6)
+    lam, _ = S.dual_solve(20)
+    T = 0.1
+    hard = S.lower_bound(lam)
+    soft = S.lower_bound(lam, T)
+    rows = reduced_rows(S)
+    logS = 0.0
+    for vs, cs, b in rows:
+        # |S_j| by counting assignments with the row's +1/-1 split
+        P, N = int((cs > 0).sum()), int((cs < 0).sum())
+        from math import comb
+        logS += np.log(sum(comb(P, k) * comb(N, k - b) for k in range(max(0, b), P + 1)
+                           if 0 <= k - b <= N))
+    assert hard - T * logS - 1e-9 <= soft <= hard + 1e-12
+
+
+@pytest.mark.parametrize("T", [0.1, 0.5])
+def test_smoothed_gradient_finite_differences(T):
+    p = make_pair(1, 1, desc_noise=0.3)
+    S = _space(p, 6)
+    c0 = S.get("cost")
+    lam, _ = S.dual_solve(30, T=T)
+    lam0 = S.init_lambda()
+    phi = lam - lam0
+    v, gc, gX, gY = S.smoothed_grad(lam, T, p.DX, p.DY)
+    assert np.isclose(v, S.smoothed_value_phi(c0, phi, T), rtol=1e-12)
+    rng = np.random.default_rng(0)
+    h = 1e-3
+    errs = []
+    for _ in range(20):
+        side = rng.integers(2)
+        D = (p.DX if side == 0 else p.DY).astype(np.float64)
+        i, k = rng.integers(D.shape[0]), rng.integers(D.shape[1])
+        g = (gX if side == 0 else gY)[i, k]
+        vals = []
+        for s in (+1, -1):
+            DX = p.DX.astype(np.float64).copy()
+            DY = p.DY.astype(np.float64).copy()
+            (DX if side == 0 else DY)[i, k] += s * h
+            # float32 descriptors would round h away: evaluate costs from the
+            # FP64 perturbed descriptors through the oracle's cost routine
+            c = _costs64(S, p, DX, DY)
+            vals.append(S.smoothed_value_phi(c, phi, T))
+        fd = (vals[0] - vals[1]) / (2 * h)
+        errs.append(abs(fd - g) / max(1e-3, abs(g)))
+    assert max(errs) <= 1e-4
+
+
+def _costs64(S, p, DX, DY):
+    """Eq. (cost) on FP64 descriptors, using the oracle's mixed areas and the
+    element list (the oracle's cost routine takes float32 descriptors)."""
+    AX = O.mixed_areas(p.VX, p.FX)
+    AY = O.mixed_areas(p.VY, p.FY)
+    pv = S.get("pv")
+    nvy = len(p.VY)
+    m, n = pv // nvy, pv % nvy
+    d = np.sqrt(((DX[m] - DY[n]) ** 2).sum(-1))
+    return ((AX[m] + AY[n]) * d).sum(1)
+
+
+def test_smoothed_gradient_single_row_is_softmax():
+    # dL_T / dlambda for one exactly-one row is softmax(-lambda / T)
+    lam = np.array([0.3, -0.2, 0.5, 0.1])
+    T = 0.25
+    tot, _, mu = O.row_dp(np.ones(4, int), 1, lam, T)
+    h = 1e-6
+    fd = np.array([(O.row_dp(np.ones(4, int), 1, lam + h * e, T)[0]
+                    - O.row_dp(np.ones(4, int), 1, lam - h * e, T)[0]) / (2 * h) for e in np.eye(4)])
+    w = np.exp(-lam / T)
+    assert np.allclose(mu, w / w.sum(), rtol=1e-12) and np.allclose(fd, mu, rtol=1e-7)
