@@ -160,12 +160,12 @@ dm_status dm_init_lambda(dm_ctx* ctx, int32_t msg_prec, void* lambda);
  * sum_j lambda^j_i = c_i on entry (e.g. from dm_init_lambda).
  *  msg_prec DM_PREC_FP32 (lambda float32) or DM_PREC_FP64 (float64).
  *  lb_trace [device] double [iters] out, or NULL.  Enqueue only. */
-dm_status dm_dual_solve(dm_ctx* ctx, int32_t iters, float omega, float temperature,
+dm_status dm_dual_solve(dm_ctx* ctx, int32_t iters, double omega, double temperature,
                         int32_t msg_prec, void* lambda, double* lb_trace);
 
 /* Dual objective (A8; Eq. (D)) at lambda: offset + sum over rows of the row
  * minimum (soft-min for temperature > 0).  Synchronises; *lb [host]. */
-dm_status dm_lower_bound(dm_ctx* ctx, const void* lambda, float temperature, int32_t msg_prec,
+dm_status dm_lower_bound(dm_ctx* ctx, const void* lambda, double temperature, int32_t msg_prec,
                          double* lb);
 
 /* Primal rounding (A9, A10).  On a copy of (c, lambda): sweep all rows; when
@@ -185,7 +185,7 @@ typedef struct {
   double delta0;
   double gamma;
   uint64_t seed;
-  float omega;
+  double omega;
   int32_t msg_prec;
 } dm_round_params;
 dm_status dm_round_primal(dm_ctx* ctx, const dm_round_params* params, const void* lambda,
@@ -203,7 +203,7 @@ dm_status dm_check_primal(dm_ctx* ctx, const uint8_t* x, int64_t* violations);
  * constant.  grad_out scales the result.  gcost [device] float32
  * [n_prod_tri] out or NULL; gFX [device] float32 [nvx*D], gFY [nvy*D] out;
  * *value [host] out (L_T) or NULL.  Synchronises when value is not NULL. */
-dm_status dm_smoothed_backward(dm_ctx* ctx, const void* lambda, float temperature,
+dm_status dm_smoothed_backward(dm_ctx* ctx, const void* lambda, double temperature,
                                int32_t msg_prec, double grad_out, const float* FX,
                                const float* FY, int32_t D, float* gcost, float* gFX, float* gFY,
                                double* value);
@@ -211,6 +211,14 @@ dm_status dm_smoothed_backward(dm_ctx* ctx, const void* lambda, float temperatur
 /* Mixed vertex areas (Meyer et al. 2003) of a device mesh, for checks.
  *  out [device] double [nv]. */
 dm_status dm_mixed_areas(dm_ctx* ctx, const dm_mesh* M, double* out);
+
+/* Measurement hook: while enabled, every dual-sweep kernel launch made by
+ * dm_dual_solve, dm_lower_bound and dm_round_primal is bracketed by a pair of
+ * HIP events on the context's stream.  dm_timing_read synchronises the stream
+ * and returns the number of timed launches and the sum of their durations in
+ * milliseconds [host], then clears the record.  Off by default. */
+dm_status dm_timing_enable(dm_ctx* ctx, int32_t enable);
+dm_status dm_timing_read(dm_ctx* ctx, int64_t* launches, double* total_ms);
 
 /* Version string of the library build. */
 const char* dm_version(void);

@@ -1,0 +1,295 @@
+"""Python binding of libdiscomatch (gfx950): argument marshalling only.
+
+Every step of the solver runs in the HIP library; this module passes device
+pointers of torch tensors and the current torch stream through the C ABI of
+include/discomatch.h and raises on any error.  The library must have been
+built (paper_2310_08230_amd/build.py); there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libdiscomatch.so")
+
+DM_OK = 0
+PREC = {"fp64": 0, "fp32": 1, "bf16": 2}
+ERRORS = {-1: "invalid argument", -2: "mesh", -3: "genus", -4: "infeasible", -5: "non-finite",
+          -6: "workspace", -7: "hip", -8: "state"}
+ARRAYS = ["pv", "code", "state", "row_key", "row_ptr", "ent_var", "ent_coef", "row_b", "free_var",
+          "rrow_orig", "rrow_ptr", "rent_var", "rent_coef", "rrow_b", "edges_x", "edges_y", "cand"]
+
+_lib = None
+
+
+class DMError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"discomatch error {code} ({ERRORS.get(code, '?')}): {msg}")
+        self.code = code
+
+
+class dm_mesh(C.Structure):
+    _fields_ = [("nv", C.c_int32), ("nf", C.c_int32), ("verts", C.c_void_p), ("faces", C.c_void_p)]
+
+
+class dm_space_info(C.Structure):
+    _fields_ = [(n, C.c_int64) for n in ("n_prod_tri", "n_rows_full", "nnz_full", "n_closed_full",
+                                         "n_free", "n_fixed1", "n_rows", "nnz", "n_short_rows",
+                                         "n_edges_x", "n_edges_y", "n_cand")] + \
+               [("presolve_rounds", C.c_int32), ("max_short_row", C.c_int32)]
+
+
+class dm_round_params(C.Structure):
+    _fields_ = [("rounds", C.c_int32), ("iters_per_round", C.c_int32), ("delta0", C.c_double),
+                ("gamma", C.c_double), ("seed", C.c_uint64), ("omega", C.c_double),
+                ("msg_prec", C.c_int32)]
+
+
+def lib():
+    """Load libdiscomatch.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} not built; run paper_2310_08230_amd/build.py")
+        L = C.CDLL(LIB_PATH)
+        P, I32, I64, F, D = C.c_void_p, C.c_int32, C.c_int64, C.c_float, C.c_double
+        sig = {
+            "dm_create": [I32, P, P],
+            "dm_destroy": [P],
+            "dm_set_stream": [P, P],
+            "dm_knn_candidates": [P, P, I32, P, I32, I32, I32, I32, P, P],
+            "dm_build_product_space": [P, P, P, P, P, I32, P],
+            "dm_get_space": [P, I32, P],
+            "dm_build_costs": [P, P, P, I32, I32, P],
+            "dm_init_lambda": [P, I32, P],
+            "dm_dual_solve": [P, I32, D, D, I32, P, P],
+            "dm_lower_bound": [P, P, D, I32, P],
+            "dm_round_primal": [P, P, P, P, P, P, P],
+            "dm_check_primal": [P, P, P],
+            "dm_smoothed_backward": [P, P, D, I32, D, P, P, I32, P, P, P, P],
+            "dm_mixed_areas": [P, P, P],
+            "dm_timing_enable": [P, I32],
+            "dm_timing_read": [P, P, P],
+        }
+        for name, args in sig.items():
+            fn = getattr(L, name)
+            fn.argtypes = args
+            fn.restype = I32
+        L.dm_last_error.argtypes = [P]
+        L.dm_last_error.restype = C.c_char_p
+        L.dm_version.argtypes = []
+        L.dm_version.restype = C.c_char_p
+        _lib = L
+    return _lib
+
+
+def _ptr(t):
+    return C.c_void_p(t.data_ptr()) if t is not None else None
+
+
+def _dev(t, dtype, device):
+    if not isinstance(t, torch.Tensor):
+        t = torch.as_tensor(t)
+    return t.to(device=device, dtype=dtype).contiguous()
+
+
+class Context:
+    """One library context on one GPU; work goes on the current torch stream."""
+
+    def __init__(self, device: int = 0):
+        if not torch.cuda.is_available():
+            raise RuntimeError("discomatch needs a ROCm GPU")
+        self.device = torch.device("cuda", device)
+        h = C.c_void_p()
+        with torch.cuda.device(self.device):
+            st = lib().dm_create(device, C.c_void_p(torch.cuda.current_stream().cuda_stream), C.byref(h))
+        if st != DM_OK:
+            raise DMError(st, "dm_create failed")
+        self.h = h
+        self.info = None
+        self._keep = []
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().dm_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _call(self, name, *args):
+        L = lib()
+        L.dm_set_stream(self.h, C.c_void_p(torch.cuda.current_stream(self.device).cuda_stream))
+        st = getattr(L, name)(self.h, *args)
+        if st != DM_OK:
+            raise DMError(st, L.dm_last_error(self.h).decode())
+
+    # -- A2 -------------------------------------------------------------
+    def knn_candidates(self, DX, DY, K, prec="fp32"):
+        DX = _dev(DX, torch.float32, self.device)
+        DY = _dev(DY, torch.float32, self.device)
+        cxy = torch.empty((DX.shape[0], K), dtype=torch.int32, device=self.device)
+        cyx = torch.empty((DY.shape[0], K), dtype=torch.int32, device=self.device)
+        self._call("dm_knn_candidates", _ptr(DX), DX.shape[0], _ptr(DY), DY.shape[0], DX.shape[1], K,
+                   PREC[prec], _ptr(cxy), _ptr(cyx))
+        return cxy, cyx
+
+    # -- A1, A3 ---------------------------------------------------------
+    def build_product_space(self, VX, FX, VY, FY, cand_xy, cand_yx):
+        VX = _dev(VX, torch.float32, self.device)
+        VY = _dev(VY, torch.float32, self.device)
+        FX = _dev(FX, torch.int32, self.device)
+        FY = _dev(FY, torch.int32, self.device)
+        cxy = _dev(cand_xy, torch.int32, self.device)
+        cyx = _dev(cand_yx, torch.int32, self.device)
+        mx = dm_mesh(VX.shape[0], FX.shape[0], VX.data_ptr(), FX.data_ptr())
+        my = dm_mesh(VY.shape[0], FY.shape[0], VY.data_ptr(), FY.data_ptr())
+        info = dm_space_info()
+        self._call("dm_build_product_space", C.byref(mx), C.byref(my), _ptr(cxy), _ptr(cyx),
+                   cxy.shape[1], C.byref(info))
+        self.info = {n: getattr(info, n) for n, _ in dm_space_info._fields_}
+        self.nvx, self.nvy = VX.shape[0], VY.shape[0]
+        return self.info
+
+    def get_space(self, name):
+        i = self.info
+        shapes = {
+            "pv": (torch.int32, (i["n_prod_tri"], 3)), "code": (torch.int32, (i["n_prod_tri"], 4)),
+            "state": (torch.int8, (i["n_prod_tri"],)), "row_key": (torch.int64, (i["n_rows_full"],)),
+            "row_ptr": (torch.int64, (i["n_rows_full"] + 1,)), "ent_var": (torch.int64, (i["nnz_full"],)),
+            "ent_coef": (torch.int32, (i["nnz_full"],)), "row_b": (torch.int32, (i["n_rows_full"],)),
+            "free_var": (torch.int64, (i["n_free"],)), "rrow_orig": (torch.int64, (i["n_rows"],)),
+            "rrow_ptr": (torch.int64, (i["n_rows"] + 1,)), "rent_var": (torch.int64, (i["nnz"],)),
+            "rent_coef": (torch.int32, (i["nnz"],)), "rrow_b": (torch.int32, (i["n_rows"],)),
+            "edges_x": (torch.int32, (i["n_edges_x"], 2)), "edges_y": (torch.int32, (i["n_edges_y"], 2)),
+            "cand": (torch.uint8, (self.nvx, self.nvy)),
+        }
+        dt, shp = shapes[name]
+        out = torch.empty(shp, dtype=dt, device=self.device)
+        self._call("dm_get_space", ARRAYS.index(name), _ptr(out))
+        return out
+
+    # -- A4 -------------------------------------------------------------
+    def build_costs(self, DX, DY, prec="fp32"):
+        DX = _dev(DX, torch.float32, self.device)
+        DY = _dev(DY, torch.float32, self.device)
+        cost = torch.empty(self.info["n_prod_tri"], dtype=torch.float32, device=self.device)
+        self._call("dm_build_costs", _ptr(DX), _ptr(DY), DX.shape[1], PREC[prec], _ptr(cost))
+        self._desc = (DX, DY)
+        return cost
+
+    # -- A5-A8 ----------------------------------------------------------
+    def init_lambda(self, msg_prec="fp32"):
+        dt = torch.float32 if msg_prec == "fp32" else torch.float64
+        lam = torch.empty(self.info["nnz"], dtype=dt, device=self.device)
+        self._call("dm_init_lambda", PREC[msg_prec], _ptr(lam))
+        return lam
+
+    def dual_solve(self, lam, iters, omega=0.5, temperature=0.0, msg_prec=None, trace=True):
+        msg_prec = msg_prec or ("fp32" if lam.dtype == torch.float32 else "fp64")
+        tr = torch.empty(max(iters, 1), dtype=torch.float64, device=self.device) if trace else None
+        self._call("dm_dual_solve", int(iters), float(omega), float(temperature), PREC[msg_prec],
+                   _ptr(lam), _ptr(tr) if trace else None)
+        return lam, (tr[:iters] if trace else None)
+
+    def lower_bound(self, lam, temperature=0.0):
+        msg_prec = "fp32" if lam.dtype == torch.float32 else "fp64"
+        out = C.c_double(0)
+        self._call("dm_lower_bound", _ptr(lam), float(temperature), PREC[msg_prec], C.byref(out))
+        return out.value
+
+    # -- A9, A10 --------------------------------------------------------
+    def round_primal(self, lam, rounds=30, iters_per_round=25, delta0=0.0, gamma=1.5, seed=0, omega=0.5):
+        msg_prec = "fp32" if lam.dtype == torch.float32 else "fp64"
+        P = dm_round_params(rounds, iters_per_round, delta0, gamma, seed, omega, PREC[msg_prec])
+        x = torch.empty(self.info["n_prod_tri"], dtype=torch.uint8, device=self.device)
+        p, feas, r = C.c_double(0), C.c_int32(0), C.c_int32(0)
+        self._call("dm_round_primal", C.byref(P), _ptr(lam), _ptr(x), C.byref(p), C.byref(feas), C.byref(r))
+        return x, p.value, bool(feas.value), r.value
+
+    def check_primal(self, x):
+        x = _dev(x, torch.uint8, self.device)
+        v = C.c_int64(0)
+        self._call("dm_check_primal", _ptr(x), C.byref(v))
+        return v.value
+
+    # -- A11 ------------------------------------------------------------
+    def smoothed_backward(self, lam, temperature, DX, DY, grad_out=1.0):
+        msg_prec = "fp32" if lam.dtype == torch.float32 else "fp64"
+        DX = _dev(DX, torch.float32, self.device)
+        DY = _dev(DY, torch.float32, self.device)
+        gc = torch.empty(self.info["n_prod_tri"], dtype=torch.float32, device=self.device)
+        gX = torch.empty_like(DX)
+        gY = torch.empty_like(DY)
+        v = C.c_double(0)
+        self._call("dm_smoothed_backward", _ptr(lam), float(temperature), PREC[msg_prec], float(grad_out),
+                   _ptr(DX), _ptr(DY), DX.shape[1], _ptr(gc), _ptr(gX), _ptr(gY), C.byref(v))
+        return gc, gX, gY, v.value
+
+    def timing(self, enable: bool):
+        self._call("dm_timing_enable", int(enable))
+
+    def timing_read(self):
+        n, ms = C.c_int64(0), C.c_double(0)
+        self._call("dm_timing_read", C.byref(n), C.byref(ms))
+        return n.value, ms.value
+
+    def mixed_areas(self, V, F):
+        V = _dev(V, torch.float32, self.device)
+        F = _dev(F, torch.int32, self.device)
+        m = dm_mesh(V.shape[0], F.shape[0], V.data_ptr(), F.data_ptr())
+        out = torch.empty(V.shape[0], dtype=torch.float64, device=self.device)
+        self._call("dm_mixed_areas", C.byref(m), _ptr(out))
+        return out
+
+
+# Module-level names matching the C ABI -------------------------------------
+def build_product_space(ctx: Context, *a, **k):
+    return ctx.build_product_space(*a, **k)
+
+
+def build_costs(ctx: Context, *a, **k):
+    return ctx.build_costs(*a, **k)
+
+
+def dual_solve(ctx: Context, *a, **k):
+    return ctx.dual_solve(*a, **k)
+
+
+def round_primal(ctx: Context, *a, **k):
+    return ctx.round_primal(*a, **k)
+
+
+def lower_bound(ctx: Context, *a, **k):
+    return ctx.lower_bound(*a, **k)
+
+
+class SmoothedBound(torch.autograd.Function):
+    """L_T of the smoothed dual as a function of the descriptors.
+
+    forward(DX, DY, ctx_obj, iters, T, omega) builds the costs from DX, DY
+    (FP32), runs ``iters`` smoothed Jacobi iterations from c/|J_i| and returns
+    L_T as a 0-d float64 tensor; backward calls dm_smoothed_backward with the
+    final multipliers held as c/|J_i| + phi, phi fixed."""
+
+    @staticmethod
+    def forward(fctx, DX, DY, dm: Context, iters: int, T: float, omega: float = 0.5, prec: str = "fp32"):
+        dm.build_costs(DX.detach(), DY.detach(), prec)
+        lam = dm.init_lambda("fp32")
+        dm.dual_solve(lam, iters, omega, T, trace=False)
+        val = dm.lower_bound(lam, T)
+        fctx.dm, fctx.T = dm, T
+        fctx.save_for_backward(DX, DY, lam)
+        return torch.tensor(val, dtype=torch.float64, device=DX.device)
+
+    @staticmethod
+    def backward(fctx, g):
+        DX, DY, lam = fctx.saved_tensors
+        _, gX, gY, _ = fctx.dm.smoothed_backward(lam, fctx.T, DX.detach(), DY.detach(), float(g))
+        return gX.to(DX.dtype), gY.to(DY.dtype), None, None, None, None, None

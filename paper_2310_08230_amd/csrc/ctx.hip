@@ -1,0 +1,186 @@
+// Context lifetime, errors, library primitives (sort, scan) and exports.
+#include <cstring>
+
+#include <rocprim/rocprim.hpp>
+
+#include <cstdarg>
+#include <vector>
+
+#include "dm_internal.h"
+
+dm_status dm_fail(dm_ctx* ctx, dm_status code, const char* fmt, ...) {
+  if (ctx) {
+    char buf[1024];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    ctx->err = buf;
+  }
+  return code;
+}
+
+extern "C" dm_status dm_create(int32_t device, void* hip_stream, dm_ctx** out) {
+  if (!out) return DM_ERR_INVALID_ARG;
+  *out = nullptr;
+  int n = 0;
+  if (hipGetDeviceCount(&n) != hipSuccess || device < 0 || device >= n) return DM_ERR_INVALID_ARG;
+  if (hipSetDevice(device) != hipSuccess) return DM_ERR_HIP;
+  dm_ctx* c = new dm_ctx();
+  c->device = device;
+  c->stream = static_cast<hipStream_t>(hip_stream);
+  *out = c;
+  return DM_OK;
+}
+
+extern "C" dm_status dm_destroy(dm_ctx* ctx) {
+  if (!ctx) return DM_ERR_INVALID_ARG;
+  (void)hipSetDevice(ctx->device);
+  (void)hipStreamSynchronize(ctx->stream);
+  delete ctx;
+  return DM_OK;
+}
+
+extern "C" const char* dm_last_error(const dm_ctx* ctx) { return ctx ? ctx->err.c_str() : ""; }
+
+extern "C" dm_status dm_set_stream(dm_ctx* ctx, void* hip_stream) {
+  if (!ctx) return DM_ERR_INVALID_ARG;
+  ctx->stream = static_cast<hipStream_t>(hip_stream);
+  return DM_OK;
+}
+
+extern "C" const char* dm_version(void) { return "discomatch-gfx950 0.1"; }
+
+// ---------------------------------------------------------------------------
+// rocPRIM wrappers (stable radix sort of key/value pairs, exclusive scans)
+// ---------------------------------------------------------------------------
+template <typename K>
+static dm_status sort_pairs_impl(dm_ctx* ctx, K* keys, int32_t* vals, size_t n, int end_bit) {
+  if (n <= 1) return DM_OK;
+  DArr<K> k2;
+  DArr<int32_t> v2;
+  DM_ALLOC(ctx, k2, n);
+  DM_ALLOC(ctx, v2, n);
+  size_t temp = 0;
+  DM_HIP(ctx, rocprim::radix_sort_pairs(nullptr, temp, keys, k2.p, vals, v2.p, n, 0u,
+                                        unsigned(end_bit), ctx->stream));
+  DArr<unsigned char> tmp;
+  DM_ALLOC(ctx, tmp, temp + 16);
+  DM_HIP(ctx, rocprim::radix_sort_pairs(tmp.p, temp, keys, k2.p, vals, v2.p, n, 0u,
+                                        unsigned(end_bit), ctx->stream));
+  DM_HIP(ctx, hipMemcpyAsync(keys, k2.p, n * sizeof(K), hipMemcpyDeviceToDevice, ctx->stream));
+  DM_HIP(ctx, hipMemcpyAsync(vals, v2.p, n * sizeof(int32_t), hipMemcpyDeviceToDevice, ctx->stream));
+  DM_HIP(ctx, hipStreamSynchronize(ctx->stream));
+  return DM_OK;
+}
+
+dm_status sort_pairs_u64(dm_ctx* ctx, uint64_t* keys, int32_t* vals, size_t n, int end_bit) {
+  return sort_pairs_impl<uint64_t>(ctx, keys, vals, n, end_bit);
+}
+
+dm_status sort_pairs_u32(dm_ctx* ctx, uint32_t* keys, int32_t* vals, size_t n, int end_bit) {
+  return sort_pairs_impl<uint32_t>(ctx, keys, vals, n, end_bit);
+}
+
+__global__ void k_scan_tail(const int32_t* in_last, int32_t* out, size_t n, int is_u8,
+                            const uint8_t* u8_last) {
+  int32_t last = is_u8 ? int32_t(*u8_last) : *in_last;
+  out[n] = out[n - 1] + last;
+}
+
+struct U8ToI32 {
+  __host__ __device__ int32_t operator()(uint8_t v) const { return int32_t(v); }
+};
+
+dm_status scan_i32(dm_ctx* ctx, const int32_t* in, int32_t* out, size_t n) {
+  if (n == 0) {
+    DM_HIP(ctx, hipMemsetAsync(out, 0, sizeof(int32_t), ctx->stream));
+    return DM_OK;
+  }
+  size_t temp = 0;
+  DM_HIP(ctx, rocprim::exclusive_scan(nullptr, temp, in, out, int32_t(0), n,
+                                      rocprim::plus<int32_t>(), ctx->stream));
+  DArr<unsigned char> tmp;
+  DM_ALLOC(ctx, tmp, temp + 16);
+  DM_HIP(ctx, rocprim::exclusive_scan(tmp.p, temp, in, out, int32_t(0), n,
+                                      rocprim::plus<int32_t>(), ctx->stream));
+  k_scan_tail<<<1, 1, 0, ctx->stream>>>(in + n - 1, out, n, 0, nullptr);
+  DM_LAUNCH_CHECK(ctx);
+  DM_HIP(ctx, hipStreamSynchronize(ctx->stream));
+  return DM_OK;
+}
+
+dm_status scan_u8(dm_ctx* ctx, const uint8_t* in, int32_t* out, size_t n) {
+  if (n == 0) {
+    DM_HIP(ctx, hipMemsetAsync(out, 0, sizeof(int32_t), ctx->stream));
+    return DM_OK;
+  }
+  auto it = rocprim::make_transform_iterator(in, U8ToI32());
+  size_t temp = 0;
+  DM_HIP(ctx, rocprim::exclusive_scan(nullptr, temp, it, out, int32_t(0), n,
+                                      rocprim::plus<int32_t>(), ctx->stream));
+  DArr<unsigned char> tmp;
+  DM_ALLOC(ctx, tmp, temp + 16);
+  DM_HIP(ctx, rocprim::exclusive_scan(tmp.p, temp, it, out, int32_t(0), n,
+                                      rocprim::plus<int32_t>(), ctx->stream));
+  k_scan_tail<<<1, 1, 0, ctx->stream>>>(nullptr, out, n, 1, in + n - 1);
+  DM_LAUNCH_CHECK(ctx);
+  DM_HIP(ctx, hipStreamSynchronize(ctx->stream));
+  return DM_OK;
+}
+
+dm_status read_i32(dm_ctx* ctx, const int32_t* dev, int32_t* host) {
+  DM_HIP(ctx, hipMemcpyAsync(host, dev, sizeof(int32_t), hipMemcpyDeviceToHost, ctx->stream));
+  DM_HIP(ctx, hipStreamSynchronize(ctx->stream));
+  return DM_OK;
+}
+
+// ---------------------------------------------------------------------------
+// exports
+// ---------------------------------------------------------------------------
+template <typename S, typename D>
+__global__ void k_widen(const S* in, D* out, int64_t n) {
+  int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i < n) out[i] = D(in[i]);
+}
+
+__global__ void k_export_code(const int32_t* code, int32_t* out, int64_t n) {
+  int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i < n) out[i] = code[i];
+}
+
+template <typename S, typename D>
+static dm_status widen(dm_ctx* ctx, const S* in, void* out, int64_t n) {
+  if (n <= 0) return DM_OK;
+  k_widen<S, D><<<grid_for(n, 256), 256, 0, ctx->stream>>>(in, static_cast<D*>(out), n);
+  DM_LAUNCH_CHECK(ctx);
+  return DM_OK;
+}
+
+extern "C" dm_status dm_get_space(dm_ctx* ctx, int32_t which, void* dst) {
+  if (!ctx) return DM_ERR_INVALID_ARG;
+  if (!ctx->has_space) return dm_fail(ctx, DM_ERR_STATE, "dm_get_space: no product space built");
+  if (!dst) return dm_fail(ctx, DM_ERR_INVALID_ARG, "dm_get_space: dst is NULL");
+  DM_HIP(ctx, hipSetDevice(ctx->device));
+  switch (which) {
+    case DM_ARR_PV: return widen<int32_t, int32_t>(ctx, ctx->pv.p, dst, ctx->nP * 3);
+    case DM_ARR_CODE: return widen<int32_t, int32_t>(ctx, ctx->code.p, dst, ctx->nP * 4);
+    case DM_ARR_STATE: return widen<int8_t, int8_t>(ctx, ctx->state.p, dst, ctx->nP);
+    case DM_ARR_ROW_KEY: return widen<int64_t, int64_t>(ctx, ctx->row_key.p, dst, ctx->n_rows_full);
+    case DM_ARR_ROW_PTR: return widen<int32_t, int64_t>(ctx, ctx->row_ptr.p, dst, ctx->n_rows_full + 1);
+    case DM_ARR_ENT_VAR: return widen<int32_t, int64_t>(ctx, ctx->ent_var.p, dst, ctx->nnz_full);
+    case DM_ARR_ENT_COEF: return widen<int8_t, int32_t>(ctx, ctx->ent_coef.p, dst, ctx->nnz_full);
+    case DM_ARR_ROW_B: return widen<int32_t, int32_t>(ctx, ctx->row_b.p, dst, ctx->n_rows_full);
+    case DM_ARR_FREE_VAR: return widen<int32_t, int64_t>(ctx, ctx->free_var.p, dst, ctx->n_free);
+    case DM_ARR_RROW_ORIG: return widen<int32_t, int64_t>(ctx, ctx->rrow_orig.p, dst, ctx->n_rows);
+    case DM_ARR_RROW_PTR: return widen<int32_t, int64_t>(ctx, ctx->rrow_ptr.p, dst, ctx->n_rows + 1);
+    case DM_ARR_RENT_VAR: return widen<int32_t, int64_t>(ctx, ctx->rent_var.p, dst, ctx->nnz);
+    case DM_ARR_RENT_COEF: return widen<int8_t, int32_t>(ctx, ctx->rent_coef.p, dst, ctx->nnz);
+    case DM_ARR_RROW_B: return widen<int32_t, int32_t>(ctx, ctx->rrow_b.p, dst, ctx->n_rows);
+    case DM_ARR_EDGES_X: return widen<int32_t, int32_t>(ctx, ctx->X.edges.p, dst, int64_t(ctx->X.ne) * 2);
+    case DM_ARR_EDGES_Y: return widen<int32_t, int32_t>(ctx, ctx->Y.edges.p, dst, int64_t(ctx->Y.ne) * 2);
+    case DM_ARR_CAND:
+      return widen<uint8_t, uint8_t>(ctx, ctx->cand.p, dst, int64_t(ctx->X.nv) * ctx->Y.nv);
+  }
+  return dm_fail(ctx, DM_ERR_INVALID_ARG, "dm_get_space: unknown array %d", which);
+}

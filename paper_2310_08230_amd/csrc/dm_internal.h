@@ -1,0 +1,194 @@
+// Internal declarations of the DiscoMatch gfx950 library: the context, device
+// buffers and the entry points of each translation unit.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstdio>
+#include <string>
+#include <vector>
+
+#include "../../include/discomatch.h"
+
+// ---------------------------------------------------------------------------
+// error plumbing
+// ---------------------------------------------------------------------------
+dm_status dm_fail(dm_ctx* ctx, dm_status code, const char* fmt, ...);
+
+#define DM_HIP(ctx, call)                                                              \
+  do {                                                                                 \
+    hipError_t e_ = (call);                                                            \
+    if (e_ != hipSuccess)                                                              \
+      return dm_fail((ctx), DM_ERR_HIP, "%s:%d %s: %s", __FILE__, __LINE__, #call,     \
+                     hipGetErrorString(e_));                                           \
+  } while (0)
+
+#define DM_TRY(expr)                  \
+  do {                                \
+    dm_status s_ = (expr);            \
+    if (s_ != DM_OK) return s_;       \
+  } while (0)
+
+#define DM_LAUNCH_CHECK(ctx) DM_HIP(ctx, hipGetLastError())
+
+// ---------------------------------------------------------------------------
+// owned device array
+// ---------------------------------------------------------------------------
+template <typename T>
+struct DArr {
+  T* p = nullptr;
+  size_t n = 0;
+  DArr() = default;
+  DArr(const DArr&) = delete;
+  DArr& operator=(const DArr&) = delete;
+  ~DArr() { release(); }
+  void release() {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    n = 0;
+  }
+  hipError_t resize(size_t count) {
+    if (count == n && p) return hipSuccess;
+    release();
+    n = count;
+    if (count == 0) return hipSuccess;
+    return hipMalloc(reinterpret_cast<void**>(&p), count * sizeof(T));
+  }
+};
+
+#define DM_ALLOC(ctx, arr, count) DM_HIP(ctx, (arr).resize(count))
+
+struct MeshDev {
+  int32_t nv = 0, nf = 0, ne = 0;
+  DArr<float> verts;       // nv*3
+  DArr<int32_t> faces;     // nf*3
+  DArr<int32_t> edges;     // ne*2 sorted (min, max)
+  DArr<int32_t> face_edge; // nf*3: id of edge (f[k], f[k+1])
+  DArr<uint64_t> dkey;     // 3*nf sorted directed-edge keys a*nv+b
+  DArr<int32_t> dval;      // 3*nf corner id 3f+k of each sorted key
+  DArr<double> area;       // nv mixed areas (filled by costs)
+};
+
+// Reduced-problem entry word: [31] coefficient is -1, [30] variable has five
+// rows, [29:27] slot of the entry in its variable's record, [26:0] variable.
+constexpr uint32_t W_NEG = 1u << 31;
+constexpr uint32_t W_DEG5 = 1u << 30;
+constexpr int W_SLOT_SHIFT = 27;
+constexpr uint32_t W_VAR_MASK = (1u << 27) - 1u;
+constexpr int REC = 8;          // record stride: 5 multiplier slots, cost, 2 spare
+constexpr int REC_COST = 5;
+constexpr int CHUNK_SPAN = 192; // short rows starting in one span form a chunk
+constexpr int MAX_SHORT_ROW = 64;
+constexpr int SOFT_MAX_ROW = 24;
+
+struct dm_ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  std::string err;
+
+  MeshDev X, Y;
+  int32_t K = 0;
+  bool has_space = false;
+
+  // candidates: byte map and compact pair list (sorted by product vertex id)
+  DArr<uint8_t> cand;      // nvx*nvy
+  DArr<int32_t> cidx;      // nvx*nvy -> pair index or -1
+  DArr<int32_t> cpair;     // nC -> m*nvy+n
+  DArr<int32_t> cpair_t;   // pairs sorted by (n, m): pair indices
+  DArr<int32_t> cand_xstart; // nvx+1: first pair of each X vertex
+  DArr<int32_t> cand_ystart; // nvy+1: first position in cpair_t of each Y vertex
+  int64_t nC = 0;
+
+  // elements (product triangles) in canonical order
+  int64_t nP = 0;
+  DArr<int32_t> pv;        // nP*3
+  DArr<int32_t> code;      // nP*4 (x class, x id, y class*8+pattern, y id)
+
+  // full incidence A (rows: closedness | X projection | Y projection)
+  int64_t n_rows_full = 0, n_closed_full = 0, nnz_full = 0;
+  DArr<int64_t> row_key;
+  DArr<int32_t> row_ptr;   // n_rows_full+1
+  DArr<int32_t> ent_var;
+  DArr<int8_t> ent_coef;
+  DArr<uint8_t> ent_slot;
+  DArr<int32_t> row_b;
+  DArr<int8_t> state;      // -1 free, 0/1 fixed
+  int32_t presolve_rounds = 0;
+
+  // reduced problem over free variables
+  int64_t n_free = 0, n_fixed1 = 0, n_rows = 0, nnz = 0, n_short = 0, nnz_short = 0;
+  int32_t max_short = 0;
+  DArr<int32_t> free_var;  // n_free -> element
+  DArr<int32_t> var_red;   // nP -> reduced var or -1
+  DArr<int32_t> rrow_orig;
+  DArr<int32_t> rrow_ptr;  // n_rows+1
+  DArr<int32_t> rrow_b;
+  DArr<int32_t> rent_var;
+  DArr<int8_t> rent_coef;
+  DArr<uint32_t> rent_word;
+  DArr<uint8_t> var_deg;   // n_free
+  int32_t n_chunks = 0;
+  DArr<int32_t> chunk_row; // n_chunks+1: first short row of each chunk
+
+  // costs
+  bool has_cost = false;
+  int32_t cost_prec = DM_PREC_FP32;
+  double offset = 0.0;
+  DArr<double> cost64;     // nP (FP64 copy of the element costs)
+  DArr<float> cost32;      // nP
+  DArr<float> pair_d;      // nC descriptor distance used by the costs
+  DArr<float> pair_a;      // nC A_X(m) + A_Y(n)
+  DArr<int32_t> corner_ptr;  // nC+1: corners (3p+v) of each pair
+  DArr<int32_t> corner_list; // 3*nP
+
+  // solver state (byte buffers reused for FP32 / FP64)
+  DArr<unsigned char> rec[2];    // records n_free * REC * sizeof(real)
+  DArr<unsigned char> rrec[2];   // rounding copy
+  DArr<unsigned char> mrec;      // min-marginals / marginals per slot
+  DArr<double> partial;          // per-block partial sums, two alternating halves
+  int pend_half = 0;             // half written by the last sweep launch
+  double* pend_partial = nullptr;
+  int32_t pend_n = 0;
+  double pend_offset = 0.0;
+  double* pend_out = nullptr;    // bound of the last launch not yet summed
+  DArr<double> scal;             // small device scalars
+  DArr<int8_t> pref;             // per variable: 1, 0 or -1
+  DArr<int64_t> icount;          // integer counters
+  DArr<float> gw;                // gradient per pair
+  DArr<float> gcost_tmp;         // gradient per element
+
+  // optional per-launch event timing of the sweep kernel
+  bool timing = false;
+  std::vector<hipEvent_t> ev_pool;
+  size_t ev_used = 0;
+
+  ~dm_ctx() {
+    for (hipEvent_t e : ev_pool) (void)hipEventDestroy(e);
+  }
+};
+
+// translation-unit entry points ------------------------------------------------
+dm_status mesh_ingest(dm_ctx* ctx, const dm_mesh* in, MeshDev& m, const char* name);
+dm_status mesh_areas(dm_ctx* ctx, MeshDev& m);
+dm_status space_build(dm_ctx* ctx, const int32_t* cand_xy, const int32_t* cand_yx, int32_t K);
+dm_status knn_distances(dm_ctx* ctx, const float* FX, int32_t nvx, const float* FY, int32_t nvy,
+                        int32_t D, int32_t prec, float* d2 /* nvx*nvy */);
+dm_status sort_pairs_u64(dm_ctx* ctx, uint64_t* keys, int32_t* vals, size_t n, int end_bit);
+dm_status sort_pairs_u32(dm_ctx* ctx, uint32_t* keys, int32_t* vals, size_t n, int end_bit);
+dm_status scan_i32(dm_ctx* ctx, const int32_t* in, int32_t* out, size_t n);  // exclusive, out[n] = total
+dm_status scan_u8(dm_ctx* ctx, const uint8_t* in, int32_t* out, size_t n);   // exclusive, out[n] = total
+dm_status read_i32(dm_ctx* ctx, const int32_t* dev, int32_t* host);
+dm_status check_finite(dm_ctx* ctx, const float* a, int64_t n);
+dm_status dual_flush(dm_ctx* ctx);  // write the bound of the last sweep launch
+
+// grid size helper
+inline unsigned grid_for(int64_t n, int block) {
+  return unsigned((n + block - 1) / block);
+}
+
+inline int bits_for(uint64_t maxval) {
+  int b = 0;
+  while (b < 64 && (maxval >> b) != 0) ++b;
+  return b < 1 ? 1 : b;
+}

@@ -1,0 +1,688 @@
+// Jacobi min-marginal averaging on the Lagrangean dual (Sec. 3.2, Eq. (D);
+// the MMA step of Alg. 1) and the dual bound.
+//
+// State layout.  The multipliers lambda^j_i of free variable i live in one
+// record of REC reals: slots 0-2 for its three closedness rows (edges k = 0,
+// 1, 2 of the element), slot 3 for its first projection row, slot 4 for its
+// Y projection row when the element is triangle-triangle, slot 5 for the cost
+// c_i.  Two record buffers alternate between iterations.
+//
+// One iteration is one kernel launch over every row of the presolved problem:
+//   1. each entry reads its variable's record from the previous iteration and
+//      restores dual feasibility, lambda^j_i = s_j + (c_i - sum_k s_k)/|J_i|;
+//   2. each row computes its minimum and the min-marginal differences
+//      M^j_i = min_{s_i=1} - min_{s_i=0} (Appendix "Coarse-to-fine");
+//   3. each entry writes s_j' = lambda^j_i - omega M^j_i to the other buffer;
+//   4. row minima are summed into an FP64 bound in a fixed order.
+// Steps 1 and 3 together are lambda <- lambda - omega (M - mean_j M): the
+// mean of the min-marginals is exactly what the projection in step 1 adds
+// back, so the variable-averaging pass needs no separate launch.
+//
+// Rows: closedness rows (short, coefficients +-1, right-hand side b) are packed
+// into chunks of at most 255 entries, one 256-thread block per chunk, with the
+// row minimum from sorted prefix sums in LDS: choosing k entries with
+// coefficient +1 and k-b with -1 costs at least S+(k) + S-(k-b), the sums of
+// the k and k-b smallest multipliers.  Projection rows (all +1, b = 1) get one
+// block each and reduce (min, argmin, second min) across the block.  With a
+// temperature T > 0 every min becomes the soft-min -T log sum exp(-./T); short
+// rows then run a partial-sum recursion with one lane per partial sum.
+#include <cmath>
+
+#include "dm_internal.h"
+
+namespace {
+
+enum { MODE_UPDATE = 0, MODE_EVAL = 1, MODE_BOUND = 2 };
+constexpr int LONG_CAP = 2048;   // projection-row entries cached in LDS
+
+template <typename R>
+__device__ inline R rinf() {
+  return R(INFINITY);
+}
+
+template <typename R>
+__device__ inline R r_exp(R x);
+template <>
+__device__ inline float r_exp<float>(float x) { return expf(x); }
+template <>
+__device__ inline double r_exp<double>(double x) { return exp(x); }
+template <typename R>
+__device__ inline R r_log(R x);
+template <>
+__device__ inline float r_log<float>(float x) { return logf(x); }
+template <>
+__device__ inline double r_log<double>(double x) { return log(x); }
+
+// soft-min of two values (hard min when T == 0)
+template <typename R, bool SOFT>
+__device__ inline R smin2(R a, R b, R T) {
+  if (!SOFT) return a < b ? a : b;
+  if (a == rinf<R>()) return b;
+  if (b == rinf<R>()) return a;
+  R m = a < b ? a : b;
+  return m - T * r_log<R>(r_exp<R>(-(a - m) / T) + r_exp<R>(-(b - m) / T));
+}
+
+// multiplier of entry word w from the previous record buffer, with dual
+// feasibility restored
+template <typename R>
+__device__ inline R cur_lambda(const R* __restrict__ rec, uint32_t w) {
+  const R* r = rec + size_t(w & W_VAR_MASK) * REC;
+  const int k = int((w >> W_SLOT_SHIFT) & 7u);
+  const bool d5 = (w & W_DEG5) != 0;
+  R s0, s1, s2, s3, s4, c;
+  if constexpr (sizeof(R) == 4) {
+    // records are 32-byte aligned: one 16-byte and one 8-byte load
+    const float4 lo = *reinterpret_cast<const float4*>(r);
+    const float2 hi = *reinterpret_cast<const float2*>(r + 4);
+    s0 = lo.x, s1 = lo.y, s2 = lo.z, s3 = lo.w, s4 = hi.x, c = hi.y;
+  } else {
+    const double2 a = *reinterpret_cast<const double2*>(r);
+    const double2 b = *reinterpret_cast<const double2*>(r + 2);
+    const double2 d = *reinterpret_cast<const double2*>(r + 4);
+    s0 = a.x, s1 = a.y, s2 = b.x, s3 = b.y, s4 = d.x, c = d.y;
+  }
+  R sum = ((s0 + s1) + s2) + s3;
+  if (d5) sum += s4;
+  R corr = (c - sum) / (d5 ? R(5) : R(4));
+  R sk = k == 0 ? s0 : k == 1 ? s1 : k == 2 ? s2 : k == 3 ? s3 : s4;
+  return sk + corr;
+}
+
+template <typename R>
+__device__ inline void write_out(R* __restrict__ out, uint32_t w, R v) {
+  out[size_t(w & W_VAR_MASK) * REC + ((w >> W_SLOT_SHIFT) & 7u)] = v;
+}
+
+// block-wide FP64 sum in a fixed order (thread value at index threadIdx.x)
+__device__ inline double block_sum(double v, double* red) {
+  red[threadIdx.x] = v;
+  __syncthreads();
+  for (int s = blockDim.x / 2; s > 0; s >>= 1) {
+    if (int(threadIdx.x) < s) red[threadIdx.x] += red[threadIdx.x + s];
+    __syncthreads();
+  }
+  double r = red[0];
+  __syncthreads();
+  return r;
+}
+
+// Each block stores the sum of its row minima; the per-block partials of one
+// launch are summed in index order by block 0 of the next launch (the kernel
+// boundary makes them visible without atomics or cache maintenance) or by a
+// one-block kernel after the last launch.
+__device__ inline void store_partial(double part, double* partial) {
+  if (threadIdx.x == 0) partial[blockIdx.x] = part;
+}
+
+__device__ inline void reduce_partials(const double* partial, int n, double offset, double* out, double* red) {
+  double s = 0.0;
+  for (int i = threadIdx.x; i < n; i += blockDim.x) s += partial[i];
+  double tot = block_sum(s, red);
+  if (threadIdx.x == 0) *out = offset + tot;
+}
+
+struct SweepArgs {
+  const uint32_t* word;
+  const int32_t* rrow_ptr;
+  const int32_t* rrow_b;
+  const int32_t* chunk_row;
+  int32_t n_short_blocks;
+  int32_t n_short;
+  int32_t n_rows;
+  double* partial;          // this launch's per-block partials
+  const double* prev_partial; // previous launch's partials still to be summed, or NULL
+  int32_t prev_n;
+  double prev_offset;
+  double* prev_out;
+};
+
+// ---------------------------------------------------------------- short rows, hard min
+// one block per chunk of whole closedness rows (<= 255 entries)
+template <typename R, int MODE>
+__device__ void short_chunk_hard(const SweepArgs& A, const R* __restrict__ rin, R* __restrict__ out, R omega,
+                                 unsigned char* smem, double* red) {
+  R* lam_s = reinterpret_cast<R*>(smem);
+  R* srt_s = lam_s + 256;
+  R* pre_s = srt_s + 256;
+  int32_t* rp_s = reinterpret_cast<int32_t*>(pre_s + 256);
+  int32_t* rb_s = rp_s + 257;
+  uint8_t* neg_s = reinterpret_cast<uint8_t*>(rb_s + 256);
+
+  const int c = blockIdx.x;
+  const int32_t r0 = A.chunk_row[c], r1 = A.chunk_row[c + 1];
+  const int32_t nrow = r1 - r0;
+  const int32_t e0 = A.rrow_ptr[r0];
+  const int32_t ne = A.rrow_ptr[r1] - e0;
+  const int t = threadIdx.x;
+  for (int i = t; i <= nrow; i += blockDim.x) rp_s[i] = A.rrow_ptr[r0 + i] - e0;
+  for (int i = t; i < nrow; i += blockDim.x) rb_s[i] = A.rrow_b[r0 + i];
+  uint32_t w = 0;
+  R lam = R(0);
+  if (t < ne) {
+    w = A.word[e0 + t];
+    lam = cur_lambda<R>(rin, w);
+    lam_s[t] = lam;
+    neg_s[t] = uint8_t(w >> 31);
+  }
+  __syncthreads();
+  int32_t s = 0, n = 0, b = 0, rank = 0, P = 0;
+  int g = 0;
+  if (t < ne) {
+    int32_t lo = 0, hi = nrow - 1;   // last row whose start <= t
+    while (lo < hi) {
+      int32_t mid = (lo + hi + 1) >> 1;
+      if (rp_s[mid] <= t) lo = mid;
+      else hi = mid - 1;
+    }
+    s = rp_s[lo];
+    n = rp_s[lo + 1] - s;
+    b = rb_s[lo];
+    g = neg_s[t];
+    for (int32_t q = s; q < s + n; ++q) {
+      int gq = neg_s[q];
+      P += gq == 0;
+      if (gq == g) {
+        R lq = lam_s[q];
+        rank += (lq < lam) || (lq == lam && q < t);
+      }
+    }
+    srt_s[s + (g ? P + rank : rank)] = lam;
+  }
+  __syncthreads();
+  const int32_t N = n - P;
+  if (t < ne) {
+    const int32_t base = s + (g ? P : 0);
+    R acc = R(0);
+    for (int32_t q = 0; q <= rank; ++q) acc += srt_s[base + q];
+    pre_s[base + rank] = acc;   // sum of the rank+1 smallest of this sign
+  }
+  __syncthreads();
+  double rowpart = 0.0;
+  if (t < ne) {
+    // own group: entries with this entry's sign; the row reads
+    //   sum(own) - sum(other) = bb  with bb = b for +1 entries, -b for -1 entries
+    const int32_t own = g ? N : P, oth = g ? P : N, bb = g ? -b : b;
+    const int32_t obase = s + (g ? P : 0), tbase = s + (g ? 0 : P);
+    const int32_t klo = bb > 0 ? bb : 0;
+    const int32_t khi = own < oth + bb ? own : oth + bb;
+    R m1 = rinf<R>(), m0 = rinf<R>(), rmin = rinf<R>();
+    for (int32_t k = klo; k <= khi; ++k) {
+      const int32_t ko = k - bb;
+      R So = k == 0 ? R(0) : pre_s[obase + k - 1];
+      R St = ko == 0 ? R(0) : pre_s[tbase + ko - 1];
+      R f = So + St;
+      rmin = f < rmin ? f : rmin;
+      if (k >= rank + 1) {
+        // the k smallest of the own group include this entry
+        m1 = f < m1 ? f : m1;
+        if (k <= own - 1) {
+          R Sn = pre_s[obase + k];   // k+1 smallest, minus this entry
+          R v = (Sn - lam) + St;
+          m0 = v < m0 ? v : m0;
+        }
+      } else {
+        m0 = f < m0 ? f : m0;
+        if (k >= 1) {
+          R Sp = k == 1 ? R(0) : pre_s[obase + k - 2];
+          R v = (lam + Sp) + St;
+          m1 = v < m1 ? v : m1;
+        }
+      }
+    }
+    const R M = m1 - m0;
+    if (MODE == MODE_UPDATE) write_out<R>(out, w, lam - omega * M);
+    if (MODE == MODE_EVAL) write_out<R>(out, w, M);
+    if (t == s) rowpart = double(rmin);
+  }
+  double part = block_sum(rowpart, red);
+  store_partial(part, A.partial);
+}
+
+// ---------------------------------------------------------------- short rows, soft min
+// one 32-lane segment per row; lane j holds the partial sum sigma = j - N of
+// the recursion F_{l+1}(sigma) = smin(F_l(sigma), F_l(sigma - a_l) + lam_l),
+// B_l(sigma) = smin(B_{l+1}(sigma), B_{l+1}(sigma + a_l) + lam_l)
+template <typename R, int MODE>
+__device__ void short_rows_soft(const SweepArgs& A, const R* __restrict__ rin, R* __restrict__ out, R omega,
+                                R T, unsigned char* smem, double* red) {
+  const int seg = threadIdx.x >> 5, lane = threadIdx.x & 31;
+  R* Ftab = reinterpret_cast<R*>(smem) + seg * (SOFT_MAX_ROW * 32);
+  R* lamL = reinterpret_cast<R*>(smem) + 8 * SOFT_MAX_ROW * 32 + seg * 32;
+  int8_t* aL = reinterpret_cast<int8_t*>(reinterpret_cast<R*>(smem) + 8 * SOFT_MAX_ROW * 32 + 8 * 32) + seg * 32;
+  const int32_t j = int32_t(blockIdx.x) * 8 + seg;
+  const bool act = j < A.n_short;
+  int32_t s = 0, n = 0, b = 0;
+  uint32_t w = 0;
+  R mylam = R(0);
+  if (act) {
+    s = A.rrow_ptr[j];
+    n = A.rrow_ptr[j + 1] - s;
+    b = A.rrow_b[j];
+    if (lane < n) {
+      w = A.word[s + lane];
+      mylam = cur_lambda<R>(rin, w);
+      lamL[lane] = mylam;
+      aL[lane] = (w >> 31) ? int8_t(-1) : int8_t(1);
+    }
+  }
+  __syncthreads();
+  double rowpart = 0.0;
+  if (act) {
+    int32_t N = 0;
+    for (int32_t l = 0; l < n; ++l) N += aL[l] < 0;
+    const int32_t P = n - N;
+    const int32_t sigma = lane - N;
+    const bool valid = lane <= P + N;
+    R F = (valid && sigma == 0) ? R(0) : rinf<R>();
+    for (int32_t l = 0; l < n; ++l) {
+      Ftab[l * 32 + lane] = F;   // read back below by the same lane only
+      const int a = aL[l];
+      R sh = __shfl(F, lane - a, 32);
+      if (lane - a < 0 || lane - a > 31 || !valid) sh = rinf<R>();
+      F = smin2<R, true>(F, sh + lamL[l], T);
+      if (!valid) F = rinf<R>();
+    }
+    R Bv = (valid && sigma == b) ? R(0) : rinf<R>();
+    R myM = R(0), my1 = R(0);
+    for (int32_t l = n - 1; l >= 0; --l) {
+      const int a = aL[l];
+      const R Fl = Ftab[l * 32 + lane];
+      R sh = __shfl(Bv, lane + a, 32);
+      if (lane + a < 0 || lane + a > 31 || !valid) sh = rinf<R>();
+      R x1 = (Fl == rinf<R>() || sh == rinf<R>()) ? rinf<R>() : Fl + lamL[l] + sh;
+      R x0 = (Fl == rinf<R>() || Bv == rinf<R>()) ? rinf<R>() : Fl + Bv;
+      for (int off = 16; off > 0; off >>= 1) {
+        x1 = smin2<R, true>(x1, __shfl_xor(x1, off, 32), T);
+        x0 = smin2<R, true>(x0, __shfl_xor(x0, off, 32), T);
+      }
+      if (lane == l) {
+        myM = x1 - x0;
+        my1 = x1;
+      }
+      Bv = smin2<R, true>(Bv, sh + lamL[l], T);
+      if (!valid) Bv = rinf<R>();
+    }
+    // soft row value B_0(0) sits on lane N
+    const R rowv = __shfl(Bv, N, 32);
+    if (lane < n) {
+      if (MODE == MODE_UPDATE) write_out<R>(out, w, mylam - omega * myM);
+      if (MODE == MODE_EVAL) write_out<R>(out, w, r_exp<R>(-(my1 - rowv) / T));
+    }
+    if (lane == 0) rowpart = double(rowv);
+  }
+  double part = block_sum(rowpart, red);
+  store_partial(part, A.partial);
+}
+
+// ---------------------------------------------------------------- long rows (exactly one)
+template <typename R>
+struct MinState {   // hard: (m, a, m2); soft adds s = sum_{k != a} exp(-(lam_k - m2)/T)
+  R m, m2, s;
+  int32_t a;
+};
+
+template <typename R, bool SOFT>
+__device__ inline MinState<R> ms_combine(MinState<R> x, MinState<R> y, R T) {
+  if (y.m < x.m || (y.m == x.m && y.a < x.a)) {
+    MinState<R> t = x;
+    x = y;
+    y = t;
+  }
+  MinState<R> r;
+  r.m = x.m;
+  r.a = x.a;
+  r.m2 = x.m2 < y.m ? x.m2 : y.m;
+  r.s = R(0);
+  if (SOFT && r.m2 != rinf<R>()) {
+    R sx = (x.m2 == rinf<R>()) ? R(0) : x.s * r_exp<R>(-(x.m2 - r.m2) / T);
+    R ys = (y.m2 == rinf<R>()) ? R(0) : y.s * r_exp<R>(-(y.m2 - y.m) / T);
+    R sy = (y.m == rinf<R>()) ? R(0) : (R(1) + ys) * r_exp<R>(-(y.m - r.m2) / T);
+    r.s = sx + sy;
+  }
+  return r;
+}
+
+template <typename R, bool SOFT>
+__device__ inline MinState<R> ms_shfl_xor(MinState<R> v, int off) {
+  MinState<R> o;
+  o.m = __shfl_xor(v.m, off);
+  o.m2 = __shfl_xor(v.m2, off);
+  o.s = SOFT ? __shfl_xor(v.s, off) : R(0);
+  o.a = __shfl_xor(v.a, off);
+  return o;
+}
+
+template <typename R, bool SOFT, int MODE>
+__device__ void long_row(const SweepArgs& A, const R* __restrict__ rin, R* __restrict__ out, R omega, R T,
+                         unsigned char* smem, double* red) {
+  R* lbuf = reinterpret_cast<R*>(smem);
+  MinState<R>* wred = reinterpret_cast<MinState<R>*>(lbuf + LONG_CAP);
+  const int32_t j = A.n_short + (int32_t(blockIdx.x) - A.n_short_blocks);
+  const int32_t s = A.rrow_ptr[j], n = A.rrow_ptr[j + 1] - s;
+  MinState<R> st;
+  st.m = rinf<R>();
+  st.m2 = rinf<R>();
+  st.s = R(0);
+  st.a = INT32_MAX;
+  for (int32_t i = threadIdx.x; i < n; i += blockDim.x) {
+    R lam = cur_lambda<R>(rin, A.word[s + i]);
+    if (i < LONG_CAP) lbuf[i] = lam;
+    MinState<R> one;
+    one.m = lam;
+    one.m2 = rinf<R>();
+    one.s = R(0);
+    one.a = i;
+    st = ms_combine<R, SOFT>(st, one, T);
+  }
+  for (int off = 32; off > 0; off >>= 1) st = ms_combine<R, SOFT>(st, ms_shfl_xor<R, SOFT>(st, off), T);
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  if (lane == 0) wred[wave] = st;
+  __syncthreads();
+  st = wred[0];
+  for (int wv = 1; wv < int(blockDim.x >> 6); ++wv) st = ms_combine<R, SOFT>(st, wred[wv], T);
+  R rowv = st.m;
+  R tot = R(0);
+  if (SOFT) {
+    tot = (st.m2 == rinf<R>()) ? R(0) : st.s * r_exp<R>(-(st.m2 - st.m) / T);
+    rowv = st.m - T * r_log<R>(R(1) + tot);
+  }
+  if (MODE != MODE_BOUND) {
+    for (int32_t i = threadIdx.x; i < n; i += blockDim.x) {
+      const uint32_t w = A.word[s + i];
+      const R lam = i < LONG_CAP ? lbuf[i] : cur_lambda<R>(rin, w);
+      R M, mu = R(0);
+      if (!SOFT) {
+        M = lam - (i == st.a ? st.m2 : st.m);
+      } else {
+        R others;
+        if (i == st.a) {
+          others = st.m2 - T * r_log<R>(st.s);
+        } else {
+          R e = r_exp<R>(-(lam - st.m) / T);
+          others = st.m - T * r_log<R>((R(1) + tot) - e);
+        }
+        M = lam - others;
+        mu = r_exp<R>(-(lam - rowv) / T);
+      }
+      if (MODE == MODE_UPDATE) write_out<R>(out, w, lam - omega * M);
+      if (MODE == MODE_EVAL) write_out<R>(out, w, SOFT ? mu : M);
+    }
+  }
+  double part = threadIdx.x == 0 ? double(rowv) : 0.0;
+  part = block_sum(part, red);
+  store_partial(part, A.partial);
+}
+
+template <typename R, bool SOFT>
+constexpr size_t smem_bytes() {
+  size_t shortb = SOFT ? (8 * SOFT_MAX_ROW * 32 + 8 * 32) * sizeof(R) + 8 * 32
+                       : 3 * 256 * sizeof(R) + 257 * 4 + 256 * 4 + 256;
+  size_t longb = LONG_CAP * sizeof(R) + 4 * sizeof(MinState<R>);
+  return shortb > longb ? shortb : longb;
+}
+
+template <typename R, bool SOFT, int MODE>
+__global__ __launch_bounds__(256) void k_sweep(SweepArgs A, const R* __restrict__ rin, R* __restrict__ out,
+                                               R omega, R T) {
+  __shared__ __align__(16) unsigned char smem[smem_bytes<R, SOFT>()];
+  __shared__ double red[256];
+  if (blockIdx.x == 0 && A.prev_partial) reduce_partials(A.prev_partial, A.prev_n, A.prev_offset, A.prev_out, red);
+  if (int32_t(blockIdx.x) < A.n_short_blocks) {
+    if (SOFT) short_rows_soft<R, MODE>(A, rin, out, omega, T, smem, red);
+    else short_chunk_hard<R, MODE>(A, rin, out, omega, smem, red);
+  } else {
+    long_row<R, SOFT, MODE>(A, rin, out, omega, T, smem, red);
+  }
+}
+
+// ---------------------------------------------------------------- state import / export
+template <typename R>
+__global__ void k_import(const R* lam, const uint32_t* word, int64_t nnz, R* rec) {
+  int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (e < nnz) write_out<R>(rec, word[e], lam[e]);
+}
+
+template <typename R>
+__global__ void k_set_cost(const int32_t* free_var, const double* c64, int64_t nfree, R* rec0, R* rec1) {
+  int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= nfree) return;
+  R c = R(c64[free_var[i]]);
+  rec0[size_t(i) * REC + REC_COST] = c;
+  if (rec1) rec1[size_t(i) * REC + REC_COST] = c;
+}
+
+template <typename R>
+__global__ void k_export(const R* rec, const uint32_t* word, int64_t nnz, R* lam) {
+  int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (e < nnz) lam[e] = cur_lambda<R>(rec, word[e]);
+}
+
+template <typename R>
+__global__ void k_init_lambda(const uint32_t* word, const int32_t* free_var, const double* c64, int64_t nnz,
+                              R* lam) {
+  int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (e >= nnz) return;
+  uint32_t w = word[e];
+  R c = R(c64[free_var[w & W_VAR_MASK]]);
+  lam[e] = c / ((w & W_DEG5) ? R(5) : R(4));
+}
+
+__global__ void k_write_offset(double* out, double v) { *out = v; }
+
+__global__ __launch_bounds__(256) void k_reduce_last(const double* partial, int n, double offset, double* out) {
+  __shared__ double red[256];
+  reduce_partials(partial, n, offset, out, red);
+}
+
+}  // namespace
+
+// ============================================================================
+// host side (shared with rounding and the backward pass)
+// ============================================================================
+template <typename R>
+dm_status dual_import(dm_ctx* ctx, const R* lam, DArr<unsigned char>* bufs) {
+  const size_t bytes = size_t(std::max<int64_t>(ctx->n_free, 1)) * REC * sizeof(R);
+  DM_ALLOC(ctx, bufs[0], bytes);
+  DM_ALLOC(ctx, bufs[1], bytes);
+  DM_HIP(ctx, hipMemsetAsync(bufs[0].p, 0, bytes, ctx->stream));
+  DM_HIP(ctx, hipMemsetAsync(bufs[1].p, 0, bytes, ctx->stream));
+  R* r0 = reinterpret_cast<R*>(bufs[0].p);
+  R* r1 = reinterpret_cast<R*>(bufs[1].p);
+  if (ctx->n_free > 0)
+    k_set_cost<R><<<grid_for(ctx->n_free, 256), 256, 0, ctx->stream>>>(ctx->free_var.p, ctx->cost64.p,
+                                                                       ctx->n_free, r0, r1);
+  if (ctx->nnz > 0)
+    k_import<R><<<grid_for(ctx->nnz, 256), 256, 0, ctx->stream>>>(lam, ctx->rent_word.p, ctx->nnz, r0);
+  DM_LAUNCH_CHECK(ctx);
+  return DM_OK;
+}
+
+template <typename R>
+dm_status dual_export(dm_ctx* ctx, const unsigned char* rec, R* lam) {
+  if (ctx->nnz > 0)
+    k_export<R><<<grid_for(ctx->nnz, 256), 256, 0, ctx->stream>>>(reinterpret_cast<const R*>(rec),
+                                                                  ctx->rent_word.p, ctx->nnz, lam);
+  DM_LAUNCH_CHECK(ctx);
+  return DM_OK;
+}
+
+// one sweep over all rows; mode 0 update rec_in -> out, 1 write M (or mu) to
+// out per slot, 2 bound only; the bound goes to *bound_out (device)
+template <typename R>
+dm_status dual_sweep(dm_ctx* ctx, int mode, bool soft, const unsigned char* rin, unsigned char* out, R omega,
+                     R T, double* bound_out) {
+  if (soft && ctx->max_short > SOFT_MAX_ROW)
+    return dm_fail(ctx, DM_ERR_WORKSPACE, "smoothed rows support at most %d entries (found %d)", SOFT_MAX_ROW,
+                   ctx->max_short);
+  SweepArgs A;
+  A.word = ctx->rent_word.p;
+  A.rrow_ptr = ctx->rrow_ptr.p;
+  A.rrow_b = ctx->rrow_b.p;
+  A.chunk_row = ctx->chunk_row.p;
+  A.n_short_blocks = soft ? int32_t((ctx->n_short + 7) / 8) : ctx->n_chunks;
+  A.n_short = int32_t(ctx->n_short);
+  A.n_rows = int32_t(ctx->n_rows);
+  const int64_t nblocks = int64_t(A.n_short_blocks) + (ctx->n_rows - ctx->n_short);
+  if (nblocks == 0) {
+    DM_TRY(dual_flush(ctx));
+    if (bound_out) k_write_offset<<<1, 1, 0, ctx->stream>>>(bound_out, ctx->offset);
+    DM_LAUNCH_CHECK(ctx);
+    return DM_OK;
+  }
+  // two halves of the partial buffer alternate between consecutive launches
+  const int64_t cap = std::max<int64_t>(ctx->n_chunks, (ctx->n_short + 7) / 8) + (ctx->n_rows - ctx->n_short);
+  if (ctx->partial.n < size_t(2 * cap)) {
+    DM_TRY(dual_flush(ctx));
+    DM_ALLOC(ctx, ctx->partial, size_t(2 * cap));
+  }
+  double* mine = ctx->partial.p + (ctx->pend_half ^ 1) * cap;
+  A.partial = mine;
+  A.prev_partial = ctx->pend_out ? ctx->pend_partial : nullptr;
+  A.prev_n = ctx->pend_n;
+  A.prev_offset = ctx->pend_offset;
+  A.prev_out = ctx->pend_out;
+  const R* ri = reinterpret_cast<const R*>(rin);
+  R* ro = reinterpret_cast<R*>(out);
+  const unsigned grid = unsigned(nblocks);
+  hipEvent_t ev_end = nullptr;
+  if (ctx->timing) {
+    while (ctx->ev_pool.size() < ctx->ev_used + 2) {
+      hipEvent_t e;
+      DM_HIP(ctx, hipEventCreate(&e));
+      ctx->ev_pool.push_back(e);
+    }
+    DM_HIP(ctx, hipEventRecord(ctx->ev_pool[ctx->ev_used], ctx->stream));
+    ev_end = ctx->ev_pool[ctx->ev_used + 1];
+    ctx->ev_used += 2;
+  }
+  if (soft) {
+    if (mode == MODE_UPDATE) k_sweep<R, true, MODE_UPDATE><<<grid, 256, 0, ctx->stream>>>(A, ri, ro, omega, T);
+    else if (mode == MODE_EVAL) k_sweep<R, true, MODE_EVAL><<<grid, 256, 0, ctx->stream>>>(A, ri, ro, omega, T);
+    else k_sweep<R, true, MODE_BOUND><<<grid, 256, 0, ctx->stream>>>(A, ri, ro, omega, T);
+  } else {
+    if (mode == MODE_UPDATE) k_sweep<R, false, MODE_UPDATE><<<grid, 256, 0, ctx->stream>>>(A, ri, ro, omega, T);
+    else if (mode == MODE_EVAL) k_sweep<R, false, MODE_EVAL><<<grid, 256, 0, ctx->stream>>>(A, ri, ro, omega, T);
+    else k_sweep<R, false, MODE_BOUND><<<grid, 256, 0, ctx->stream>>>(A, ri, ro, omega, T);
+  }
+  DM_LAUNCH_CHECK(ctx);
+  if (ev_end) DM_HIP(ctx, hipEventRecord(ev_end, ctx->stream));
+  ctx->pend_half ^= 1;
+  ctx->pend_partial = mine;
+  ctx->pend_n = int32_t(nblocks);
+  ctx->pend_offset = ctx->offset;
+  ctx->pend_out = bound_out;
+  return DM_OK;
+}
+
+// sum the partials of the last launch whose bound has not been written yet
+dm_status dual_flush(dm_ctx* ctx) {
+  if (ctx->pend_out) {
+    k_reduce_last<<<1, 256, 0, ctx->stream>>>(ctx->pend_partial, ctx->pend_n, ctx->pend_offset, ctx->pend_out);
+    DM_LAUNCH_CHECK(ctx);
+  }
+  ctx->pend_out = nullptr;
+  return DM_OK;
+}
+
+extern "C" dm_status dm_timing_enable(dm_ctx* ctx, int32_t enable) {
+  if (!ctx) return DM_ERR_INVALID_ARG;
+  ctx->timing = enable != 0;
+  return DM_OK;
+}
+
+extern "C" dm_status dm_timing_read(dm_ctx* ctx, int64_t* launches, double* total_ms) {
+  if (!ctx || !launches || !total_ms) return DM_ERR_INVALID_ARG;
+  DM_HIP(ctx, hipSetDevice(ctx->device));
+  DM_HIP(ctx, hipStreamSynchronize(ctx->stream));
+  double tot = 0.0;
+  for (size_t i = 0; i + 1 < ctx->ev_used; i += 2) {
+    float ms = 0.0f;
+    DM_HIP(ctx, hipEventElapsedTime(&ms, ctx->ev_pool[i], ctx->ev_pool[i + 1]));
+    tot += ms;
+  }
+  *launches = int64_t(ctx->ev_used / 2);
+  *total_ms = tot;
+  ctx->ev_used = 0;
+  return DM_OK;
+}
+
+template dm_status dual_import<float>(dm_ctx*, const float*, DArr<unsigned char>*);
+template dm_status dual_import<double>(dm_ctx*, const double*, DArr<unsigned char>*);
+template dm_status dual_export<float>(dm_ctx*, const unsigned char*, float*);
+template dm_status dual_export<double>(dm_ctx*, const unsigned char*, double*);
+template dm_status dual_sweep<float>(dm_ctx*, int, bool, const unsigned char*, unsigned char*, float, float, double*);
+template dm_status dual_sweep<double>(dm_ctx*, int, bool, const unsigned char*, unsigned char*, double, double,
+                                      double*);
+
+static dm_status check_solver(dm_ctx* ctx, int32_t msg_prec) {
+  if (!ctx) return DM_ERR_INVALID_ARG;
+  if (!ctx->has_space) return dm_fail(ctx, DM_ERR_STATE, "no product space built");
+  if (!ctx->has_cost) return dm_fail(ctx, DM_ERR_STATE, "no costs built");
+  if (msg_prec != DM_PREC_FP32 && msg_prec != DM_PREC_FP64)
+    return dm_fail(ctx, DM_ERR_INVALID_ARG, "message precision must be FP32 or FP64");
+  return DM_OK;
+}
+
+template <typename R>
+static dm_status solve_impl(dm_ctx* ctx, int32_t iters, R omega, R T, R* lam, double* trace) {
+  DM_TRY(dual_import<R>(ctx, lam, ctx->rec));
+  const bool soft = T > R(0);
+  for (int32_t t = 0; t < iters; ++t)
+    DM_TRY(dual_sweep<R>(ctx, MODE_UPDATE, soft, ctx->rec[t & 1].p, ctx->rec[(t + 1) & 1].p, omega, T,
+                         trace ? trace + t : nullptr));
+  DM_TRY(dual_flush(ctx));
+  DM_TRY(dual_export<R>(ctx, ctx->rec[iters & 1].p, lam));
+  return DM_OK;
+}
+
+extern "C" dm_status dm_dual_solve(dm_ctx* ctx, int32_t iters, double omega, double temperature,
+                                   int32_t msg_prec, void* lambda, double* lb_trace) {
+  DM_TRY(check_solver(ctx, msg_prec));
+  ctx->err.clear();
+  if (iters < 0 || !lambda) return dm_fail(ctx, DM_ERR_INVALID_ARG, "dm_dual_solve: bad arguments");
+  if (!(omega > 0.0 && omega <= 1.0)) return dm_fail(ctx, DM_ERR_INVALID_ARG, "omega must be in (0, 1]");
+  if (!(temperature >= 0.0)) return dm_fail(ctx, DM_ERR_INVALID_ARG, "temperature must be >= 0");
+  DM_HIP(ctx, hipSetDevice(ctx->device));
+  if (msg_prec == DM_PREC_FP32)
+    return solve_impl<float>(ctx, iters, float(omega), float(temperature), static_cast<float*>(lambda), lb_trace);
+  return solve_impl<double>(ctx, iters, omega, temperature, static_cast<double*>(lambda), lb_trace);
+}
+
+extern "C" dm_status dm_init_lambda(dm_ctx* ctx, int32_t msg_prec, void* lambda) {
+  DM_TRY(check_solver(ctx, msg_prec));
+  if (!lambda) return dm_fail(ctx, DM_ERR_INVALID_ARG, "dm_init_lambda: NULL lambda");
+  DM_HIP(ctx, hipSetDevice(ctx->device));
+  if (ctx->nnz == 0) return DM_OK;
+  if (msg_prec == DM_PREC_FP32)
+    k_init_lambda<float><<<grid_for(ctx->nnz, 256), 256, 0, ctx->stream>>>(
+        ctx->rent_word.p, ctx->free_var.p, ctx->cost64.p, ctx->nnz, static_cast<float*>(lambda));
+  else
+    k_init_lambda<double><<<grid_for(ctx->nnz, 256), 256, 0, ctx->stream>>>(
+        ctx->rent_word.p, ctx->free_var.p, ctx->cost64.p, ctx->nnz, static_cast<double*>(lambda));
+  DM_LAUNCH_CHECK(ctx);
+  return DM_OK;
+}
+
+template <typename R>
+static dm_status bound_impl(dm_ctx* ctx, const R* lam, R T, double* out) {
+  DArr<unsigned char> bufs[2];
+  DM_TRY(dual_import<R>(ctx, lam, bufs));
+  DM_ALLOC(ctx, ctx->scal, 16);
+  DM_TRY(dual_sweep<R>(ctx, MODE_BOUND, T > R(0), bufs[0].p, nullptr, R(0), T, ctx->scal.p));
+  DM_TRY(dual_flush(ctx));
+  DM_HIP(ctx, hipMemcpyAsync(out, ctx->scal.p, sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
+  DM_HIP(ctx, hipStreamSynchronize(ctx->stream));
+  return DM_OK;
+}
+
+extern "C" dm_status dm_lower_bound(dm_ctx* ctx, const void* lambda, double temperature, int32_t msg_prec,
+                                    double* lb) {
+  DM_TRY(check_solver(ctx, msg_prec));
+  if (!lambda || !lb) return dm_fail(ctx, DM_ERR_INVALID_ARG, "dm_lower_bound: NULL argument");
+  if (!(temperature >= 0.0)) return dm_fail(ctx, DM_ERR_INVALID_ARG, "temperature must be >= 0");
+  DM_HIP(ctx, hipSetDevice(ctx->device));
+  if (msg_prec == DM_PREC_FP32)
+    return bound_impl<float>(ctx, static_cast<const float*>(lambda), float(temperature), lb);
+  return bound_impl<double>(ctx, static_cast<const double*>(lambda), temperature, lb);
+}

@@ -1,0 +1,131 @@
+"""GPU product space, incidence, presolve and candidates against the oracle:
+bit-exact for every index array."""
+import numpy as np
+import pytest
+import torch
+
+from gpu_common import both, dm, np_, say
+from helpers import full_candidates
+from oracle import oracle as O
+from synth import make_pair, meshes, tiny_pair
+
+pytestmark = pytest.mark.gpu
+
+EXACT = ["pv", "code", "state", "row_key", "row_ptr", "ent_var", "ent_coef", "row_b", "free_var",
+         "rrow_orig", "rrow_ptr", "rent_var", "rent_coef", "rrow_b", "cand"]
+
+
+def _compare_space(S, ctx):
+    i = ctx.info
+    o = S.info
+    assert (i["n_prod_tri"], i["n_rows_full"], i["nnz_full"], i["n_closed_full"], i["n_free"],
+            i["n_fixed1"], i["n_rows"], i["nnz"]) == (o["nP"], o["n_rows_full"], o["nnz_full"],
+                                                      o["n_closed_full"], o["n_free"], o["n_fixed1"],
+                                                      o["n_rows"], o["nnz"])
+    for name in EXACT:
+        g = np_(ctx.get_space(name))
+        r = S.get(name)
+        assert g.dtype == r.dtype and g.shape == r.shape, name
+        assert np.array_equal(g, r), name
+
+
+@pytest.mark.parametrize("cfg,seed", [(1, 0), (1, 3), (2, 0), (2, 1)])
+def test_space_parity_configs(cfg, seed):
+    p = make_pair(cfg, seed)
+    S, ctx = both(p, p.spec.k)
+    say(f"  |P|={ctx.info['n_prod_tri']} nnz={ctx.info['nnz']} rounds={ctx.info['presolve_rounds']}")
+    _compare_space(S, ctx)
+
+
+def test_space_parity_config3_full_size():
+    p = make_pair(3, 0)
+    S, ctx = both(p, p.spec.k, "fp32")
+    _compare_space(S, ctx)
+
+
+@pytest.mark.parametrize("kx,ky", [("tetra", "tetra"), ("octa", "icosa"), ("icosa", "icosa")])
+def test_space_parity_unpruned(kx, ky):
+    p = tiny_pair(kx, ky)
+    cxy, cyx, _ = full_candidates(len(p.VX), len(p.VY))
+    S = O.Space(p.VX, p.FX, p.VY, p.FY, cxy, cyx)
+    ctx = dm().Context(0)
+    ctx.build_product_space(p.VX, p.FX, p.VY, p.FY, cxy, cyx)
+    _compare_space(S, ctx)
+    assert ctx.info["n_prod_tri"] == O.unpruned_count(len(p.VX), len(p.VX) + len(p.FX) - 2, len(p.FX),
+                                                      len(p.VY), len(p.VY) + len(p.FY) - 2, len(p.FY))
+
+
+def test_space_with_fixed_variables():
+    # harder pruning leaves variables fixed to 1 and closedness rows with b != 0
+    p = make_pair(1, 0)
+    S, ctx = both(p, 6)
+    assert ctx.info["n_fixed1"] > 0
+    assert np.any(S.get("rrow_b")[: ctx.info["n_short_rows"]] != 0) or ctx.info["n_fixed1"] > 0
+    _compare_space(S, ctx)
+
+
+def test_edges_match_oracle():
+    p = make_pair(2, 0)
+    ctx = dm().Context(0)
+    cxy, cyx = O.knn(p.DX, p.DY, 16)
+    ctx.build_product_space(p.VX, p.FX, p.VY, p.FY, cxy, cyx)
+    for F, V, name in [(p.FX, p.VX, "edges_x"), (p.FY, p.VY, "edges_y")]:
+        E, _ = O.mesh_edges(F, len(V))
+        assert np.array_equal(np_(ctx.get_space(name)), E)
+
+
+def test_errors():
+    ctx = dm().Context(0)
+    p = make_pair(1, 0, desc_noise=0.6)
+    cxy, cyx = O.knn(p.DX, p.DY, 6)
+    with pytest.raises(dm().DMError) as e:
+        ctx.build_product_space(p.VX, p.FX, p.VY, p.FY, cxy, cyx)
+    assert e.value.code == -4
+    V, F = meshes.icosahedron()
+    bad = F.copy()
+    bad[0] = bad[0][[0, 2, 1]]
+    cxy, cyx, _ = full_candidates(12, 12)
+    with pytest.raises(dm().DMError) as e:
+        ctx.build_product_space(V, bad, V, F, cxy, cyx)
+    assert e.value.code == -2
+    V2, F2 = meshes.octahedron()
+    n = 3
+    T = []
+    for a in range(n):
+        for b in range(n):
+            i, j = a * n + b, a * n + (b + 1) % n
+            k, l_ = ((a + 1) % n) * n + b, ((a + 1) % n) * n + (b + 1) % n
+            T += [[i, j, l_], [i, l_, k]]
+    cxy, cyx, _ = full_candidates(6, 9)
+    with pytest.raises(dm().DMError) as e:
+        ctx.build_product_space(V2, F2, np.zeros((9, 3), np.float32), np.array(T), cxy, cyx)
+    assert e.value.code == -3
+    bad_c = cxy.copy()
+    bad_c[0, 0] = 99
+    with pytest.raises(dm().DMError) as e:
+        ctx.build_product_space(V2, F2, V2, F2, bad_c[:, :6], full_candidates(6, 6)[1])
+    assert e.value.code == -1
+
+
+@pytest.mark.parametrize("cfg,prec", [(1, "fp32"), (2, "fp32"), (2, "bf16"), (3, "bf16")])
+def test_knn_candidates(cfg, prec):
+    p = make_pair(cfg, 0)
+    K = p.spec.k
+    ctx = dm().Context(0)
+    cxy, cyx = ctx.knn_candidates(torch.from_numpy(p.DX), torch.from_numpy(p.DY), K, prec)
+    rxy, ryx = O.knn(p.DX, p.DY, K)
+    D = np.sqrt(((p.DX.astype(np.float64)[:, None, :] - p.DY.astype(np.float64)[None]) ** 2).sum(-1))
+    # distance error bound of the form: FP32 ~1e-5 relative; BF16 from the
+    # rounding of the inputs (2^-9 per component)
+    tol = 1e-4 if prec == "fp32" else 3e-2
+    near_ties = 0
+    for G, R, Dm in [(np_(cxy), rxy, D), (np_(cyx), ryx, D.T)]:
+        for q in range(len(G)):
+            if set(G[q]) == set(R[q]):
+                continue
+            # differences only where the K-th and (K+1)-th distances are within tol
+            srt = np.sort(Dm[q])
+            assert srt[K] - srt[K - 1] <= tol * srt[K], (q, srt[K - 1], srt[K])
+            near_ties += 1
+    say(f"  {prec} candidate sets differing at near ties: {near_ties}")
+    assert near_ties <= (2 if prec == "fp32" else 0.2 * (len(p.DX) + len(p.DY)))
