@@ -88,11 +88,15 @@ class Workload:
         return out
 
 
-def time_to_gap(cfg, seed, smoothed=False, check_every=50, max_iters=1000):
+def time_to_gap(cfg, seed, smoothed=False, check_every=50, max_iters=2000, smooth_iters=50):
     """Wall time from the first Jacobi iteration until a rounding reaches a
-    primal-dual gap <= 1e-2 (rounding time included); build excluded.  The
-    bound is the hard dual objective at the current multipliers (valid for
-    any multipliers, also smoothed ones); best gap reported if not reached."""
+    primal-dual gap <= 1e-2 (rounding time included); build excluded.
+
+    Differentiable form: ``smooth_iters`` smoothed iterations at the config's
+    temperature and one backward pass to the descriptors come first (their
+    time is included and reported), then hard iterations continue from the
+    smoothed multipliers.  The bound is always the hard dual objective (valid
+    at any multipliers); the best gap is reported if 1 % is not reached."""
     import torch
     w = Workload(cfg, seed)
     c = w.ctx
@@ -100,30 +104,52 @@ def time_to_gap(cfg, seed, smoothed=False, check_every=50, max_iters=1000):
     c.build_product_space(w.VX, w.FX, w.VY, w.FY, cxy, cyx)
     c.build_costs(w.DX, w.DY, w.cost)
     lam = c.init_lambda(w.msg)
-    T = w.spec.temperature if smoothed else 0.0
     torch.cuda.synchronize()
     t0 = time.perf_counter()
+    out = {}
+    if smoothed:
+        T = w.spec.temperature
+        lam, _ = c.dual_solve(lam, smooth_iters, w.spec.omega, T, trace=False)
+        _, gX, gY, LT = c.smoothed_backward(lam, T, w.DX, w.DY)
+        torch.cuda.synchronize()
+        out.update(smooth_seconds=round(time.perf_counter() - t0, 6), smooth_iters=smooth_iters,
+                   L_T=LT, hard_bound_after_smoothing=c.lower_bound(lam, 0.0))
     dmax = -float("inf")
     it = 0
     best = None
     while it < max_iters:
-        lam, tr = c.dual_solve(lam, check_every, w.spec.omega, T)
+        lam, tr = c.dual_solve(lam, check_every, w.spec.omega, 0.0)
         it += check_every
-        if T > 0:
-            c.smoothed_backward(lam, T, w.DX, w.DY)
-            dmax = max(dmax, c.lower_bound(lam, 0.0))
-        else:
-            dmax = max(dmax, float(tr.max()))
+        dmax = max(dmax, float(tr.max()))
         _, pobj, feas, _ = c.round_primal(lam, rounds=10, seed=0)
         if feas:
             g = (pobj - dmax) / pobj
             best = g if best is None else min(best, g)
             if g <= 1e-2:
                 torch.cuda.synchronize()
-                return {"seconds": round(time.perf_counter() - t0, 6), "iters": it, "gap": g}
+                out.update(seconds=round(time.perf_counter() - t0, 6), iters=it, gap=g)
+                return out
     torch.cuda.synchronize()
-    return {"seconds": None, "iters": it, "gap": None, "best_gap": best,
-            "bound": dmax, "note": "1% gap not reached within the iteration cap"}
+    out.update(seconds=None, iters=it, gap=None, best_gap=best, bound=dmax,
+               note="1% gap not reached within the iteration cap")
+    return out
+
+
+def _traffic(n_launch_bytes_note=None):
+    """HBM bytes per sweep launch from the committed rocprofv3 counter summary
+    (FETCH_SIZE and WRITE_SIZE per dispatch, each scaled by its reading on a
+    plain copy kernel), used only while the sweep source is the one that was
+    profiled; otherwise None."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "sweep_plain_fp32_500_hbm_traffic.json")
+    src = os.path.join(ROOT, "paper_2310_08230_amd", "csrc", "dual.hip")
+    if not os.path.exists(path):
+        return None
+    rec = json.load(open(path))
+    h = hashlib.sha256(open(src, "rb").read()).hexdigest()
+    if rec.get("dual_hip_sha256") != h:
+        return None
+    return rec.get("bytes_per_launch")
 
 
 def cpu_baseline(cfg, seed, iters):
@@ -144,7 +170,65 @@ def cpu_baseline(cfg, seed, iters):
                       f"presolve, costs and {iters} Jacobi iterations in {dt:.1f} s"}
 
 
+def summarize_counters(fetch_csv, write_csv, copy_fetch_csv, copy_write_csv, out_json, copy_bytes):
+    """Turn rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE collections (KiB per
+    dispatch) of the sweep kernel and of a plain copy of ``copy_bytes`` bytes
+    into HBM bytes per sweep launch; writes the summary JSON used by the
+    roofline's ``traffic`` field."""
+    import csv
+    import hashlib
+    import statistics
+
+    def per_kernel(path, counter, name_has):
+        vals = [float(r["Counter_Value"]) for r in csv.DictReader(open(path))
+                if r["Counter_Name"] == counter and name_has in r["Kernel_Name"]]
+        return statistics.median(vals), len(vals)
+
+    cf, _ = per_kernel(copy_fetch_csv, "FETCH_SIZE", "copyBuffer")
+    cw, _ = per_kernel(copy_write_csv, "WRITE_SIZE", "copyBuffer")
+    f, nf = per_kernel(fetch_csv, "FETCH_SIZE", "k_sweep<float, false, 0>")
+    wv, nw = per_kernel(write_csv, "WRITE_SIZE", "k_sweep<float, false, 0>")
+    kib = copy_bytes / 1024.0
+    ffac, wfac = kib / cf, kib / cw
+    fetch_b = f * ffac * 1024.0
+    write_b = wv * wfac * 1024.0
+    src = os.path.join(ROOT, "paper_2310_08230_amd", "csrc", "dual.hip")
+    rec = {"kernel": "k_sweep<float,false,MODE_UPDATE>", "workload": "plain_fp32_500 (config 2, seed 0)",
+           "fetch_kib_median": f, "write_kib_median": wv, "dispatches": [nf, nw],
+           "copy_calibration": {"bytes": copy_bytes, "fetch_kib": cf, "write_kib": cw,
+                                "fetch_factor": ffac, "write_factor": wfac},
+           "bytes_per_launch": int(fetch_b + write_b), "fetch_bytes": int(fetch_b), "write_bytes": int(write_b),
+           "dual_hip_sha256": hashlib.sha256(open(src, "rb").read()).hexdigest()}
+    with open(out_json, "w") as fh:
+        json.dump(rec, fh, indent=1)
+    print(json.dumps(rec, indent=1))
+
+
+def summarize_trace(stats_csv, out_txt, command):
+    """Short text summary of a rocprofv3 --kernel-trace --stats run: the
+    command that made it and the kernels by total time."""
+    import csv
+    rows = list(csv.DictReader(open(stats_csv)))
+    rows.sort(key=lambda r: -float(r["TotalDurationNs"]))
+    lines = [f"command: {command}", "",
+             f"{'kernel':70s} {'calls':>7s} {'avg_us':>9s} {'min_us':>9s} {'max_us':>9s} {'total_ms':>9s} {'pct':>6s}"]
+    for r in rows[:20]:
+        name = r["Name"].replace("(anonymous namespace)::", "")
+        name = name.split("(")[0] if not name.startswith("void rocprim") else "rocprim (sort/scan)"
+        lines.append(f"{name[:70]:70s} {int(r['Calls']):7d} {float(r['AverageNs']) / 1e3:9.2f} "
+                     f"{float(r['MinNs']) / 1e3:9.2f} {float(r['MaxNs']) / 1e3:9.2f} "
+                     f"{float(r['TotalDurationNs']) / 1e6:9.2f} {float(r['Percentage']):6.1f}")
+    open(out_txt, "w").write("\n".join(lines) + "\n")
+    print("\n".join(lines))
+
+
 def main():
+    if len(sys.argv) > 1 and sys.argv[1] == "--summarize-counters":
+        summarize_counters(*sys.argv[2:7], int(sys.argv[7]))
+        return
+    if len(sys.argv) > 1 and sys.argv[1] == "--summarize-trace":
+        summarize_trace(sys.argv[2], sys.argv[3], " ".join(sys.argv[4:]))
+        return
     a = parse()
     if a.gpus != 1:
         print(f"bench.py runs on one GPU only; --gpus {a.gpus} is not supported "
@@ -186,7 +270,8 @@ def main():
     bytes_per_launch = BYTES_PER_NNZ * info["nnz"] + BYTES_PER_ROW * info["n_rows"]
     achieved = bytes_per_launch / avg_s / 1e9
     roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+            "frac": round(achieved / HBM_PEAK_GBS, 4),
+            "traffic": _traffic() if a.config == 2 and w.iters > 0 else None,
             "kernel": "k_sweep<float,false,MODE_UPDATE>", "avg_launch_us": round(avg_s * 1e6, 3),
             "bytes_per_launch": bytes_per_launch}
     log(f"[bench] sweep kernel: {n_launch} launches, avg {avg_s * 1e6:.2f} us, {achieved:.0f} GB/s algorithmic")

@@ -78,7 +78,6 @@ constexpr int W_SLOT_SHIFT = 27;
 constexpr uint32_t W_VAR_MASK = (1u << 27) - 1u;
 constexpr int REC = 8;          // record stride: 5 multiplier slots, cost, 2 spare
 constexpr int REC_COST = 5;
-constexpr int CHUNK_SPAN = 192; // short rows starting in one span form a chunk
 constexpr int MAX_SHORT_ROW = 64;
 constexpr int SOFT_MAX_ROW = 24;
 
@@ -129,7 +128,7 @@ struct dm_ctx {
   DArr<uint32_t> rent_word;
   DArr<uint8_t> var_deg;   // n_free
   int32_t n_chunks = 0;
-  DArr<int32_t> chunk_row; // n_chunks+1: first short row of each chunk
+  DArr<int4> chunk_desc;   // n_chunks wave chunks: (first row, rows, first entry, entries)
 
   // costs
   bool has_cost = false;

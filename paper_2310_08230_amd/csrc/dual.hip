@@ -33,7 +33,6 @@
 namespace {
 
 enum { MODE_UPDATE = 0, MODE_EVAL = 1, MODE_BOUND = 2 };
-constexpr int LONG_CAP = 2048;   // projection-row entries cached in LDS
 
 template <typename R>
 __device__ inline R rinf() {
@@ -94,15 +93,14 @@ __device__ inline void write_out(R* __restrict__ out, uint32_t w, R v) {
   out[size_t(w & W_VAR_MASK) * REC + ((w >> W_SLOT_SHIFT) & 7u)] = v;
 }
 
-// block-wide FP64 sum in a fixed order (thread value at index threadIdx.x)
+// block-wide FP64 sum of a 256-thread block in a fixed order: an xor butterfly
+// inside each wave (every lane ends with the same value, since a + b == b + a
+// exactly), then the four wave sums in index order
 __device__ inline double block_sum(double v, double* red) {
-  red[threadIdx.x] = v;
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
   __syncthreads();
-  for (int s = blockDim.x / 2; s > 0; s >>= 1) {
-    if (int(threadIdx.x) < s) red[threadIdx.x] += red[threadIdx.x + s];
-    __syncthreads();
-  }
-  double r = red[0];
+  double r = ((red[0] + red[1]) + red[2]) + red[3];
   __syncthreads();
   return r;
 }
@@ -111,8 +109,8 @@ __device__ inline double block_sum(double v, double* red) {
 // launch are summed in index order by block 0 of the next launch (the kernel
 // boundary makes them visible without atomics or cache maintenance) or by a
 // one-block kernel after the last launch.
-__device__ inline void store_partial(double part, double* partial) {
-  if (threadIdx.x == 0) partial[blockIdx.x] = part;
+__device__ inline void store_partial(double part, double* partial, int32_t item) {
+  if (threadIdx.x == 0) partial[item] = part;
 }
 
 __device__ inline void reduce_partials(const double* partial, int n, double offset, double* out, double* red) {
@@ -126,10 +124,12 @@ struct SweepArgs {
   const uint32_t* word;
   const int32_t* rrow_ptr;
   const int32_t* rrow_b;
-  const int32_t* chunk_row;
+  const int4* chunk_desc;   // (first row, rows, first entry, entries) per chunk
   int32_t n_short_blocks;
   int32_t n_short;
   int32_t n_rows;
+  int32_t n_items;          // short-row blocks + long-row blocks
+  int32_t n_chunks;         // wave chunks of short rows (hard form)
   double* partial;          // this launch's per-block partials
   const double* prev_partial; // previous launch's partials still to be summed, or NULL
   int32_t prev_n;
@@ -138,105 +138,127 @@ struct SweepArgs {
 };
 
 // ---------------------------------------------------------------- short rows, hard min
-// one block per chunk of whole closedness rows (<= 255 entries)
-template <typename R, int MODE>
-__device__ void short_chunk_hard(const SweepArgs& A, const R* __restrict__ rin, R* __restrict__ out, R omega,
-                                 unsigned char* smem, double* red) {
-  R* lam_s = reinterpret_cast<R*>(smem);
-  R* srt_s = lam_s + 256;
-  R* pre_s = srt_s + 256;
-  int32_t* rp_s = reinterpret_cast<int32_t*>(pre_s + 256);
-  int32_t* rb_s = rp_s + 257;
-  uint8_t* neg_s = reinterpret_cast<uint8_t*>(rb_s + 256);
+// One wave per chunk of whole closedness rows (<= 64 entries, one per lane),
+// four chunks per block, no LDS and no barrier until the bound.  Every
+// cross-lane step runs in a wave-uniform loop, so no lane ever reads from an
+// inactive lane:
+//  1. lane e holds entry e (multiplier, sign, word); the first lanes hold the
+//     row starts, and each lane finds its row with a 5-step binary search;
+//  2. rank inside the row's sign group by comparing with the row's lanes;
+//  3. ds_permute moves every value to its sorted position;
+//  4. a segmented inclusive scan gives S(k), the sum of the k smallest of a
+//     group, at the lane of the k-th smallest;
+//  5. each lane evaluates its two constrained minima over k.
+__device__ inline int wave_max_i(int v) {
+  for (int o = 32; o > 0; o >>= 1) v = max(v, __shfl_xor(v, o));
+  return v;
+}
 
-  const int c = blockIdx.x;
-  const int32_t r0 = A.chunk_row[c], r1 = A.chunk_row[c + 1];
-  const int32_t nrow = r1 - r0;
-  const int32_t e0 = A.rrow_ptr[r0];
-  const int32_t ne = A.rrow_ptr[r1] - e0;
-  const int t = threadIdx.x;
-  for (int i = t; i <= nrow; i += blockDim.x) rp_s[i] = A.rrow_ptr[r0 + i] - e0;
-  for (int i = t; i < nrow; i += blockDim.x) rb_s[i] = A.rrow_b[r0 + i];
-  uint32_t w = 0;
-  R lam = R(0);
-  if (t < ne) {
-    w = A.word[e0 + t];
-    lam = cur_lambda<R>(rin, w);
-    lam_s[t] = lam;
-    neg_s[t] = uint8_t(w >> 31);
+template <typename R>
+__device__ inline R permute_to(int dst_lane, R v) {   // push v to lane dst_lane
+  if constexpr (sizeof(R) == 4) {
+    return __int_as_float(__builtin_amdgcn_ds_permute(dst_lane << 2, __float_as_int(v)));
+  } else {
+    const long long bits = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_ds_permute(dst_lane << 2, int(bits & 0xFFFFFFFFll));
+    const int hi = __builtin_amdgcn_ds_permute(dst_lane << 2, int(bits >> 32));
+    return __longlong_as_double((static_cast<long long>(hi) << 32) | (static_cast<long long>(lo) & 0xFFFFFFFFll));
   }
-  __syncthreads();
-  int32_t s = 0, n = 0, b = 0, rank = 0, P = 0;
-  int g = 0;
-  if (t < ne) {
-    int32_t lo = 0, hi = nrow - 1;   // last row whose start <= t
-    while (lo < hi) {
-      int32_t mid = (lo + hi + 1) >> 1;
-      if (rp_s[mid] <= t) lo = mid;
-      else hi = mid - 1;
-    }
-    s = rp_s[lo];
-    n = rp_s[lo + 1] - s;
-    b = rb_s[lo];
-    g = neg_s[t];
-    for (int32_t q = s; q < s + n; ++q) {
-      int gq = neg_s[q];
-      P += gq == 0;
-      if (gq == g) {
-        R lq = lam_s[q];
-        rank += (lq < lam) || (lq == lam && q < t);
-      }
-    }
-    srt_s[s + (g ? P + rank : rank)] = lam;
-  }
-  __syncthreads();
-  const int32_t N = n - P;
-  if (t < ne) {
-    const int32_t base = s + (g ? P : 0);
-    R acc = R(0);
-    for (int32_t q = 0; q <= rank; ++q) acc += srt_s[base + q];
-    pre_s[base + rank] = acc;   // sum of the rank+1 smallest of this sign
-  }
-  __syncthreads();
+}
+
+template <typename R, int MODE>
+__device__ void short_wave_hard(const SweepArgs& A, const R* __restrict__ rin, R* __restrict__ out, R omega,
+                                double* red, int32_t item) {
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int32_t wc = item * 4 + wave;
   double rowpart = 0.0;
-  if (t < ne) {
-    // own group: entries with this entry's sign; the row reads
-    //   sum(own) - sum(other) = bb  with bb = b for +1 entries, -b for -1 entries
+  if (wc < A.n_chunks) {   // uniform across the wave
+    const int4 d = A.chunk_desc[wc];
+    const int32_t r0 = d.x, nrow = d.y, e0 = d.z, ne = d.w;
+    // lane r < nrow: start of row r (relative), lane nrow: ne, others 64
+    int32_t rstart = lane < nrow ? A.rrow_ptr[r0 + lane] - e0 : (lane == nrow ? ne : 64);
+    const int32_t rb = lane < nrow ? A.rrow_b[r0 + lane] : 0;
+    const bool act = lane < ne;
+    const uint32_t w = act ? A.word[e0 + lane] : 0u;
+    const R lam = act ? cur_lambda<R>(rin, w) : R(0);
+    const int g = int(w >> 31);
+    // my row: the last row whose start <= lane (rows have >= 2 entries, so nrow <= 32)
+    int32_t myrow = 0;
+    for (int step = 16; step > 0; step >>= 1) {
+      const int32_t cand = myrow + step;
+      const int32_t sc = __shfl(rstart, cand < 64 ? cand : 63);
+      if (cand < nrow && sc <= lane) myrow = cand;
+    }
+    const int32_t s = __shfl(rstart, myrow);
+    const int32_t n = __shfl(rstart, myrow + 1) - s;
+    const int32_t b = __shfl(rb, myrow);
+    const unsigned long long negm = __ballot(act && g);
+    const unsigned long long rowm = act ? (((n >= 64) ? ~0ull : ((1ull << n) - 1ull)) << s) : 0ull;
+    const int32_t P = __popcll(rowm & ~negm);
+    const int32_t N = n - P;
+    // rank of this entry in its sign group (ties broken by lane)
+    const int nmax = wave_max_i(act ? n : 0);
+    int32_t rank = 0;
+    for (int q = 0; q < nmax; ++q) {
+      const int src = s + q;
+      const R lq = __shfl(lam, src < 64 ? src : 63);
+      const int gq = int((negm >> (src & 63)) & 1ull);
+      if (act && q < n && gq == g) rank += (lq < lam) || (lq == lam && src < lane);
+    }
+    // sorted position: positive group first, then negative group
+    const int dst = act ? s + (g ? P + rank : rank) : lane;
+    const R srt = permute_to<R>(dst, lam);
+    // segmented inclusive scan over the sorted groups: lane j of row [s, s+n)
+    // belongs to the +1 group if j - s < P
+    const int32_t seg = act ? s + (lane - s < P ? 0 : P) : lane;
+    R pre = srt;
+    for (int off = 1; off < 64; off <<= 1) {
+      const R t = __shfl(pre, lane >= off ? lane - off : 0);
+      if (lane - off >= seg) pre += t;
+    }
+    // pre at lane (group start + k - 1) = S_group(k)
     const int32_t own = g ? N : P, oth = g ? P : N, bb = g ? -b : b;
     const int32_t obase = s + (g ? P : 0), tbase = s + (g ? 0 : P);
     const int32_t klo = bb > 0 ? bb : 0;
     const int32_t khi = own < oth + bb ? own : oth + bb;
+    const int kmax = wave_max_i(act ? khi - klo + 1 : 0);
     R m1 = rinf<R>(), m0 = rinf<R>(), rmin = rinf<R>();
-    for (int32_t k = klo; k <= khi; ++k) {
-      const int32_t ko = k - bb;
-      R So = k == 0 ? R(0) : pre_s[obase + k - 1];
-      R St = ko == 0 ? R(0) : pre_s[tbase + ko - 1];
-      R f = So + St;
+    for (int kk = 0; kk < kmax; ++kk) {
+      const int32_t k = klo + kk, ko = k - bb;
+      const int io = obase + k - 1, it = tbase + ko - 1, ix = k >= rank + 1 ? obase + k : obase + k - 2;
+      const R So = __shfl(pre, io >= 0 && io < 64 ? io : 0);
+      const R St = __shfl(pre, it >= 0 && it < 64 ? it : 0);
+      const R Sx = __shfl(pre, ix >= 0 && ix < 64 ? ix : 0);
+      if (!act || k > khi) continue;
+      const R so = k == 0 ? R(0) : So;
+      const R st = ko == 0 ? R(0) : St;
+      const R f = so + st;
       rmin = f < rmin ? f : rmin;
       if (k >= rank + 1) {
         // the k smallest of the own group include this entry
         m1 = f < m1 ? f : m1;
         if (k <= own - 1) {
-          R Sn = pre_s[obase + k];   // k+1 smallest, minus this entry
-          R v = (Sn - lam) + St;
+          const R v = (Sx - lam) + st;   // k+1 smallest, minus this entry
           m0 = v < m0 ? v : m0;
         }
       } else {
         m0 = f < m0 ? f : m0;
         if (k >= 1) {
-          R Sp = k == 1 ? R(0) : pre_s[obase + k - 2];
-          R v = (lam + Sp) + St;
+          const R sp = k == 1 ? R(0) : Sx;   // k-1 smallest
+          const R v = (lam + sp) + st;
           m1 = v < m1 ? v : m1;
         }
       }
     }
-    const R M = m1 - m0;
-    if (MODE == MODE_UPDATE) write_out<R>(out, w, lam - omega * M);
-    if (MODE == MODE_EVAL) write_out<R>(out, w, M);
-    if (t == s) rowpart = double(rmin);
+    if (act) {
+      const R M = m1 - m0;
+      if (MODE == MODE_UPDATE) write_out<R>(out, w, lam - omega * M);
+      if (MODE == MODE_EVAL) write_out<R>(out, w, M);
+      if (lane == s) rowpart = double(rmin);
+    }
   }
   double part = block_sum(rowpart, red);
-  store_partial(part, A.partial);
+  store_partial(part, A.partial, item);
 }
 
 // ---------------------------------------------------------------- short rows, soft min
@@ -245,12 +267,12 @@ __device__ void short_chunk_hard(const SweepArgs& A, const R* __restrict__ rin, 
 // B_l(sigma) = smin(B_{l+1}(sigma), B_{l+1}(sigma + a_l) + lam_l)
 template <typename R, int MODE>
 __device__ void short_rows_soft(const SweepArgs& A, const R* __restrict__ rin, R* __restrict__ out, R omega,
-                                R T, unsigned char* smem, double* red) {
+                                R T, unsigned char* smem, double* red, int32_t item) {
   const int seg = threadIdx.x >> 5, lane = threadIdx.x & 31;
   R* Ftab = reinterpret_cast<R*>(smem) + seg * (SOFT_MAX_ROW * 32);
   R* lamL = reinterpret_cast<R*>(smem) + 8 * SOFT_MAX_ROW * 32 + seg * 32;
   int8_t* aL = reinterpret_cast<int8_t*>(reinterpret_cast<R*>(smem) + 8 * SOFT_MAX_ROW * 32 + 8 * 32) + seg * 32;
-  const int32_t j = int32_t(blockIdx.x) * 8 + seg;
+  const int32_t j = item * 8 + seg;
   const bool act = j < A.n_short;
   int32_t s = 0, n = 0, b = 0;
   uint32_t w = 0;
@@ -312,7 +334,7 @@ __device__ void short_rows_soft(const SweepArgs& A, const R* __restrict__ rin, R
     if (lane == 0) rowpart = double(rowv);
   }
   double part = block_sum(rowpart, red);
-  store_partial(part, A.partial);
+  store_partial(part, A.partial, item);
 }
 
 // ---------------------------------------------------------------- long rows (exactly one)
@@ -353,73 +375,98 @@ __device__ inline MinState<R> ms_shfl_xor(MinState<R> v, int off) {
   return o;
 }
 
+// one wave per projection row, four rows per block; each lane keeps up to
+// LONG_REG of its row's multipliers in registers between the two passes
+constexpr int LONG_ROWS_PER_BLOCK = 4;
+constexpr int LONG_REG = 16;
+
 template <typename R, bool SOFT, int MODE>
-__device__ void long_row(const SweepArgs& A, const R* __restrict__ rin, R* __restrict__ out, R omega, R T,
-                         unsigned char* smem, double* red) {
-  R* lbuf = reinterpret_cast<R*>(smem);
-  MinState<R>* wred = reinterpret_cast<MinState<R>*>(lbuf + LONG_CAP);
-  const int32_t j = A.n_short + (int32_t(blockIdx.x) - A.n_short_blocks);
-  const int32_t s = A.rrow_ptr[j], n = A.rrow_ptr[j + 1] - s;
-  MinState<R> st;
-  st.m = rinf<R>();
-  st.m2 = rinf<R>();
-  st.s = R(0);
-  st.a = INT32_MAX;
-  for (int32_t i = threadIdx.x; i < n; i += blockDim.x) {
-    R lam = cur_lambda<R>(rin, A.word[s + i]);
-    if (i < LONG_CAP) lbuf[i] = lam;
-    MinState<R> one;
-    one.m = lam;
-    one.m2 = rinf<R>();
-    one.s = R(0);
-    one.a = i;
-    st = ms_combine<R, SOFT>(st, one, T);
-  }
-  for (int off = 32; off > 0; off >>= 1) st = ms_combine<R, SOFT>(st, ms_shfl_xor<R, SOFT>(st, off), T);
+__device__ void long_rows(const SweepArgs& A, const R* __restrict__ rin, R* __restrict__ out, R omega, R T,
+                          double* red, int32_t item) {
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  if (lane == 0) wred[wave] = st;
-  __syncthreads();
-  st = wred[0];
-  for (int wv = 1; wv < int(blockDim.x >> 6); ++wv) st = ms_combine<R, SOFT>(st, wred[wv], T);
-  R rowv = st.m;
-  R tot = R(0);
-  if (SOFT) {
-    tot = (st.m2 == rinf<R>()) ? R(0) : st.s * r_exp<R>(-(st.m2 - st.m) / T);
-    rowv = st.m - T * r_log<R>(R(1) + tot);
-  }
-  if (MODE != MODE_BOUND) {
-    for (int32_t i = threadIdx.x; i < n; i += blockDim.x) {
-      const uint32_t w = A.word[s + i];
-      const R lam = i < LONG_CAP ? lbuf[i] : cur_lambda<R>(rin, w);
-      R M, mu = R(0);
-      if (!SOFT) {
-        M = lam - (i == st.a ? st.m2 : st.m);
-      } else {
-        R others;
-        if (i == st.a) {
-          others = st.m2 - T * r_log<R>(st.s);
-        } else {
-          R e = r_exp<R>(-(lam - st.m) / T);
-          others = st.m - T * r_log<R>((R(1) + tot) - e);
-        }
-        M = lam - others;
-        mu = r_exp<R>(-(lam - rowv) / T);
-      }
-      if (MODE == MODE_UPDATE) write_out<R>(out, w, lam - omega * M);
-      if (MODE == MODE_EVAL) write_out<R>(out, w, SOFT ? mu : M);
+  const int32_t j = A.n_short + (item - A.n_short_blocks) * LONG_ROWS_PER_BLOCK + wave;
+  double rowpart = 0.0;
+  if (j < A.n_rows) {
+    const int32_t s = A.rrow_ptr[j], n = A.rrow_ptr[j + 1] - s;
+    MinState<R> st;
+    st.m = rinf<R>();
+    st.m2 = rinf<R>();
+    st.s = R(0);
+    st.a = INT32_MAX;
+    uint32_t wv[LONG_REG];
+    R lv[LONG_REG];
+#pragma unroll
+    for (int u = 0; u < LONG_REG; ++u) {
+      const int32_t i = lane + 64 * u;
+      wv[u] = i < n ? A.word[s + i] : 0u;
     }
+#pragma unroll
+    for (int u = 0; u < LONG_REG; ++u) {
+      const int32_t i = lane + 64 * u;
+      lv[u] = R(0);
+      if (i < n) {
+        lv[u] = cur_lambda<R>(rin, wv[u]);
+        MinState<R> one;
+        one.m = lv[u];
+        one.m2 = rinf<R>();
+        one.s = R(0);
+        one.a = i;
+        st = ms_combine<R, SOFT>(st, one, T);
+      }
+    }
+    for (int32_t i = lane + 64 * LONG_REG; i < n; i += 64) {   // rows longer than 64 * LONG_REG
+      MinState<R> one;
+      one.m = cur_lambda<R>(rin, A.word[s + i]);
+      one.m2 = rinf<R>();
+      one.s = R(0);
+      one.a = i;
+      st = ms_combine<R, SOFT>(st, one, T);
+    }
+    for (int off = 32; off > 0; off >>= 1) st = ms_combine<R, SOFT>(st, ms_shfl_xor<R, SOFT>(st, off), T);
+    R rowv = st.m;
+    R tot = R(0);
+    if (SOFT) {
+      tot = (st.m2 == rinf<R>()) ? R(0) : st.s * r_exp<R>(-(st.m2 - st.m) / T);
+      rowv = st.m - T * r_log<R>(R(1) + tot);
+    }
+    if (MODE != MODE_BOUND) {
+      auto finish = [&](int32_t i, uint32_t w, R lam) {
+        R M, mu = R(0);
+        if (!SOFT) {
+          M = lam - (i == st.a ? st.m2 : st.m);
+        } else {
+          R others;
+          if (i == st.a) {
+            others = st.m2 - T * r_log<R>(st.s);
+          } else {
+            R e = r_exp<R>(-(lam - st.m) / T);
+            others = st.m - T * r_log<R>((R(1) + tot) - e);
+          }
+          M = lam - others;
+          mu = r_exp<R>(-(lam - rowv) / T);
+        }
+        if (MODE == MODE_UPDATE) write_out<R>(out, w, lam - omega * M);
+        if (MODE == MODE_EVAL) write_out<R>(out, w, SOFT ? mu : M);
+      };
+#pragma unroll
+      for (int u = 0; u < LONG_REG; ++u) {
+        const int32_t i = lane + 64 * u;
+        if (i < n) finish(i, wv[u], lv[u]);
+      }
+      for (int32_t i = lane + 64 * LONG_REG; i < n; i += 64) {
+        const uint32_t w = A.word[s + i];
+        finish(i, w, cur_lambda<R>(rin, w));
+      }
+    }
+    if (lane == 0) rowpart = double(rowv);
   }
-  double part = threadIdx.x == 0 ? double(rowv) : 0.0;
-  part = block_sum(part, red);
-  store_partial(part, A.partial);
+  double part = block_sum(rowpart, red);
+  store_partial(part, A.partial, item);
 }
 
 template <typename R, bool SOFT>
 constexpr size_t smem_bytes() {
-  size_t shortb = SOFT ? (8 * SOFT_MAX_ROW * 32 + 8 * 32) * sizeof(R) + 8 * 32
-                       : 3 * 256 * sizeof(R) + 257 * 4 + 256 * 4 + 256;
-  size_t longb = LONG_CAP * sizeof(R) + 4 * sizeof(MinState<R>);
-  return shortb > longb ? shortb : longb;
+  return SOFT ? (8 * SOFT_MAX_ROW * 32 + 8 * 32) * sizeof(R) + 8 * 32 : 16;
 }
 
 template <typename R, bool SOFT, int MODE>
@@ -428,11 +475,27 @@ __global__ __launch_bounds__(256) void k_sweep(SweepArgs A, const R* __restrict_
   __shared__ __align__(16) unsigned char smem[smem_bytes<R, SOFT>()];
   __shared__ double red[256];
   if (blockIdx.x == 0 && A.prev_partial) reduce_partials(A.prev_partial, A.prev_n, A.prev_offset, A.prev_out, red);
-  if (int32_t(blockIdx.x) < A.n_short_blocks) {
-    if (SOFT) short_rows_soft<R, MODE>(A, rin, out, omega, T, smem, red);
-    else short_chunk_hard<R, MODE>(A, rin, out, omega, smem, red);
+  // Workgroups are dealt to the 8 XCDs round-robin (block b runs on XCD b % 8).
+  // Each XCD takes a contiguous range of short-row chunks, so rows that share
+  // variables share one L2, and every eighth projection-row block; the heavier
+  // projection-row blocks come first on each XCD.
+  const int32_t x = int32_t(blockIdx.x % 8u), k = int32_t(blockIdx.x / 8u);
+  const int32_t n_long_blocks = A.n_items - A.n_short_blocks;
+  const int32_t lx = n_long_blocks > x ? (n_long_blocks - x + 7) / 8 : 0;
+  int32_t item;
+  if (k < lx) {
+    item = A.n_short_blocks + k * 8 + x;
   } else {
-    long_row<R, SOFT, MODE>(A, rin, out, omega, T, smem, red);
+    const int32_t pc = (A.n_short_blocks + 7) / 8;
+    const int32_t c = x * pc + (k - lx);
+    if (k - lx >= pc || c >= A.n_short_blocks) return;
+    item = c;
+  }
+  if (item < A.n_short_blocks) {
+    if (SOFT) short_rows_soft<R, MODE>(A, rin, out, omega, T, smem, red, item);
+    else short_wave_hard<R, MODE>(A, rin, out, omega, red, item);
+  } else {
+    long_rows<R, SOFT, MODE>(A, rin, out, omega, T, red, item);
   }
 }
 
@@ -519,11 +582,13 @@ dm_status dual_sweep(dm_ctx* ctx, int mode, bool soft, const unsigned char* rin,
   A.word = ctx->rent_word.p;
   A.rrow_ptr = ctx->rrow_ptr.p;
   A.rrow_b = ctx->rrow_b.p;
-  A.chunk_row = ctx->chunk_row.p;
-  A.n_short_blocks = soft ? int32_t((ctx->n_short + 7) / 8) : ctx->n_chunks;
+  A.chunk_desc = ctx->chunk_desc.p;
+  A.n_chunks = ctx->n_chunks;
+  A.n_short_blocks = soft ? int32_t((ctx->n_short + 7) / 8) : int32_t((ctx->n_chunks + 3) / 4);
+  const int64_t n_long_blocks = (ctx->n_rows - ctx->n_short + LONG_ROWS_PER_BLOCK - 1) / LONG_ROWS_PER_BLOCK;
   A.n_short = int32_t(ctx->n_short);
   A.n_rows = int32_t(ctx->n_rows);
-  const int64_t nblocks = int64_t(A.n_short_blocks) + (ctx->n_rows - ctx->n_short);
+  const int64_t nblocks = int64_t(A.n_short_blocks) + n_long_blocks;
   if (nblocks == 0) {
     DM_TRY(dual_flush(ctx));
     if (bound_out) k_write_offset<<<1, 1, 0, ctx->stream>>>(bound_out, ctx->offset);
@@ -531,7 +596,7 @@ dm_status dual_sweep(dm_ctx* ctx, int mode, bool soft, const unsigned char* rin,
     return DM_OK;
   }
   // two halves of the partial buffer alternate between consecutive launches
-  const int64_t cap = std::max<int64_t>(ctx->n_chunks, (ctx->n_short + 7) / 8) + (ctx->n_rows - ctx->n_short);
+  const int64_t cap = std::max<int64_t>(ctx->n_chunks, (ctx->n_short + 7) / 8) + n_long_blocks;
   if (ctx->partial.n < size_t(2 * cap)) {
     DM_TRY(dual_flush(ctx));
     DM_ALLOC(ctx, ctx->partial, size_t(2 * cap));
@@ -544,7 +609,9 @@ dm_status dual_sweep(dm_ctx* ctx, int mode, bool soft, const unsigned char* rin,
   A.prev_out = ctx->pend_out;
   const R* ri = reinterpret_cast<const R*>(rin);
   R* ro = reinterpret_cast<R*>(out);
-  const unsigned grid = unsigned(nblocks);
+  A.n_items = int32_t(nblocks);
+  // 8 XCDs x (projection-row blocks per XCD + chunks per XCD), see k_sweep
+  const unsigned grid = unsigned(8 * ((n_long_blocks + 7) / 8 + (A.n_short_blocks + 7) / 8));
   hipEvent_t ev_end = nullptr;
   if (ctx->timing) {
     while (ctx->ev_pool.size() < ctx->ev_used + 2) {

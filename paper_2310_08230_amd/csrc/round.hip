@@ -86,6 +86,20 @@ __global__ void k_violations(const int32_t* row_ptr, const int32_t* ent_var, con
   if (s != row_b[j]) atomicAdd(reinterpret_cast<unsigned long long*>(count), 1ull);
 }
 
+// projection rows (all +1, right-hand side 1): one block per row
+__global__ __launch_bounds__(256) void k_violations_proj(const int32_t* row_ptr, const int32_t* ent_var,
+                                                         int64_t nc, const uint8_t* x, int64_t* count) {
+  __shared__ int sh[4];
+  const int64_t j = nc + blockIdx.x;
+  int c = 0;
+  for (int32_t i = row_ptr[j] + threadIdx.x; i < row_ptr[j + 1]; i += blockDim.x) c += x[ent_var[i]] ? 1 : 0;
+  for (int o = 32; o > 0; o >>= 1) c += __shfl_xor(c, o);
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = c;
+  __syncthreads();
+  if (threadIdx.x == 0 && sh[0] + sh[1] + sh[2] + sh[3] != 1)
+    atomicAdd(reinterpret_cast<unsigned long long*>(count), 1ull);
+}
+
 __global__ __launch_bounds__(1024) void k_primal_obj(const double* c, const uint8_t* x, int64_t nP, double* out) {
   __shared__ double red[1024];
   double s = 0.0;
@@ -118,8 +132,12 @@ __global__ void k_perturb(const int8_t* pref, int64_t nfree, double delta, uint6
 dm_status count_violations(dm_ctx* ctx, const uint8_t* x, int64_t* out) {
   DM_ALLOC(ctx, ctx->icount, 4);
   DM_HIP(ctx, hipMemsetAsync(ctx->icount.p + 1, 0, sizeof(int64_t), ctx->stream));
-  k_violations<<<grid_for(ctx->n_rows_full, 256), 256, 0, ctx->stream>>>(
-      ctx->row_ptr.p, ctx->ent_var.p, ctx->ent_coef.p, ctx->row_b.p, ctx->n_rows_full, x, ctx->icount.p + 1);
+  const int64_t nc = ctx->n_closed_full;
+  if (nc > 0)
+    k_violations<<<grid_for(nc, 256), 256, 0, ctx->stream>>>(ctx->row_ptr.p, ctx->ent_var.p, ctx->ent_coef.p,
+                                                             ctx->row_b.p, nc, x, ctx->icount.p + 1);
+  k_violations_proj<<<unsigned(ctx->n_rows_full - nc), 256, 0, ctx->stream>>>(ctx->row_ptr.p, ctx->ent_var.p, nc,
+                                                                               x, ctx->icount.p + 1);
   DM_LAUNCH_CHECK(ctx);
   DM_HIP(ctx, hipMemcpyAsync(out, ctx->icount.p + 1, sizeof(int64_t), hipMemcpyDeviceToHost, ctx->stream));
   DM_HIP(ctx, hipStreamSynchronize(ctx->stream));

@@ -373,6 +373,110 @@ __global__ void k_reduced_fill(const int32_t* row_ptr, const int32_t* ent_var, c
   }
 }
 
+// ---- projection rows (all coefficients +1, right-hand side 1, hundreds to
+// thousands of entries): one 256-thread block per row
+__device__ inline int block_sum_i(int v, int* sh) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
+  __syncthreads();
+  return sh[0] + sh[1] + sh[2] + sh[3];
+}
+
+// exclusive prefix of a 0/1 flag over the block (thread order), and the total
+__device__ inline int block_excl_flag(bool f, int* sh, int* total) {
+  const unsigned long long m = __ballot(f);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int in_wave = __popcll(m & ((1ull << lane) - 1ull));
+  __syncthreads();
+  if (lane == 0) sh[wave] = __popcll(m);
+  __syncthreads();
+  int before = 0;
+  for (int w = 0; w < wave; ++w) before += sh[w];
+  *total = sh[0] + sh[1] + sh[2] + sh[3];
+  return before + in_wave;
+}
+
+__global__ __launch_bounds__(256) void k_presolve_proj(const int32_t* row_ptr, const int32_t* ent_var, int64_t nc,
+                                                       const int8_t* state, uint32_t* force, int* flags) {
+  __shared__ int sh[4];
+  const int64_t j = nc + blockIdx.x;
+  const int32_t s = row_ptr[j], e = row_ptr[j + 1];
+  int c1 = 0, cf = 0;
+  for (int32_t i = s + threadIdx.x; i < e; i += blockDim.x) {
+    int8_t st = state[ent_var[i]];
+    c1 += st == 1;
+    cf += st < 0;
+  }
+  const int ones = block_sum_i(c1, sh);
+  const int P = block_sum_i(cf, sh);
+  const int r = 1 - ones;
+  if (r < 0 || r > P) {
+    if (threadIdx.x == 0) atomicOr(&flags[1], 1);
+    return;
+  }
+  // r == 0: every free entry must be 0; r == 1 with one free entry: it is 1
+  if (r == 0 || P == 1)
+    for (int32_t i = s + threadIdx.x; i < e; i += blockDim.x) {
+      int32_t v = ent_var[i];
+      if (state[v] < 0) atomicOr(&force[v], r == 0 ? 1u : 2u);
+    }
+}
+
+__global__ __launch_bounds__(256) void k_row_residual_proj(const int32_t* row_ptr, const int32_t* ent_var,
+                                                           int64_t nc, const int8_t* state, int32_t* nfree,
+                                                           int32_t* resid, uint8_t* keep, int* flags) {
+  __shared__ int sh[4];
+  const int64_t j = nc + blockIdx.x;
+  int c1 = 0, cf = 0;
+  for (int32_t i = row_ptr[j] + threadIdx.x; i < row_ptr[j + 1]; i += blockDim.x) {
+    int8_t st = state[ent_var[i]];
+    c1 += st == 1;
+    cf += st < 0;
+  }
+  const int ones = block_sum_i(c1, sh);
+  const int c = block_sum_i(cf, sh);
+  if (threadIdx.x == 0) {
+    if (c == 0 && 1 - ones != 0) atomicOr(&flags[1], 1);
+    nfree[j] = c;
+    resid[j] = 1 - ones;
+    keep[j] = c > 0 ? 1 : 0;
+  }
+}
+
+__global__ __launch_bounds__(256) void k_reduced_fill_proj(
+    const int32_t* row_ptr, const int32_t* ent_var, const uint8_t* ent_slot, int64_t nc, const int8_t* state,
+    const int32_t* var_red, const int32_t* code, const uint8_t* keep, const int32_t* new_id,
+    const int32_t* cnt_excl, const int32_t* resid, int32_t* rrow_orig, int32_t* rrow_ptr, int32_t* rrow_b,
+    int32_t* rent_var, int8_t* rent_coef, uint32_t* rent_word) {
+  __shared__ int sh[4];
+  const int64_t j = nc + blockIdx.x;
+  if (!keep[j]) return;   // uniform over the block
+  const int32_t nr = new_id[j];
+  if (threadIdx.x == 0) {
+    rrow_orig[nr] = int32_t(j);
+    rrow_b[nr] = resid[j];
+    rrow_ptr[nr] = cnt_excl[j];
+  }
+  int32_t pos = cnt_excl[j];
+  for (int32_t t0 = row_ptr[j]; t0 < row_ptr[j + 1]; t0 += blockDim.x) {
+    const int32_t i = t0 + threadIdx.x;
+    const bool in = i < row_ptr[j + 1];
+    const int32_t v = in ? ent_var[i] : 0;
+    const bool f = in && state[v] < 0;
+    int total = 0;
+    const int off = block_excl_flag(f, sh, &total);
+    if (f) {
+      const int32_t rv = var_red[v];
+      const bool deg5 = code[4 * int64_t(v)] == 0 && (code[4 * int64_t(v) + 2] >> 3) == 0;
+      rent_var[pos + off] = rv;
+      rent_coef[pos + off] = 1;
+      rent_word[pos + off] = (deg5 ? W_DEG5 : 0u) | (uint32_t(ent_slot[i]) << W_SLOT_SHIFT) | uint32_t(rv);
+    }
+    pos += total;
+  }
+}
+
 __global__ void k_var_deg(const int32_t* free_var, const int32_t* code, int64_t n, uint8_t* deg) {
   int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (i >= n) return;
@@ -395,21 +499,44 @@ __global__ void k_row_stats(const int32_t* rrow_ptr, const int32_t* rrow_b, cons
   }
 }
 
-__global__ void k_chunks(const int32_t* rrow_ptr, int64_t n_short, int32_t n_chunks, int32_t* chunk_row) {
-  int32_t c = int32_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (c > n_chunks) return;
-  if (c == n_chunks) {
-    chunk_row[c] = int32_t(n_short);
+// Short rows are packed greedily, in row order, into wave chunks of at most
+// 64 entries (one entry per lane, whole rows only).  The greedy walk runs in
+// parallel over segments of PACK_SEG entries: segment j holds the rows whose
+// first entry lies in [j*PACK_SEG, (j+1)*PACK_SEG).
+constexpr int PACK_SEG = 4096;
+
+__global__ void k_seg_rows(const int32_t* rrow_ptr, int64_t n_short, int32_t n_seg, int32_t* seg_row) {
+  int32_t j = int32_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (j > n_seg) return;
+  if (j == n_seg) {
+    seg_row[j] = int32_t(n_short);
     return;
   }
-  int64_t target = int64_t(c) * CHUNK_SPAN;
+  int64_t target = int64_t(j) * PACK_SEG;
   int64_t lo = 0, hi = n_short;
   while (lo < hi) {
     int64_t mid = (lo + hi) >> 1;
     if (rrow_ptr[mid] < target) lo = mid + 1;
     else hi = mid;
   }
-  chunk_row[c] = int32_t(lo);
+  seg_row[j] = int32_t(lo);
+}
+
+// fill == false: count the wave chunks of each segment; fill == true: write
+// their (first row, rows, first entry, entries) at the scanned offsets
+__global__ void k_pack(const int32_t* seg_row, const int32_t* rrow_ptr, int32_t n_seg, int32_t* count,
+                       const int32_t* offset, int4* desc, int fill) {
+  int32_t j = int32_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (j >= n_seg) return;
+  int32_t r = seg_row[j], r1 = seg_row[j + 1];
+  int32_t c = 0, o = fill ? offset[j] : 0;
+  while (r < r1) {
+    int32_t r0 = r, e0 = rrow_ptr[r];
+    while (r < r1 && rrow_ptr[r + 1] - e0 <= 64) ++r;
+    if (fill) desc[o + c] = make_int4(r0, r - r0, e0, rrow_ptr[r] - e0);
+    ++c;
+  }
+  if (!fill) count[j] = c;
 }
 
 }  // namespace
@@ -572,8 +699,11 @@ dm_status space_build(dm_ctx* ctx, const int32_t* cand_xy, const int32_t* cand_y
   int rounds = 0;
   for (;;) {
     DM_HIP(ctx, hipMemsetAsync(err.p, 0, 2 * sizeof(int), st));
-    k_presolve_rows<<<grid_for(nrows, 128), 128, 0, st>>>(ctx->row_ptr.p, ctx->ent_var.p, ctx->ent_coef.p,
-                                                          ctx->row_b.p, nrows, ctx->state.p, force.p, err.p);
+    if (nc > 0)
+      k_presolve_rows<<<grid_for(nc, 128), 128, 0, st>>>(ctx->row_ptr.p, ctx->ent_var.p, ctx->ent_coef.p,
+                                                         ctx->row_b.p, nc, ctx->state.p, force.p, err.p);
+    k_presolve_proj<<<unsigned(nrows - nc), 256, 0, st>>>(ctx->row_ptr.p, ctx->ent_var.p, nc, ctx->state.p,
+                                                          force.p, err.p);
     k_presolve_vars<<<grid_for(nP, 256), 256, 0, st>>>(nP, ctx->state.p, force.p, err.p);
     DM_LAUNCH_CHECK(ctx);
     int flags[2];
@@ -613,9 +743,12 @@ dm_status space_build(dm_ctx* ctx, const int32_t* cand_xy, const int32_t* cand_y
   DM_ALLOC(ctx, new_id, size_t(nrows) + 1);
   DM_ALLOC(ctx, cnt_excl, size_t(nrows) + 1);
   DM_HIP(ctx, hipMemsetAsync(err.p, 0, 4 * sizeof(int), st));
-  k_row_residual<<<grid_for(nrows, 128), 128, 0, st>>>(ctx->row_ptr.p, ctx->ent_var.p, ctx->ent_coef.p,
-                                                       ctx->row_b.p, nrows, ctx->state.p, nfr.p, resid.p,
-                                                       keep.p, err.p);
+  if (nc > 0)
+    k_row_residual<<<grid_for(nc, 128), 128, 0, st>>>(ctx->row_ptr.p, ctx->ent_var.p, ctx->ent_coef.p,
+                                                      ctx->row_b.p, nc, ctx->state.p, nfr.p, resid.p, keep.p,
+                                                      err.p);
+  k_row_residual_proj<<<unsigned(nrows - nc), 256, 0, st>>>(ctx->row_ptr.p, ctx->ent_var.p, nc, ctx->state.p,
+                                                            nfr.p, resid.p, keep.p, err.p);
   DM_LAUNCH_CHECK(ctx);
   DM_TRY(scan_u8(ctx, keep.p, new_id.p, size_t(nrows)));
   DM_TRY(scan_i32(ctx, nfr.p, cnt_excl.p, size_t(nrows)));
@@ -634,10 +767,15 @@ dm_status space_build(dm_ctx* ctx, const int32_t* cand_xy, const int32_t* cand_y
   DM_ALLOC(ctx, ctx->rent_var, size_t(std::max(rnnz, 1)));
   DM_ALLOC(ctx, ctx->rent_coef, size_t(std::max(rnnz, 1)));
   DM_ALLOC(ctx, ctx->rent_word, size_t(std::max(rnnz, 1)));
-  k_reduced_fill<<<grid_for(nrows, 128), 128, 0, st>>>(
-      ctx->row_ptr.p, ctx->ent_var.p, ctx->ent_coef.p, ctx->ent_slot.p, nrows, ctx->state.p, ctx->var_red.p,
-      ctx->code.p, ctx->free_var.p, keep.p, new_id.p, cnt_excl.p, resid.p, ctx->rrow_orig.p, ctx->rrow_ptr.p,
-      ctx->rrow_b.p, ctx->rent_var.p, ctx->rent_coef.p, ctx->rent_word.p);
+  if (nc > 0)
+    k_reduced_fill<<<grid_for(nc, 128), 128, 0, st>>>(
+        ctx->row_ptr.p, ctx->ent_var.p, ctx->ent_coef.p, ctx->ent_slot.p, nc, ctx->state.p, ctx->var_red.p,
+        ctx->code.p, ctx->free_var.p, keep.p, new_id.p, cnt_excl.p, resid.p, ctx->rrow_orig.p, ctx->rrow_ptr.p,
+        ctx->rrow_b.p, ctx->rent_var.p, ctx->rent_coef.p, ctx->rent_word.p);
+  k_reduced_fill_proj<<<unsigned(nrows - nc), 256, 0, st>>>(
+      ctx->row_ptr.p, ctx->ent_var.p, ctx->ent_slot.p, nc, ctx->state.p, ctx->var_red.p, ctx->code.p, keep.p,
+      new_id.p, cnt_excl.p, resid.p, ctx->rrow_orig.p, ctx->rrow_ptr.p, ctx->rrow_b.p, ctx->rent_var.p,
+      ctx->rent_coef.p, ctx->rent_word.p);
   k_set_i32<<<1, 1, 0, st>>>(ctx->rrow_ptr.p, nr, rnnz);
   DM_LAUNCH_CHECK(ctx);
   DM_ALLOC(ctx, ctx->var_deg, size_t(std::max(nfree, 1)));
@@ -659,10 +797,23 @@ dm_status space_build(dm_ctx* ctx, const int32_t* cand_xy, const int32_t* cand_y
   int32_t nnz_short = 0;
   DM_TRY(read_i32(ctx, ctx->rrow_ptr.p + nshort, &nnz_short));
   ctx->nnz_short = nnz_short;
-  ctx->n_chunks = int32_t((int64_t(nnz_short) + CHUNK_SPAN - 1) / CHUNK_SPAN);
-  DM_ALLOC(ctx, ctx->chunk_row, size_t(ctx->n_chunks) + 1);
-  k_chunks<<<grid_for(ctx->n_chunks + 1, 256), 256, 0, st>>>(ctx->rrow_ptr.p, nshort, ctx->n_chunks,
-                                                               ctx->chunk_row.p);
+  const int32_t n_seg = int32_t((int64_t(nnz_short) + PACK_SEG - 1) / PACK_SEG);
+  DArr<int32_t> seg_row, seg_cnt, seg_off;
+  DM_ALLOC(ctx, seg_row, size_t(n_seg) + 1);
+  DM_ALLOC(ctx, seg_cnt, size_t(std::max(n_seg, 1)));
+  DM_ALLOC(ctx, seg_off, size_t(n_seg) + 1);
+  k_seg_rows<<<grid_for(n_seg + 1, 256), 256, 0, st>>>(ctx->rrow_ptr.p, nshort, n_seg, seg_row.p);
+  if (n_seg > 0)
+    k_pack<<<grid_for(n_seg, 64), 64, 0, st>>>(seg_row.p, ctx->rrow_ptr.p, n_seg, seg_cnt.p, nullptr, nullptr, 0);
+  DM_LAUNCH_CHECK(ctx);
+  DM_TRY(scan_i32(ctx, seg_cnt.p, seg_off.p, size_t(n_seg)));
+  int32_t n_chunks = 0;
+  DM_TRY(read_i32(ctx, seg_off.p + n_seg, &n_chunks));
+  ctx->n_chunks = n_chunks;
+  DM_ALLOC(ctx, ctx->chunk_desc, size_t(std::max(n_chunks, 1)));
+  if (n_seg > 0)
+    k_pack<<<grid_for(n_seg, 64), 64, 0, st>>>(seg_row.p, ctx->rrow_ptr.p, n_seg, nullptr, seg_off.p,
+                                               ctx->chunk_desc.p, 1);
   DM_LAUNCH_CHECK(ctx);
   DM_HIP(ctx, hipStreamSynchronize(st));
   return DM_OK;
