@@ -11,7 +11,9 @@
 //   * Sec. 3.2, Eq. (D)   Lagrangean decomposition, one subproblem per row;
 //   * Appendix "Coarse-to-fine solving strategy", min-marginal equation;
 //   * Sec. 4.2, Eq. (cost) costs from mixed areas and feature distances;
-//   * Sec. 5 "Metrics"    primal-dual gap.
+//   * Sec. 5 "Metrics"    primal-dual gap;
+//   * Sec. 4.1, Alg. 1 and Appendix "Quasi-Newton Updates": L-BFGS steps
+//     interleaved with MMA (two-loop direction, FindStepSize, history).
 // Where the paper is silent (product-space conventions it defers to earlier
 // work, the MMA schedule it defers to FastDOG, the rounding heuristic, the
 // smoothed dual) the reading taken is written next to the code.
@@ -976,6 +978,204 @@ int or_smoothed_grad(void* h, const double* lam, double T, const float* DX, cons
       }
     }
   return OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+// ---------------------------------------------------------------------------
+// Quasi-Newton powered MMA (Sec. 4.1, Alg. 1; Appendix "Quasi-Newton updates":
+// the inverse-Hessian update, the L-BFGS direction and FindStepSize).
+// One iteration: subgradient g (every row's minimising assignment), direction
+// d^ = H g by the two-loop recursion, dual-feasible projection of d^, step size
+// search, step, one MMA (Jacobi) iteration, history update.  Readings:
+//   * L-BFGS is applied to the convex function -E, so the stored pairs are
+//     s = lambda_{k+1} - lambda_k and y = g(lambda_k) - g(lambda_{k+1}) and
+//     the curvature test s^T y >= eps keeps only pairs of positive curvature;
+//   * with an empty history H = I; otherwise H0 = (s^T y / y^T y) I from the
+//     newest pair, then the two-loop recursion;
+//   * FindStepSize compares against E(lambda) (the objective before the step,
+//     as the prose describes); Delta_min = 1e-6 (E(lambda^1) - E(lambda^0)),
+//     +inf during the first invocation; the step is taken only if the best
+//     trial improves on E(lambda);
+//   * every row's minimiser takes ties to the lowest index (exactly-one rows)
+//     or, for +-1 rows, the smallest count k of +1 entries and the entries of
+//     lowest rank within each sign (rank by value, ties by position).
+// ---------------------------------------------------------------------------
+void row_argmin(int n, const int* a, int b, const double* lam, double* g) {
+  // choose k entries of +1 and k - b of -1, each the cheapest of its sign
+  std::vector<int> pos, neg;
+  for (int l = 0; l < n; ++l) (a[l] > 0 ? pos : neg).push_back(l);
+  auto by_value = [&](int x, int y) { return lam[x] < lam[y] || (lam[x] == lam[y] && x < y); };
+  std::sort(pos.begin(), pos.end(), by_value);
+  std::sort(neg.begin(), neg.end(), by_value);
+  const int P = int(pos.size()), N = int(neg.size());
+  double best = INF;
+  int kbest = -1;
+  for (int k = std::max(0, b); k <= std::min(P, N + b); ++k) {
+    double f = 0.0;
+    for (int q = 0; q < k; ++q) f += lam[pos[q]];
+    for (int q = 0; q < k - b; ++q) f += lam[neg[q]];
+    if (f < best) {
+      best = f;
+      kbest = k;
+    }
+  }
+  for (int l = 0; l < n; ++l) g[l] = 0.0;
+  for (int q = 0; q < kbest; ++q) g[pos[q]] = 1.0;
+  for (int q = 0; q < kbest - b; ++q) g[neg[q]] = 1.0;
+}
+
+void subgradient(const Space& S, const double* lam, double* g) {
+  const int64_t nr = int64_t(S.rrow_b.size());
+  for (int64_t j = 0; j < nr; ++j) {
+    int64_t b0 = S.rrow_ptr[j], n = S.rrow_ptr[j + 1] - b0;
+    row_argmin(int(n), &S.rent_coef[b0], S.rrow_b[j], lam + b0, g + b0);
+  }
+}
+
+// subtract from every multiplier direction the mean over its variable's rows
+void project_feasible(const Space& S, double* d) {
+  for (size_t i = 0; i < S.free_var.size(); ++i) {
+    double sum = 0.0;
+    for (int64_t e : S.var_ents[i]) sum += d[e];
+    double mean = sum / S.deg[i];
+    for (int64_t e : S.var_ents[i]) d[e] -= mean;
+  }
+}
+
+double dotv(const std::vector<double>& x, const std::vector<double>& y) {
+  double s = 0.0;
+  for (size_t i = 0; i < x.size(); ++i) s += x[i] * y[i];
+  return s;
+}
+
+// two-loop recursion: d = H g with history pairs (oldest first)
+void lbfgs_direction(const std::vector<std::vector<double>>& Sh, const std::vector<std::vector<double>>& Yh,
+                     const std::vector<double>& g, std::vector<double>& d) {
+  const size_t m = Sh.size();
+  d = g;
+  if (m == 0) return;
+  std::vector<double> alpha(m), rho(m);
+  for (size_t j = m; j-- > 0;) {
+    rho[j] = 1.0 / dotv(Sh[j], Yh[j]);
+    alpha[j] = rho[j] * dotv(Sh[j], d);
+    for (size_t e = 0; e < d.size(); ++e) d[e] -= alpha[j] * Yh[j][e];
+  }
+  const double h0 = dotv(Sh[m - 1], Yh[m - 1]) / dotv(Yh[m - 1], Yh[m - 1]);
+  for (double& v : d) v *= h0;
+  for (size_t j = 0; j < m; ++j) {
+    const double beta = rho[j] * dotv(Yh[j], d);
+    for (size_t e = 0; e < d.size(); ++e) d[e] += Sh[j][e] * (alpha[j] - beta);
+  }
+}
+
+struct StepResult {
+  double gamma, E_best;
+};
+
+// FindStepSize: grow gamma by a_up while the step does not reach Delta_min,
+// shrink by a_down while it does not improve; keep the best trial
+template <typename F>
+StepResult find_step(F&& E_at, double E_init, double gamma, int K, double a_up, double a_down, double dmin) {
+  double gm = gamma, Em = E_at(gamma), Ecur = Em;
+  for (int t = 0; t < K; ++t) {
+    gamma = (Ecur <= E_init) ? a_down * gamma : a_up * gamma;
+    Ecur = E_at(gamma);
+    if (Ecur >= Em) {
+      gm = gamma;
+      Em = Ecur;
+    }
+    if (Ecur - E_init >= dmin) break;
+  }
+  return {gm, Em};
+}
+
+}  // namespace
+
+extern "C" {
+
+int or_lbfgs_solve(void* h, int iters, double omega, int m, int K, double eps, double a_up, double a_down,
+                   double gamma0, double* lam, double* trace_E, double* trace_gamma, int* taken) {
+  Space& S = *static_cast<Space*>(h);
+  if (!S.has_cost || iters < 0 || m < 0 || K < 1) return E_ARG;
+  const size_t nnz = S.rent_var.size();
+  std::vector<double> L(lam, lam + nnz), g(nnz), g_new(nnz), d(nnz), trial(nnz), L_prev(nnz);
+  std::vector<std::vector<double>> Sh, Yh;
+  double gamma = gamma0, dmin = INF, E0 = 0.0;
+  double E_now = sweep(S, L.data(), 0.0, nullptr, nullptr, nullptr);
+  subgradient(S, L.data(), g.data());
+  for (int t = 0; t < iters; ++t) {
+    if (trace_E) trace_E[t] = E_now;
+    if (t == 0) E0 = E_now;
+    if (t == 1) dmin = 1e-6 * (E_now - E0);
+    lbfgs_direction(Sh, Yh, g, d);
+    project_feasible(S, d.data());
+    auto E_at = [&](double gm) {
+      for (size_t e = 0; e < nnz; ++e) trial[e] = L[e] + gm * d[e];
+      return sweep(S, trial.data(), 0.0, nullptr, nullptr, nullptr);
+    };
+    StepResult st = find_step(E_at, E_now, gamma, K, a_up, a_down, dmin);
+    L_prev = L;
+    gamma = st.gamma;
+    if (trace_gamma) trace_gamma[t] = gamma;
+    const bool step = st.E_best > E_now;
+    if (taken) taken[t] = step ? 1 : 0;
+    if (step)
+      for (size_t e = 0; e < nnz; ++e) L[e] += gamma * d[e];
+    jacobi(S, L.data(), 1, omega, 0.0, nullptr);
+    E_now = sweep(S, L.data(), 0.0, nullptr, nullptr, nullptr);
+    subgradient(S, L.data(), g_new.data());
+    std::vector<double> s(nnz), y(nnz);
+    for (size_t e = 0; e < nnz; ++e) {
+      s[e] = L[e] - L_prev[e];
+      y[e] = g[e] - g_new[e];
+    }
+    if (dotv(s, y) >= eps) {
+      Sh.push_back(std::move(s));
+      Yh.push_back(std::move(y));
+      if (int(Sh.size()) > m) {
+        Sh.erase(Sh.begin());
+        Yh.erase(Yh.begin());
+      }
+    }
+    g.swap(g_new);
+  }
+  if (trace_E) trace_E[iters] = E_now;
+  std::copy(L.begin(), L.end(), lam);
+  return OK;
+}
+
+int or_project_feasible(void* h, double* d) {
+  project_feasible(*static_cast<Space*>(h), d);
+  return OK;
+}
+
+int or_subgradient(void* h, const double* lam, double* g) {
+  subgradient(*static_cast<Space*>(h), lam, g);
+  return OK;
+}
+
+int or_lbfgs_direction(int n, int m, const double* Sflat, const double* Yflat, const double* g, double* d) {
+  std::vector<std::vector<double>> Sh(m), Yh(m);
+  for (int j = 0; j < m; ++j) {
+    Sh[j].assign(Sflat + size_t(j) * n, Sflat + size_t(j + 1) * n);
+    Yh[j].assign(Yflat + size_t(j) * n, Yflat + size_t(j + 1) * n);
+  }
+  std::vector<double> gv(g, g + n), dv;
+  lbfgs_direction(Sh, Yh, gv, dv);
+  std::copy(dv.begin(), dv.end(), d);
+  return OK;
+}
+
+// FindStepSize on the concave parabola E(gamma) = -(gamma - c)^2 (checks)
+double or_find_step_parabola(double c, double gamma, int K, double a_up, double a_down, double dmin,
+                             double* E_best) {
+  auto E_at = [&](double gm) { return -(gm - c) * (gm - c); };
+  StepResult r = find_step(E_at, E_at(0.0), gamma, K, a_up, a_down, dmin);
+  if (E_best) *E_best = r.E_best;
+  return r.gamma;
 }
 
 // L_T at lam = c / deg + phi for given element costs (finite-difference checks)

@@ -55,6 +55,14 @@ def lib():
         L.or_smoothed_value_phi.argtypes = [P, P, P, C.c_double]
         L.or_smoothed_value_phi.restype = C.c_double
         L.or_costs_for.argtypes = [P, P, P, C.c_int, P]
+        L.or_lbfgs_solve.argtypes = [P, C.c_int, C.c_double, C.c_int, C.c_int, C.c_double,
+                                     C.c_double, C.c_double, C.c_double, P, P, P, P]
+        L.or_subgradient.argtypes = [P, P, P]
+        L.or_project_feasible.argtypes = [P, P]
+        L.or_lbfgs_direction.argtypes = [C.c_int, C.c_int, P, P, P, P]
+        L.or_find_step_parabola.argtypes = [C.c_double, C.c_double, C.c_int, C.c_double,
+                                            C.c_double, C.c_double, P]
+        L.or_find_step_parabola.restype = C.c_double
     return _LIB
 
 
@@ -132,6 +140,24 @@ def row_dp(coef, b, lam, T=0.0):
 
 def uniform_pm1(seed, r, i):
     return lib().or_uniform_pm1(seed, r, i)
+
+
+def lbfgs_direction(S, Y, g):
+    """Two-loop recursion d = H g over history pairs S[j], Y[j] (oldest first)."""
+    g = _c(g, np.float64)
+    S = _c(np.reshape(S, (-1, len(g))), np.float64)
+    Y = _c(np.reshape(Y, (-1, len(g))), np.float64)
+    d = np.zeros(len(g))
+    lib().or_lbfgs_direction(len(g), S.shape[0], _p(S), _p(Y), _p(g), _p(d))
+    return d
+
+
+def find_step_parabola(c, gamma, K=5, a_up=1.1, a_down=0.8, dmin=float("inf")):
+    """FindStepSize on E(gamma) = -(gamma - c)^2 starting from gamma (E_init = E(0))."""
+    e = C.c_double(0)
+    gm = lib().or_find_step_parabola(float(c), float(gamma), int(K), float(a_up),
+                                     float(a_down), float(dmin), C.byref(e))
+    return gm, e.value
 
 
 class Space:
@@ -230,6 +256,35 @@ class Space:
         if st:
             raise OracleError(st)
         return lam, trace[:iters]
+
+    def lbfgs_solve(self, iters, lam=None, omega=0.5, m=5, K=5, eps=1e-8, a_up=1.1,
+                    a_down=0.8, gamma0=1e-3):
+        """Quasi-newton powered MMA (Alg. 1); returns lambda, E per iteration
+        (iters + 1 values: before each iteration and at the end), the step size
+        after each FindStepSize and whether the step was taken."""
+        lam = self.init_lambda() if lam is None else _c(lam, np.float64).copy()
+        tE = np.zeros(iters + 1)
+        tg = np.zeros(max(iters, 1))
+        tk = np.zeros(max(iters, 1), np.int32)
+        st = lib().or_lbfgs_solve(self.h, int(iters), float(omega), int(m), int(K), float(eps),
+                                  float(a_up), float(a_down), float(gamma0), _p(lam), _p(tE),
+                                  _p(tg), _p(tk))
+        if st:
+            raise OracleError(st)
+        return lam, tE, tg[:iters], tk[:iters].astype(bool)
+
+    def subgradient(self, lam):
+        """Per entry: 1 where the row's minimising assignment sets the variable."""
+        lam = _c(lam, np.float64)
+        g = np.zeros(self.info["nnz"])
+        lib().or_subgradient(self.h, _p(lam), _p(g))
+        return g
+
+    def project_feasible(self, d):
+        """Subtract from every entry the mean over its variable's entries."""
+        d = _c(d, np.float64).copy()
+        lib().or_project_feasible(self.h, _p(d))
+        return d
 
     def lower_bound(self, lam, T=0.0):
         lam = _c(lam, np.float64)

@@ -274,3 +274,162 @@ def test_smoothed_gradient_single_row_is_softmax():
                     - O.row_dp(np.ones(4, int), 1, lam - h * e, T)[0]) / (2 * h) for e in np.eye(4)])
     w = np.exp(-lam / T)
     assert np.allclose(mu, w / w.sum(), rtol=1e-12) and np.allclose(fd, mu, rtol=1e-7)
+
+
+# ---------------------------------------------------------------------------
+# Quasi-Newton layer (Sec. 4.1, Alg. 1; Appendix "Quasi-Newton Updates")
+# ---------------------------------------------------------------------------
+def _dense_bfgs_inverse(S, Y):
+    """Inverse-Hessian estimate built by the textbook BFGS update
+    H <- (I - rho s y^T) H (I - rho y s^T) + rho s s^T, applied to the pairs
+    oldest first from H0 = (s^T y / y^T y) I of the newest pair (Nocedal &
+    Wright, Eqs. 6.17 and 7.20).  The two-loop recursion must equal H g."""
+    n = S.shape[1]
+    H = (S[-1] @ Y[-1]) / (Y[-1] @ Y[-1]) * np.eye(n)
+    for s, y in zip(S, Y):
+        rho = 1.0 / (s @ y)
+        V = np.eye(n) - rho * np.outer(y, s)
+        H = V.T @ H @ V + rho * np.outer(s, s)
+    return H
+
+
+@pytest.mark.parametrize("m", [1, 2, 5])
+def test_lbfgs_direction_equals_dense_bfgs(m):
+    rng = np.random.default_rng(m)
+    n = 9
+    B = rng.normal(size=(n, n))
+    A = B @ B.T + n * np.eye(n)                 # SPD: y = A s gives s^T y > 0
+    S = rng.normal(size=(m, n))
+    Y = S @ A.T + 0.01 * rng.normal(size=(m, n))
+    g = rng.normal(size=n)
+    d = O.lbfgs_direction(S, Y, g)
+    assert np.allclose(d, _dense_bfgs_inverse(S, Y) @ g, rtol=1e-10, atol=1e-12)
+    # secant condition of the newest pair: H y_k = s_k
+    assert np.allclose(O.lbfgs_direction(S, Y, Y[-1]), S[-1], rtol=1e-10, atol=1e-12)
+
+
+def test_lbfgs_direction_without_history_is_identity():
+    g = np.arange(7.0) - 3.0
+    assert np.array_equal(O.lbfgs_direction(np.zeros((0, 7)), np.zeros((0, 7)), g), g)
+
+
+def test_find_step_worked_examples():
+    """FindStepSize on E(gamma) = -(gamma - c)^2 with E_init = E(0), factors
+    1.1 up and 0.8 down and K = 5; the expected step sizes are worked out by
+    hand from the procedure:
+      c = 1,   gamma = 0.5: every trial improves and beats the best so far, so
+               gamma grows five times: 0.5 * 1.1^5;
+      same with Delta_min = 0.5: E(0.55) - E(0) = 0.7975 stops the search;
+      c = 0.1, gamma = 1: no trial beats E(0) = -0.01, so gamma shrinks five
+               times; the best trial is the last one, 0.8^5, still worse than
+               E(0) (no step is taken);
+      c = 1,   gamma = 1.9: trials 2.09 (worse than E_init -> shrink), 1.672
+               (best), 1.8392, 2.02312 (worse than E_init -> shrink), 1.618496
+               (best)."""
+    gm, e = O.find_step_parabola(1.0, 0.5)
+    assert np.isclose(gm, 0.5 * 1.1 ** 5, rtol=1e-14) and np.isclose(e, -(gm - 1) ** 2)
+    gm, _ = O.find_step_parabola(1.0, 0.5, dmin=0.5)
+    assert np.isclose(gm, 0.55, rtol=1e-14)
+    gm, e = O.find_step_parabola(0.1, 1.0)
+    assert np.isclose(gm, 0.8 ** 5, rtol=1e-14) and e < -0.01
+    gm, _ = O.find_step_parabola(1.0, 1.9)
+    assert np.isclose(gm, 1.618496, rtol=1e-12)
+    # a single search step (K = 1) from the worked case above keeps 1.9
+    gm, _ = O.find_step_parabola(1.0, 1.9, K=1)
+    assert np.isclose(gm, 1.9, rtol=1e-14)
+
+
+def _perturbed_lambda(S, seed, scale=0.05):
+    """A dual-feasible lambda away from the initial point: c/deg plus a
+    zero-mean (per variable) random perturbation."""
+    lam = S.init_lambda()
+    rng = np.random.default_rng(seed)
+    z = rng.normal(size=len(lam)) * scale
+    rv = S.get("rent_var")
+    mean = np.bincount(rv, weights=z, minlength=S.info["n_free"]) / np.bincount(rv)
+    return lam + z - mean[rv]
+
+
+def test_subgradient_is_a_row_minimiser():
+    p = make_pair(1, 0, desc_noise=1.0)
+    S = _space(p, 16)
+    lam = _perturbed_lambda(S, 3)
+    g = S.subgradient(lam)
+    _, rowmin, _ = S.min_marginals(lam)
+    rp, coef, b = S.get("rrow_ptr"), S.get("rent_coef"), S.get("rrow_b")
+    assert set(np.unique(g)) <= {0.0, 1.0}
+    for j in range(S.info["n_rows"]):
+        sl = slice(rp[j], rp[j + 1])
+        assert int(np.dot(coef[sl], g[sl])) == b[j]
+        assert abs(np.dot(g[sl], lam[sl]) - rowmin[j]) <= 1e-12 * (1 + abs(rowmin[j]))
+    # short rows: the minimiser is the unique one found by enumeration
+    for j in range(0, S.info["n_rows"], 7):
+        n = rp[j + 1] - rp[j]
+        if n > 12:
+            continue
+        sl = slice(rp[j], rp[j + 1])
+        sols = [np.array(s) for s in itertools.product((0, 1), repeat=n)
+                if np.dot(s, coef[sl]) == b[j]]
+        vals = np.array([np.dot(s, lam[sl]) for s in sols])
+        assert np.array_equal(g[sl], sols[int(np.argmin(vals))])
+
+
+def test_subgradient_is_a_supergradient_of_the_dual():
+    """E is concave: E(l') <= E(l) + g^T (l' - l) for every l', with equality
+    for small steps while every row keeps its (unique) minimiser."""
+    p = make_pair(1, 1, desc_noise=1.0)
+    S = _space(p, 16)
+    lam = _perturbed_lambda(S, 4)
+    g = S.subgradient(lam)
+    E = S.lower_bound(lam)
+    rng = np.random.default_rng(9)
+    for scale in (1e-9, 1e-3, 1e-1, 1.0):
+        u = rng.normal(size=len(lam)) * scale
+        assert S.lower_bound(lam + u) <= E + g @ u + 1e-10 * (1 + abs(E))
+    u = rng.normal(size=len(lam)) * 1e-9
+    assert np.isclose(S.lower_bound(lam + u) - E, g @ u, rtol=1e-4, atol=1e-14)
+
+
+def test_lbfgs_with_zero_step_is_plain_mma():
+    """With step size 0 no trial improves, so no quasi-Newton step is taken and
+    the iteration reduces to the Jacobi MMA update."""
+    p = make_pair(1, 0, desc_noise=1.0)
+    S = _space(p, 16)
+    lam, tE, tg, tk = S.lbfgs_solve(12, gamma0=0.0)
+    lam_j, tr = S.dual_solve(12)
+    assert not tk.any() and np.all(tg == 0.0)
+    assert np.array_equal(lam, lam_j)
+    assert np.array_equal(tE[:12], tr)
+
+
+def test_lbfgs_feasible_bounded_and_faster_than_mma():
+    p = make_pair(1, 0, desc_noise=1.0)
+    S = _space(p, 16)
+    lam, tE, tg, tk = S.lbfgs_solve(60, gamma0=0.1)
+    rv = S.get("rent_var")
+    c = S.get("cost")[S.get("free_var")]
+    sums = np.bincount(rv, weights=lam, minlength=S.info["n_free"])
+    assert np.all(np.abs(sums - c) <= 1e-10 * (1 + c))
+    lp = _lp_ilp(S, integral=False)
+    assert np.all(tE <= lp + 1e-9 * abs(lp))
+    assert np.isclose(tE[-1], S.lower_bound(lam), rtol=0, atol=1e-12)
+    _, tr = S.dual_solve(60)
+    # the quasi-Newton steps raise the bound well beyond the same number of
+    # Jacobi iterations on this instance (Sec. 4.1: faster than MMA alone)
+    assert (lp - tE.max()) < 0.5 * (lp - tr.max())
+    assert tk.sum() > 30
+
+
+def test_feasibility_projection_is_orthogonal():
+    """Alg. 1's projection removes each variable's mean: the result sums to 0
+    over every variable's entries, is idempotent, and d - Pd is orthogonal to
+    every feasible direction."""
+    S = _space(make_pair(1, 0), 6)
+    rng = np.random.default_rng(1)
+    d = rng.normal(size=S.info["nnz"])
+    e = S.project_feasible(d)
+    rv = S.get("rent_var")
+    assert np.abs(np.bincount(rv, weights=e)).max() < 1e-12
+    assert np.allclose(S.project_feasible(e), e, atol=1e-15)
+    f = S.project_feasible(rng.normal(size=S.info["nnz"]))
+    assert abs((d - e) @ f) < 1e-10
