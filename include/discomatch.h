@@ -163,6 +163,58 @@ dm_status dm_init_lambda(dm_ctx* ctx, int32_t msg_prec, void* lambda);
 dm_status dm_dual_solve(dm_ctx* ctx, int32_t iters, double omega, double temperature,
                         int32_t msg_prec, void* lambda, double* lb_trace);
 
+/* Quasi-Newton powered MMA (Sec. 4.1, Alg. 1; Appendix "Quasi-Newton
+ * Updates").  One iteration: the subgradient g (every row's minimising
+ * assignment, 1 / 0 per multiplier); the direction d^ = H g by the L-BFGS
+ * two-loop recursion over the last `history` accepted pairs (H = I without
+ * history, H0 = (s^T y / y^T y) I of the newest pair otherwise); d = d^ minus
+ * its mean over each variable's rows (keeps sum_j lambda^j_i = c_i);
+ * FindStepSize: from the previous step size, up to max_search rescalings by
+ * step_up (the trial did not lose against E(lambda)) or step_down (it did),
+ * stopping once a trial gains Delta_min = 1e-6 (E(lambda^1) - E(lambda^0))
+ * (no early stop in the first iteration), keeping the best trial; the step
+ * lambda += gamma d only when that trial beats E(lambda); one Jacobi MMA
+ * iteration with omega; then the pair s = lambda_new - lambda_old,
+ * y = g_old - g_new joins the history when s^T y >= eps (L-BFGS acting on -E).
+ * Dots are summed in FP64 in a fixed order.
+ *  lambda [device] float32 / float64 (msg_prec) [nnz] in/out, feasible on entry.
+ *  lb_trace [device] double [iters + 1] out or NULL: E at the start of every
+ *  iteration and at the end.  gamma_trace [device] double [iters] out or NULL:
+ *  the step size FindStepSize returned.  taken [device] int32 [iters] out or
+ *  NULL: 1 where the quasi-Newton step was applied.  Allocates its work
+ *  buffers (history of (history + 1) s and y vectors); reads one flag back to
+ *  the host per iteration (synchronises). */
+typedef struct {
+  int32_t history;      /* m, number of stored (s, y) pairs, >= 0 */
+  int32_t max_search;   /* K, rescalings per FindStepSize, >= 1 */
+  double omega;         /* MMA damping, (0, 1] */
+  double eps;           /* curvature threshold */
+  double step_up;       /* > 1 */
+  double step_down;     /* in (0, 1) */
+  double gamma0;        /* first step size, >= 0 */
+} dm_lbfgs_params;
+dm_status dm_lbfgs_solve(dm_ctx* ctx, int32_t iters, const dm_lbfgs_params* params, int32_t msg_prec,
+                         void* lambda, double* lb_trace, double* gamma_trace, int32_t* taken);
+
+/* Subgradient of the dual (first step of Alg. 1): per multiplier, 1 where the
+ * minimising assignment of its row sets the variable (exactly-one rows: the
+ * smallest multiplier, lowest position on ties; +-1 rows: the fewest +1
+ * entries among the minimisers, the smallest multipliers of each sign with
+ * lower positions first on ties).
+ *  lambda [device] (msg_prec) [nnz]; g [device] uint8 [nnz] out;
+ *  *lb [host] out (the bound at lambda) or NULL.  Synchronises. */
+dm_status dm_subgradient(dm_ctx* ctx, int32_t msg_prec, const void* lambda, uint8_t* g, double* lb);
+
+/* The direction step of Alg. 1 on a given history: d^ = H g by the two-loop
+ * recursion over the pairs (S[k], Y[k]), k = 0 (oldest) .. h-1 (newest), then
+ * the projection to zero mean over each variable's rows.  Every pair needs
+ * s^T y != 0.
+ *  S [device] (msg_prec) [h * nnz]; Y [device] int8 [h * nnz] (differences of
+ *  subgradients, values -1, 0, 1); g [device] uint8 [nnz]; d [device]
+ *  (msg_prec) [nnz] out.  Enqueue only (allocates work buffers). */
+dm_status dm_lbfgs_direction(dm_ctx* ctx, int32_t msg_prec, int32_t h, const void* S, const int8_t* Y,
+                             const uint8_t* g, void* d);
+
 /* Dual objective (A8; Eq. (D)) at lambda: offset + sum over rows of the row
  * minimum (soft-min for temperature > 0).  Synchronises; *lb [host]. */
 dm_status dm_lower_bound(dm_ctx* ctx, const void* lambda, double temperature, int32_t msg_prec,

@@ -258,7 +258,7 @@ class Space:
         return lam, trace[:iters]
 
     def lbfgs_solve(self, iters, lam=None, omega=0.5, m=5, K=5, eps=1e-8, a_up=1.1,
-                    a_down=0.8, gamma0=1e-3):
+                    a_down=0.8, gamma0=0.1):
         """Quasi-newton powered MMA (Alg. 1); returns lambda, E per iteration
         (iters + 1 values: before each iteration and at the end), the step size
         after each FindStepSize and whether the step was taken."""

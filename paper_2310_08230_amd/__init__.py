@@ -48,6 +48,12 @@ class dm_round_params(C.Structure):
                 ("msg_prec", C.c_int32)]
 
 
+class dm_lbfgs_params(C.Structure):
+    _fields_ = [("history", C.c_int32), ("max_search", C.c_int32), ("omega", C.c_double),
+                ("eps", C.c_double), ("step_up", C.c_double), ("step_down", C.c_double),
+                ("gamma0", C.c_double)]
+
+
 def lib():
     """Load libdiscomatch.so (raises if it has not been built)."""
     global _lib
@@ -73,6 +79,9 @@ def lib():
             "dm_mixed_areas": [P, P, P],
             "dm_timing_enable": [P, I32],
             "dm_timing_read": [P, P, P],
+            "dm_lbfgs_solve": [P, I32, P, I32, P, P, P, P],
+            "dm_subgradient": [P, I32, P, P, P],
+            "dm_lbfgs_direction": [P, I32, I32, P, P, P, P],
         }
         for name, args in sig.items():
             fn = getattr(L, name)
@@ -198,6 +207,41 @@ class Context:
                    _ptr(lam), _ptr(tr) if trace else None)
         return lam, (tr[:iters] if trace else None)
 
+    def lbfgs_solve(self, lam, iters, history=5, max_search=5, omega=0.5, eps=1e-8, step_up=1.1,
+                    step_down=0.8, gamma0=0.1):
+        """Quasi-Newton powered MMA (Alg. 1), in place on lam.  Returns lam, the
+        bound before every iteration and at the end (iters + 1 values), the
+        step sizes and whether each quasi-Newton step was taken."""
+        msg_prec = "fp32" if lam.dtype == torch.float32 else "fp64"
+        P = dm_lbfgs_params(int(history), int(max_search), float(omega), float(eps), float(step_up),
+                            float(step_down), float(gamma0))
+        tr = torch.empty(iters + 1, dtype=torch.float64, device=self.device)
+        gm = torch.empty(max(iters, 1), dtype=torch.float64, device=self.device)
+        tk = torch.empty(max(iters, 1), dtype=torch.int32, device=self.device)
+        self._call("dm_lbfgs_solve", int(iters), C.byref(P), PREC[msg_prec], _ptr(lam), _ptr(tr),
+                   _ptr(gm), _ptr(tk))
+        return lam, tr, gm[:iters], tk[:iters].bool()
+
+    def subgradient(self, lam):
+        """Per multiplier 1 where its row's minimiser sets the variable, and the bound."""
+        msg_prec = "fp32" if lam.dtype == torch.float32 else "fp64"
+        g = torch.empty(self.info["nnz"], dtype=torch.uint8, device=self.device)
+        lb = C.c_double(0)
+        self._call("dm_subgradient", PREC[msg_prec], _ptr(lam), _ptr(g), C.byref(lb))
+        return g, lb.value
+
+    def lbfgs_direction(self, S, Y, g):
+        """Projected two-loop direction over the pairs S[k], Y[k] (oldest first)."""
+        S = S.contiguous()
+        msg_prec = "fp32" if S.dtype == torch.float32 else "fp64"
+        Y = Y.to(torch.int8).contiguous()
+        g = g.to(torch.uint8).contiguous()
+        d = torch.empty(self.info["nnz"], dtype=S.dtype, device=self.device)
+        h = S.shape[0] if S.dim() == 2 else 0
+        self._call("dm_lbfgs_direction", PREC[msg_prec], int(h), _ptr(S) if h else None,
+                   _ptr(Y) if h else None, _ptr(g), _ptr(d))
+        return d
+
     def lower_bound(self, lam, temperature=0.0):
         msg_prec = "fp32" if lam.dtype == torch.float32 else "fp64"
         out = C.c_double(0)
@@ -260,6 +304,10 @@ def build_costs(ctx: Context, *a, **k):
 
 def dual_solve(ctx: Context, *a, **k):
     return ctx.dual_solve(*a, **k)
+
+
+def lbfgs_solve(ctx: Context, *a, **k):
+    return ctx.lbfgs_solve(*a, **k)
 
 
 def round_primal(ctx: Context, *a, **k):

@@ -81,6 +81,36 @@ constexpr int REC_COST = 5;
 constexpr int MAX_SHORT_ROW = 64;
 constexpr int SOFT_MAX_ROW = 24;
 
+// Multipliers of free variable i from its record (slots 0-4 hold s_k, slot 5
+// the cost c_i), with dual feasibility restored: lambda_k = s_k + (c_i -
+// sum_k s_k) / |J_i|.  Slot 4 is used only when the variable has five rows.
+// Every reader of a record (the row sweeps and the per-variable passes) goes
+// through this one function, so they all see bit-identical multipliers.
+template <typename R>
+__device__ inline void rec_lambdas(const R* __restrict__ rec, size_t i, bool d5, R lam[5]) {
+  const R* r = rec + i * REC;
+  R s0, s1, s2, s3, s4, c;
+  if constexpr (sizeof(R) == 4) {
+    // records are 32-byte aligned: one 16-byte and one 8-byte load
+    const float4 lo = *reinterpret_cast<const float4*>(r);
+    const float2 hi = *reinterpret_cast<const float2*>(r + 4);
+    s0 = lo.x, s1 = lo.y, s2 = lo.z, s3 = lo.w, s4 = hi.x, c = hi.y;
+  } else {
+    const double2 a = *reinterpret_cast<const double2*>(r);
+    const double2 b = *reinterpret_cast<const double2*>(r + 2);
+    const double2 d = *reinterpret_cast<const double2*>(r + 4);
+    s0 = a.x, s1 = a.y, s2 = b.x, s3 = b.y, s4 = d.x, c = d.y;
+  }
+  R sum = ((s0 + s1) + s2) + s3;
+  if (d5) sum += s4;
+  const R corr = (c - sum) / (d5 ? R(5) : R(4));
+  lam[0] = s0 + corr;
+  lam[1] = s1 + corr;
+  lam[2] = s2 + corr;
+  lam[3] = s3 + corr;
+  lam[4] = d5 ? s4 + corr : R(0);
+}
+
 struct dm_ctx {
   int device = 0;
   hipStream_t stream = nullptr;
@@ -180,6 +210,28 @@ dm_status scan_u8(dm_ctx* ctx, const uint8_t* in, int32_t* out, size_t n);   // 
 dm_status read_i32(dm_ctx* ctx, const int32_t* dev, int32_t* host);
 dm_status check_finite(dm_ctx* ctx, const float* a, int64_t n);
 dm_status dual_flush(dm_ctx* ctx);  // write the bound of the last sweep launch
+
+// One sweep over all rows of the presolved problem (dual.hip).  Modes: update
+// the multipliers (rin -> out), write min-marginals (or soft marginals) per
+// slot to out, bound only, or write each row's minimising assignment.
+enum SweepMode { SWEEP_UPDATE = 0, SWEEP_EVAL = 1, SWEEP_BOUND = 2, SWEEP_SUBGRAD = 3 };
+// Options of the hard sweep used by the quasi-Newton layer: rows see
+// lambda + (*gamma) * dir (dir in the record layout, gamma on the device); the
+// launch does nothing while *skip is nonzero; SWEEP_SUBGRAD writes 1 / 0 per
+// slot to gsub.
+struct SweepExt {
+  const void* dir = nullptr;
+  const double* gamma = nullptr;
+  const int32_t* skip = nullptr;
+  uint8_t* gsub = nullptr;
+};
+template <typename R>
+dm_status dual_import(dm_ctx* ctx, const R* lam, DArr<unsigned char>* bufs);
+template <typename R>
+dm_status dual_export(dm_ctx* ctx, const unsigned char* rec, R* lam);
+template <typename R>
+dm_status dual_sweep(dm_ctx* ctx, int mode, bool soft, const unsigned char* rin, unsigned char* out, R omega,
+                     R T, double* bound_out, const SweepExt* ext = nullptr);
 
 // grid size helper
 inline unsigned grid_for(int64_t n, int block) {

@@ -32,7 +32,8 @@
 
 namespace {
 
-enum { MODE_UPDATE = 0, MODE_EVAL = 1, MODE_BOUND = 2 };
+constexpr int MODE_UPDATE = SWEEP_UPDATE, MODE_EVAL = SWEEP_EVAL, MODE_BOUND = SWEEP_BOUND,
+              MODE_SUBGRAD = SWEEP_SUBGRAD;
 
 template <typename R>
 __device__ inline R rinf() {
@@ -66,26 +67,10 @@ __device__ inline R smin2(R a, R b, R T) {
 // feasibility restored
 template <typename R>
 __device__ inline R cur_lambda(const R* __restrict__ rec, uint32_t w) {
-  const R* r = rec + size_t(w & W_VAR_MASK) * REC;
+  R lam[5];
+  rec_lambdas<R>(rec, size_t(w & W_VAR_MASK), (w & W_DEG5) != 0, lam);
   const int k = int((w >> W_SLOT_SHIFT) & 7u);
-  const bool d5 = (w & W_DEG5) != 0;
-  R s0, s1, s2, s3, s4, c;
-  if constexpr (sizeof(R) == 4) {
-    // records are 32-byte aligned: one 16-byte and one 8-byte load
-    const float4 lo = *reinterpret_cast<const float4*>(r);
-    const float2 hi = *reinterpret_cast<const float2*>(r + 4);
-    s0 = lo.x, s1 = lo.y, s2 = lo.z, s3 = lo.w, s4 = hi.x, c = hi.y;
-  } else {
-    const double2 a = *reinterpret_cast<const double2*>(r);
-    const double2 b = *reinterpret_cast<const double2*>(r + 2);
-    const double2 d = *reinterpret_cast<const double2*>(r + 4);
-    s0 = a.x, s1 = a.y, s2 = b.x, s3 = b.y, s4 = d.x, c = d.y;
-  }
-  R sum = ((s0 + s1) + s2) + s3;
-  if (d5) sum += s4;
-  R corr = (c - sum) / (d5 ? R(5) : R(4));
-  R sk = k == 0 ? s0 : k == 1 ? s1 : k == 2 ? s2 : k == 3 ? s3 : s4;
-  return sk + corr;
+  return k == 0 ? lam[0] : k == 1 ? lam[1] : k == 2 ? lam[2] : k == 3 ? lam[3] : lam[4];
 }
 
 template <typename R>
@@ -135,7 +120,23 @@ struct SweepArgs {
   int32_t prev_n;
   double prev_offset;
   double* prev_out;
+  // quasi-Newton extensions (hard min only): rows see lambda + gamma * dir
+  // when dir is set (dir in the record layout, gamma a device scalar); the
+  // launch does nothing when *skip is nonzero; MODE_SUBGRAD writes the row's
+  // minimising assignment (1 / 0 per entry) to gsub in the record layout
+  const void* dir;
+  const double* gamma;
+  const int32_t* skip;
+  uint8_t* gsub;
 };
+
+// multiplier seen by the rows: the record's, moved along dir when one is set
+template <typename R>
+__device__ inline R row_lambda(const SweepArgs& A, const R* __restrict__ rin, uint32_t w, R gam) {
+  R v = cur_lambda<R>(rin, w);
+  if (A.dir) v += gam * static_cast<const R*>(A.dir)[size_t(w & W_VAR_MASK) * REC + ((w >> W_SLOT_SHIFT) & 7u)];
+  return v;
+}
 
 // ---------------------------------------------------------------- short rows, hard min
 // One wave per chunk of whole closedness rows (<= 64 entries, one per lane),
@@ -168,7 +169,7 @@ __device__ inline R permute_to(int dst_lane, R v) {   // push v to lane dst_lane
 
 template <typename R, int MODE>
 __device__ void short_wave_hard(const SweepArgs& A, const R* __restrict__ rin, R* __restrict__ out, R omega,
-                                double* red, int32_t item) {
+                                R gam, double* red, int32_t item) {
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int32_t wc = item * 4 + wave;
   double rowpart = 0.0;
@@ -180,7 +181,7 @@ __device__ void short_wave_hard(const SweepArgs& A, const R* __restrict__ rin, R
     const int32_t rb = lane < nrow ? A.rrow_b[r0 + lane] : 0;
     const bool act = lane < ne;
     const uint32_t w = act ? A.word[e0 + lane] : 0u;
-    const R lam = act ? cur_lambda<R>(rin, w) : R(0);
+    const R lam = act ? row_lambda<R>(A, rin, w, gam) : R(0);
     const int g = int(w >> 31);
     // my row: the last row whose start <= lane (rows have >= 2 entries, so nrow <= 32)
     int32_t myrow = 0;
@@ -223,6 +224,7 @@ __device__ void short_wave_hard(const SweepArgs& A, const R* __restrict__ rin, R
     const int32_t khi = own < oth + bb ? own : oth + bb;
     const int kmax = wave_max_i(act ? khi - klo + 1 : 0);
     R m1 = rinf<R>(), m0 = rinf<R>(), rmin = rinf<R>();
+    int32_t kbest = 0;   // own-group count of the minimiser (smallest on ties)
     for (int kk = 0; kk < kmax; ++kk) {
       const int32_t k = klo + kk, ko = k - bb;
       const int io = obase + k - 1, it = tbase + ko - 1, ix = k >= rank + 1 ? obase + k : obase + k - 2;
@@ -233,7 +235,11 @@ __device__ void short_wave_hard(const SweepArgs& A, const R* __restrict__ rin, R
       const R so = k == 0 ? R(0) : So;
       const R st = ko == 0 ? R(0) : St;
       const R f = so + st;
-      rmin = f < rmin ? f : rmin;
+      if (f < rmin) {
+        rmin = f;
+        kbest = k;
+      }
+      if (MODE == MODE_SUBGRAD || MODE == MODE_BOUND) continue;
       if (k >= rank + 1) {
         // the k smallest of the own group include this entry
         m1 = f < m1 ? f : m1;
@@ -254,6 +260,8 @@ __device__ void short_wave_hard(const SweepArgs& A, const R* __restrict__ rin, R
       const R M = m1 - m0;
       if (MODE == MODE_UPDATE) write_out<R>(out, w, lam - omega * M);
       if (MODE == MODE_EVAL) write_out<R>(out, w, M);
+      if (MODE == MODE_SUBGRAD)
+        A.gsub[size_t(w & W_VAR_MASK) * REC + ((w >> W_SLOT_SHIFT) & 7u)] = uint8_t(rank < kbest ? 1 : 0);
       if (lane == s) rowpart = double(rmin);
     }
   }
@@ -382,7 +390,7 @@ constexpr int LONG_REG = 16;
 
 template <typename R, bool SOFT, int MODE>
 __device__ void long_rows(const SweepArgs& A, const R* __restrict__ rin, R* __restrict__ out, R omega, R T,
-                          double* red, int32_t item) {
+                          R gam, double* red, int32_t item) {
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int32_t j = A.n_short + (item - A.n_short_blocks) * LONG_ROWS_PER_BLOCK + wave;
   double rowpart = 0.0;
@@ -405,7 +413,7 @@ __device__ void long_rows(const SweepArgs& A, const R* __restrict__ rin, R* __re
       const int32_t i = lane + 64 * u;
       lv[u] = R(0);
       if (i < n) {
-        lv[u] = cur_lambda<R>(rin, wv[u]);
+        lv[u] = row_lambda<R>(A, rin, wv[u], gam);
         MinState<R> one;
         one.m = lv[u];
         one.m2 = rinf<R>();
@@ -416,7 +424,7 @@ __device__ void long_rows(const SweepArgs& A, const R* __restrict__ rin, R* __re
     }
     for (int32_t i = lane + 64 * LONG_REG; i < n; i += 64) {   // rows longer than 64 * LONG_REG
       MinState<R> one;
-      one.m = cur_lambda<R>(rin, A.word[s + i]);
+      one.m = row_lambda<R>(A, rin, A.word[s + i], gam);
       one.m2 = rinf<R>();
       one.s = R(0);
       one.a = i;
@@ -447,6 +455,8 @@ __device__ void long_rows(const SweepArgs& A, const R* __restrict__ rin, R* __re
         }
         if (MODE == MODE_UPDATE) write_out<R>(out, w, lam - omega * M);
         if (MODE == MODE_EVAL) write_out<R>(out, w, SOFT ? mu : M);
+        if (MODE == MODE_SUBGRAD)
+          A.gsub[size_t(w & W_VAR_MASK) * REC + ((w >> W_SLOT_SHIFT) & 7u)] = uint8_t(i == st.a ? 1 : 0);
       };
 #pragma unroll
       for (int u = 0; u < LONG_REG; ++u) {
@@ -455,7 +465,7 @@ __device__ void long_rows(const SweepArgs& A, const R* __restrict__ rin, R* __re
       }
       for (int32_t i = lane + 64 * LONG_REG; i < n; i += 64) {
         const uint32_t w = A.word[s + i];
-        finish(i, w, cur_lambda<R>(rin, w));
+        finish(i, w, row_lambda<R>(A, rin, w, gam));
       }
     }
     if (lane == 0) rowpart = double(rowv);
@@ -474,7 +484,9 @@ __global__ __launch_bounds__(256) void k_sweep(SweepArgs A, const R* __restrict_
                                                R omega, R T) {
   __shared__ __align__(16) unsigned char smem[smem_bytes<R, SOFT>()];
   __shared__ double red[256];
+  if (A.skip && *A.skip) return;   // uniform across the grid
   if (blockIdx.x == 0 && A.prev_partial) reduce_partials(A.prev_partial, A.prev_n, A.prev_offset, A.prev_out, red);
+  const R gam = A.gamma ? R(*A.gamma) : R(0);
   // Workgroups are dealt to the 8 XCDs round-robin (block b runs on XCD b % 8).
   // Each XCD takes a contiguous range of short-row chunks, so rows that share
   // variables share one L2, and every eighth projection-row block; the heavier
@@ -493,9 +505,9 @@ __global__ __launch_bounds__(256) void k_sweep(SweepArgs A, const R* __restrict_
   }
   if (item < A.n_short_blocks) {
     if (SOFT) short_rows_soft<R, MODE>(A, rin, out, omega, T, smem, red, item);
-    else short_wave_hard<R, MODE>(A, rin, out, omega, red, item);
+    else short_wave_hard<R, MODE>(A, rin, out, omega, gam, red, item);
   } else {
-    long_rows<R, SOFT, MODE>(A, rin, out, omega, T, red, item);
+    long_rows<R, SOFT, MODE>(A, rin, out, omega, T, gam, red, item);
   }
 }
 
@@ -574,7 +586,9 @@ dm_status dual_export(dm_ctx* ctx, const unsigned char* rec, R* lam) {
 // out per slot, 2 bound only; the bound goes to *bound_out (device)
 template <typename R>
 dm_status dual_sweep(dm_ctx* ctx, int mode, bool soft, const unsigned char* rin, unsigned char* out, R omega,
-                     R T, double* bound_out) {
+                     R T, double* bound_out, const SweepExt* ext) {
+  if (soft && (ext || mode == MODE_SUBGRAD))
+    return dm_fail(ctx, DM_ERR_INVALID_ARG, "direction, skip and subgradient sweeps use the hard minimum");
   if (soft && ctx->max_short > SOFT_MAX_ROW)
     return dm_fail(ctx, DM_ERR_WORKSPACE, "smoothed rows support at most %d entries (found %d)", SOFT_MAX_ROW,
                    ctx->max_short);
@@ -588,6 +602,10 @@ dm_status dual_sweep(dm_ctx* ctx, int mode, bool soft, const unsigned char* rin,
   const int64_t n_long_blocks = (ctx->n_rows - ctx->n_short + LONG_ROWS_PER_BLOCK - 1) / LONG_ROWS_PER_BLOCK;
   A.n_short = int32_t(ctx->n_short);
   A.n_rows = int32_t(ctx->n_rows);
+  A.dir = ext ? ext->dir : nullptr;
+  A.gamma = ext ? ext->gamma : nullptr;
+  A.skip = ext ? ext->skip : nullptr;
+  A.gsub = ext ? ext->gsub : nullptr;
   const int64_t nblocks = int64_t(A.n_short_blocks) + n_long_blocks;
   if (nblocks == 0) {
     DM_TRY(dual_flush(ctx));
@@ -630,7 +648,8 @@ dm_status dual_sweep(dm_ctx* ctx, int mode, bool soft, const unsigned char* rin,
   } else {
     if (mode == MODE_UPDATE) k_sweep<R, false, MODE_UPDATE><<<grid, 256, 0, ctx->stream>>>(A, ri, ro, omega, T);
     else if (mode == MODE_EVAL) k_sweep<R, false, MODE_EVAL><<<grid, 256, 0, ctx->stream>>>(A, ri, ro, omega, T);
-    else k_sweep<R, false, MODE_BOUND><<<grid, 256, 0, ctx->stream>>>(A, ri, ro, omega, T);
+    else if (mode == MODE_BOUND) k_sweep<R, false, MODE_BOUND><<<grid, 256, 0, ctx->stream>>>(A, ri, ro, omega, T);
+    else k_sweep<R, false, MODE_SUBGRAD><<<grid, 256, 0, ctx->stream>>>(A, ri, ro, omega, T);
   }
   DM_LAUNCH_CHECK(ctx);
   if (ev_end) DM_HIP(ctx, hipEventRecord(ev_end, ctx->stream));
@@ -678,9 +697,10 @@ template dm_status dual_import<float>(dm_ctx*, const float*, DArr<unsigned char>
 template dm_status dual_import<double>(dm_ctx*, const double*, DArr<unsigned char>*);
 template dm_status dual_export<float>(dm_ctx*, const unsigned char*, float*);
 template dm_status dual_export<double>(dm_ctx*, const unsigned char*, double*);
-template dm_status dual_sweep<float>(dm_ctx*, int, bool, const unsigned char*, unsigned char*, float, float, double*);
+template dm_status dual_sweep<float>(dm_ctx*, int, bool, const unsigned char*, unsigned char*, float, float, double*,
+                                     const SweepExt*);
 template dm_status dual_sweep<double>(dm_ctx*, int, bool, const unsigned char*, unsigned char*, double, double,
-                                      double*);
+                                      double*, const SweepExt*);
 
 static dm_status check_solver(dm_ctx* ctx, int32_t msg_prec) {
   if (!ctx) return DM_ERR_INVALID_ARG;

@@ -13,12 +13,6 @@
 
 #include "dm_internal.h"
 
-template <typename R>
-dm_status dual_import(dm_ctx* ctx, const R* lam, DArr<unsigned char>* bufs);
-template <typename R>
-dm_status dual_sweep(dm_ctx* ctx, int mode, bool soft, const unsigned char* rin, unsigned char* out, R omega,
-                     R T, double* bound_out);
-
 namespace {
 
 // splitmix64 (Steele, Lea, Flood 2014): one step of the published mixer
@@ -162,7 +156,7 @@ static dm_status round_impl(dm_ctx* ctx, const dm_round_params& P, const R* lam,
   int cur = 0;
   *feasible = 0;
   for (int32_t r = 0; r <= P.rounds; ++r) {
-    DM_TRY(dual_sweep<R>(ctx, 1, false, ctx->rrec[cur].p, ctx->mrec.p, R(0), R(0), nullptr));
+    DM_TRY(dual_sweep<R>(ctx, SWEEP_EVAL, false, ctx->rrec[cur].p, ctx->mrec.p, R(0), R(0), nullptr));
     DM_HIP(ctx, hipMemsetAsync(ctx->icount.p, 0, sizeof(int64_t), st));
     if (nfree > 0)
       k_agree<R><<<grid_for(nfree, 256), 256, 0, st>>>(reinterpret_cast<const R*>(ctx->mrec.p), ctx->var_deg.p,
@@ -196,7 +190,7 @@ static dm_status round_impl(dm_ctx* ctx, const dm_round_params& P, const R* lam,
         reinterpret_cast<R*>(ctx->rrec[1].p));
     DM_LAUNCH_CHECK(ctx);
     for (int32_t t = 0; t < P.iters_per_round; ++t) {
-      DM_TRY(dual_sweep<R>(ctx, 0, false, ctx->rrec[cur].p, ctx->rrec[cur ^ 1].p, R(P.omega), R(0), nullptr));
+      DM_TRY(dual_sweep<R>(ctx, SWEEP_UPDATE, false, ctx->rrec[cur].p, ctx->rrec[cur ^ 1].p, R(P.omega), R(0), nullptr));
       cur ^= 1;
     }
     delta *= P.gamma;

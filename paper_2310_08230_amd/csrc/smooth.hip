@@ -13,12 +13,6 @@
 
 #include "dm_internal.h"
 
-template <typename R>
-dm_status dual_import(dm_ctx* ctx, const R* lam, DArr<unsigned char>* bufs);
-template <typename R>
-dm_status dual_sweep(dm_ctx* ctx, int mode, bool soft, const unsigned char* rin, unsigned char* out, R omega,
-                     R T, double* bound_out);
-
 namespace {
 
 template <typename R>
@@ -100,7 +94,7 @@ static dm_status backward_impl(dm_ctx* ctx, const R* lam, R T, double scale, con
   DM_ALLOC(ctx, ctx->mrec, bytes);
   DM_HIP(ctx, hipMemsetAsync(ctx->mrec.p, 0, bytes, st));
   DM_ALLOC(ctx, ctx->scal, 16);
-  DM_TRY(dual_sweep<R>(ctx, 1, true, bufs[0].p, ctx->mrec.p, R(0), T, ctx->scal.p + 2));
+  DM_TRY(dual_sweep<R>(ctx, SWEEP_EVAL, true, bufs[0].p, ctx->mrec.p, R(0), T, ctx->scal.p + 2));
   DM_TRY(dual_flush(ctx));
   DM_ALLOC(ctx, ctx->gcost_tmp, size_t(ctx->nP));
   DM_ALLOC(ctx, ctx->gw, size_t(std::max<int64_t>(ctx->nC, 1)));
