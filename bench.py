@@ -170,7 +170,21 @@ def cpu_baseline(cfg, seed, iters):
                       f"presolve, costs and {iters} Jacobi iterations in {dt:.1f} s"}
 
 
-def summarize_counters(fetch_csv, write_csv, copy_fetch_csv, copy_write_csv, out_json, copy_bytes):
+def copy_calibration(nbytes, reps=5):
+    """A plain device-to-device copy of ``nbytes`` bytes (the runtime's copy
+    kernel), the reference that scales the FETCH_SIZE / WRITE_SIZE counters to
+    bytes."""
+    import torch
+    src = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(reps):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(f"copied {nbytes} bytes {reps} times", flush=True)
+
+
+def summarize_counters(fetch_csv, write_csv, copy_fetch_csv, copy_write_csv, out_json, copy_bytes,
+                       command=""):
     """Turn rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE collections (KiB per
     dispatch) of the sweep kernel and of a plain copy of ``copy_bytes`` bytes
     into HBM bytes per sweep launch; writes the summary JSON used by the
@@ -198,6 +212,7 @@ def summarize_counters(fetch_csv, write_csv, copy_fetch_csv, copy_write_csv, out
            "copy_calibration": {"bytes": copy_bytes, "fetch_kib": cf, "write_kib": cw,
                                 "fetch_factor": ffac, "write_factor": wfac},
            "bytes_per_launch": int(fetch_b + write_b), "fetch_bytes": int(fetch_b), "write_bytes": int(write_b),
+           "commands": command,
            "dual_hip_sha256": hashlib.sha256(open(src, "rb").read()).hexdigest()}
     with open(out_json, "w") as fh:
         json.dump(rec, fh, indent=1)
@@ -224,7 +239,10 @@ def summarize_trace(stats_csv, out_txt, command):
 
 def main():
     if len(sys.argv) > 1 and sys.argv[1] == "--summarize-counters":
-        summarize_counters(*sys.argv[2:7], int(sys.argv[7]))
+        summarize_counters(*sys.argv[2:7], int(sys.argv[7]), " ".join(sys.argv[8:]))
+        return
+    if len(sys.argv) > 1 and sys.argv[1] == "--copy-calibration":
+        copy_calibration(int(sys.argv[2]))
         return
     if len(sys.argv) > 1 and sys.argv[1] == "--summarize-trace":
         summarize_trace(sys.argv[2], sys.argv[3], " ".join(sys.argv[4:]))

@@ -264,11 +264,12 @@ dm_status dm_smoothed_backward(dm_ctx* ctx, const void* lambda, double temperatu
  *  out [device] double [nv]. */
 dm_status dm_mixed_areas(dm_ctx* ctx, const dm_mesh* M, double* out);
 
-/* Measurement hook: while enabled, every dual-sweep kernel launch made by
- * dm_dual_solve, dm_lower_bound and dm_round_primal is bracketed by a pair of
- * HIP events on the context's stream.  dm_timing_read synchronises the stream
- * and returns the number of timed launches and the sum of their durations in
- * milliseconds [host], then clears the record.  Off by default. */
+/* Measurement hook: while enabled, every dual-sweep kernel launch (of any
+ * entry point) carries a pair of HIP events that record the kernel's own
+ * start and end (hipExtLaunchKernelGGL) on the context's stream.
+ * dm_timing_read synchronises the stream and returns the number of timed
+ * launches and the sum of their durations in milliseconds [host], then
+ * clears the record.  Off by default. */
 dm_status dm_timing_enable(dm_ctx* ctx, int32_t enable);
 dm_status dm_timing_read(dm_ctx* ctx, int64_t* launches, double* total_ms);
 

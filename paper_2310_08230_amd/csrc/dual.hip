@@ -26,6 +26,8 @@
 // block each and reduce (min, argmin, second min) across the block.  With a
 // temperature T > 0 every min becomes the soft-min -T log sum exp(-./T); short
 // rows then run a partial-sum recursion with one lane per partial sum.
+#include <hip/hip_ext.h>
+
 #include <cmath>
 
 #include "dm_internal.h"
@@ -550,6 +552,17 @@ __global__ __launch_bounds__(256) void k_reduce_last(const double* partial, int 
   reduce_partials(partial, n, offset, out, red);
 }
 
+// one sweep launch; with timing events the launch records the kernel's own
+// start and end (hipExtLaunchKernelGGL), as a kernel trace does
+template <typename R, bool SOFT, int MODE>
+void launch_sweep(hipStream_t st, unsigned grid, hipEvent_t e0, hipEvent_t e1, const SweepArgs& A, const R* ri,
+                  R* ro, R omega, R T) {
+  if (e0)
+    hipExtLaunchKernelGGL(k_sweep<R, SOFT, MODE>, dim3(grid), dim3(256), 0, st, e0, e1, 0, A, ri, ro, omega, T);
+  else
+    k_sweep<R, SOFT, MODE><<<grid, 256, 0, st>>>(A, ri, ro, omega, T);
+}
+
 }  // namespace
 
 // ============================================================================
@@ -630,29 +643,29 @@ dm_status dual_sweep(dm_ctx* ctx, int mode, bool soft, const unsigned char* rin,
   A.n_items = int32_t(nblocks);
   // 8 XCDs x (projection-row blocks per XCD + chunks per XCD), see k_sweep
   const unsigned grid = unsigned(8 * ((n_long_blocks + 7) / 8 + (A.n_short_blocks + 7) / 8));
-  hipEvent_t ev_end = nullptr;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
   if (ctx->timing) {
     while (ctx->ev_pool.size() < ctx->ev_used + 2) {
       hipEvent_t e;
       DM_HIP(ctx, hipEventCreate(&e));
       ctx->ev_pool.push_back(e);
     }
-    DM_HIP(ctx, hipEventRecord(ctx->ev_pool[ctx->ev_used], ctx->stream));
-    ev_end = ctx->ev_pool[ctx->ev_used + 1];
+    e0 = ctx->ev_pool[ctx->ev_used];
+    e1 = ctx->ev_pool[ctx->ev_used + 1];
     ctx->ev_used += 2;
   }
+  hipStream_t st = ctx->stream;
   if (soft) {
-    if (mode == MODE_UPDATE) k_sweep<R, true, MODE_UPDATE><<<grid, 256, 0, ctx->stream>>>(A, ri, ro, omega, T);
-    else if (mode == MODE_EVAL) k_sweep<R, true, MODE_EVAL><<<grid, 256, 0, ctx->stream>>>(A, ri, ro, omega, T);
-    else k_sweep<R, true, MODE_BOUND><<<grid, 256, 0, ctx->stream>>>(A, ri, ro, omega, T);
+    if (mode == MODE_UPDATE) launch_sweep<R, true, MODE_UPDATE>(st, grid, e0, e1, A, ri, ro, omega, T);
+    else if (mode == MODE_EVAL) launch_sweep<R, true, MODE_EVAL>(st, grid, e0, e1, A, ri, ro, omega, T);
+    else launch_sweep<R, true, MODE_BOUND>(st, grid, e0, e1, A, ri, ro, omega, T);
   } else {
-    if (mode == MODE_UPDATE) k_sweep<R, false, MODE_UPDATE><<<grid, 256, 0, ctx->stream>>>(A, ri, ro, omega, T);
-    else if (mode == MODE_EVAL) k_sweep<R, false, MODE_EVAL><<<grid, 256, 0, ctx->stream>>>(A, ri, ro, omega, T);
-    else if (mode == MODE_BOUND) k_sweep<R, false, MODE_BOUND><<<grid, 256, 0, ctx->stream>>>(A, ri, ro, omega, T);
-    else k_sweep<R, false, MODE_SUBGRAD><<<grid, 256, 0, ctx->stream>>>(A, ri, ro, omega, T);
+    if (mode == MODE_UPDATE) launch_sweep<R, false, MODE_UPDATE>(st, grid, e0, e1, A, ri, ro, omega, T);
+    else if (mode == MODE_EVAL) launch_sweep<R, false, MODE_EVAL>(st, grid, e0, e1, A, ri, ro, omega, T);
+    else if (mode == MODE_BOUND) launch_sweep<R, false, MODE_BOUND>(st, grid, e0, e1, A, ri, ro, omega, T);
+    else launch_sweep<R, false, MODE_SUBGRAD>(st, grid, e0, e1, A, ri, ro, omega, T);
   }
   DM_LAUNCH_CHECK(ctx);
-  if (ev_end) DM_HIP(ctx, hipEventRecord(ev_end, ctx->stream));
   ctx->pend_half ^= 1;
   ctx->pend_partial = mine;
   ctx->pend_n = int32_t(nblocks);
