@@ -117,6 +117,7 @@ struct SweepArgs {
   int32_t n_rows;
   int32_t n_items;          // short-row blocks + long-row blocks
   int32_t n_chunks;         // wave chunks of short rows (hard form)
+  int32_t long_wpr;         // waves per projection row: 1 or 4
   double* partial;          // this launch's per-block partials
   const double* prev_partial; // previous launch's partials still to be summed, or NULL
   int32_t prev_n;
@@ -170,10 +171,9 @@ __device__ inline R permute_to(int dst_lane, R v) {   // push v to lane dst_lane
 }
 
 template <typename R, int MODE>
-__device__ void short_wave_hard(const SweepArgs& A, const R* __restrict__ rin, R* __restrict__ out, R omega,
-                                R gam, double* red, int32_t item) {
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int32_t wc = item * 4 + wave;
+__device__ inline double short_chunk_hard(const SweepArgs& A, const R* __restrict__ rin, R* __restrict__ out,
+                                          R omega, R gam, int32_t wc) {
+  const int lane = threadIdx.x & 63;
   double rowpart = 0.0;
   if (wc < A.n_chunks) {   // uniform across the wave
     const int4 d = A.chunk_desc[wc];
@@ -219,44 +219,79 @@ __device__ void short_wave_hard(const SweepArgs& A, const R* __restrict__ rin, R
       const R t = __shfl(pre, lane >= off ? lane - off : 0);
       if (lane - off >= seg) pre += t;
     }
-    // pre at lane (group start + k - 1) = S_group(k)
+    // pre at lane (group start + k - 1) = S_group(k).
+    // Choosing k of the own group and k - bb of the other costs
+    // f(k) = S_own(k) + S_oth(k - bb) for k in [klo, khi]; its increments
+    // o_k + q_{k-bb} (sorted values of the two groups) never decrease, so f is
+    // convex and its smallest minimiser is klo plus the number of negative
+    // increments.  The constrained minima of an entry at sorted position t are
+    // minima of two more convex sequences over ranges that depend on t:
+    //   A(k) = S_own(k-1) + S_oth(k-bb)  (increments o_{k-1} + q_{k-bb}),
+    //   B(k) = S_own(k+1) + S_oth(k-bb)  (increments o_{k+1} + q_{k-bb}),
+    // so they too come from counts of negative increments, clamped to the range.
+    // 1. sorted role: lane L holds the k-th smallest of its group
+    const int32_t j = lane - s;
+    const int gs = act && j >= P;
+    const int32_t ks = j - (gs ? P : 0) + 1;
+    const int32_t own_s = gs ? N : P, oth_s = gs ? P : N, bb_s = gs ? -b : b;
+    const int32_t klo_s = bb_s > 0 ? bb_s : 0;
+    const int32_t khi_s = own_s < oth_s + bb_s ? own_s : oth_s + bb_s;
+    const int32_t qi = s + (gs ? 0 : P) + (ks - bb_s) - 1;
+    const R qv = __shfl(srt, qi >= 0 && qi < 64 ? qi : 0);
+    const R om1 = __shfl(srt, lane > 0 ? lane - 1 : 0);
+    const R op1 = __shfl(srt, lane < 63 ? lane + 1 : 63);
+    const int32_t alo_s = klo_s > 1 ? klo_s : 1;
+    const int32_t bhi_s = khi_s < own_s - 1 ? khi_s : own_s - 1;
+    const unsigned long long mF = __ballot(act && ks > klo_s && ks <= khi_s && srt + qv < R(0));
+    const unsigned long long mA = __ballot(act && ks > alo_s && ks <= khi_s && om1 + qv < R(0));
+    const unsigned long long mB = __ballot(act && ks > klo_s && ks <= bhi_s && op1 + qv < R(0));
+    // 2. entry role: this lane's entry has own-group position t = rank + 1
     const int32_t own = g ? N : P, oth = g ? P : N, bb = g ? -b : b;
     const int32_t obase = s + (g ? P : 0), tbase = s + (g ? 0 : P);
     const int32_t klo = bb > 0 ? bb : 0;
     const int32_t khi = own < oth + bb ? own : oth + bb;
-    const int kmax = wave_max_i(act ? khi - klo + 1 : 0);
-    R m1 = rinf<R>(), m0 = rinf<R>(), rmin = rinf<R>();
-    int32_t kbest = 0;   // own-group count of the minimiser (smallest on ties)
-    for (int kk = 0; kk < kmax; ++kk) {
-      const int32_t k = klo + kk, ko = k - bb;
-      const int io = obase + k - 1, it = tbase + ko - 1, ix = k >= rank + 1 ? obase + k : obase + k - 2;
-      const R So = __shfl(pre, io >= 0 && io < 64 ? io : 0);
-      const R St = __shfl(pre, it >= 0 && it < 64 ? it : 0);
-      const R Sx = __shfl(pre, ix >= 0 && ix < 64 ? ix : 0);
-      if (!act || k > khi) continue;
-      const R so = k == 0 ? R(0) : So;
-      const R st = ko == 0 ? R(0) : St;
-      const R f = so + st;
-      if (f < rmin) {
-        rmin = f;
-        kbest = k;
-      }
-      if (MODE == MODE_SUBGRAD || MODE == MODE_BOUND) continue;
-      if (k >= rank + 1) {
-        // the k smallest of the own group include this entry
-        m1 = f < m1 ? f : m1;
-        if (k <= own - 1) {
-          const R v = (Sx - lam) + st;   // k+1 smallest, minus this entry
-          m0 = v < m0 ? v : m0;
-        }
+    const unsigned long long gmask = act ? (((own >= 64) ? ~0ull : ((1ull << own) - 1ull)) << obase) : 0ull;
+    const int32_t kbest = klo + __popcll(mF & gmask);   // smallest minimiser
+    auto s_own = [&](int32_t k) {   // every lane shuffles; k == 0 gives 0
+      const int i = obase + k - 1;
+      const R v = __shfl(pre, i >= 0 && i < 64 ? i : 0);
+      return k <= 0 ? R(0) : v;
+    };
+    auto s_oth = [&](int32_t k) {
+      const int i = tbase + k - 1;
+      const R v = __shfl(pre, i >= 0 && i < 64 ? i : 0);
+      return k <= 0 ? R(0) : v;
+    };
+    const R rmin = s_own(kbest) + s_oth(kbest - bb);
+    R m1 = rmin, m0 = rmin;
+    if (MODE == MODE_UPDATE || MODE == MODE_EVAL) {
+      const int32_t t = rank + 1;
+      const bool sel = t <= kbest;   // the minimiser takes this entry
+      // the other side's minimum: f at the nearest k on that side, and A or B
+      // at their convex minimiser clamped to the side's range
+      const int32_t x1 = sel ? t - 1 : t;
+      const bool c1ok = sel ? (t - 1 >= klo) : (t <= khi);
+      const R c1 = s_own(x1) + s_oth(x1 - bb);
+      int32_t lo2, hi2, kst;
+      if (sel) {
+        lo2 = t > klo ? t : klo;
+        hi2 = khi < own - 1 ? khi : own - 1;
+        kst = klo + __popcll(mB & gmask);
       } else {
-        m0 = f < m0 ? f : m0;
-        if (k >= 1) {
-          const R sp = k == 1 ? R(0) : Sx;   // k-1 smallest
-          const R v = (lam + sp) + st;
-          m1 = v < m1 ? v : m1;
-        }
+        lo2 = klo > 1 ? klo : 1;
+        hi2 = t - 1 < khi ? t - 1 : khi;
+        kst = lo2 + __popcll(mA & gmask);
       }
+      const bool c2ok = lo2 <= hi2;
+      const int32_t k2 = kst < lo2 ? lo2 : (kst > hi2 ? hi2 : kst);
+      const R so2 = s_own(sel ? k2 + 1 : k2 - 1);
+      const R st2 = s_oth(k2 - bb);
+      const R c2 = sel ? (so2 - lam) + st2 : (lam + so2) + st2;
+      R other = rinf<R>();
+      if (c1ok) other = c1;
+      if (c2ok && c2 < other) other = c2;
+      if (sel) m0 = other;
+      else m1 = other;
     }
     if (act) {
       const R M = m1 - m0;
@@ -267,6 +302,16 @@ __device__ void short_wave_hard(const SweepArgs& A, const R* __restrict__ rin, R
       if (lane == s) rowpart = double(rmin);
     }
   }
+  return rowpart;
+}
+
+// the four waves of a block take four adjacent chunks (one chunk per wave
+// keeps the most waves in flight; batching chunks per wave measured slower)
+template <typename R, int MODE>
+__device__ void short_wave_hard(const SweepArgs& A, const R* __restrict__ rin, R* __restrict__ out, R omega,
+                                R gam, double* red, int32_t item) {
+  const int wave = threadIdx.x >> 6;
+  const double rowpart = short_chunk_hard<R, MODE>(A, rin, out, omega, gam, item * 4 + wave);
   double part = block_sum(rowpart, red);
   store_partial(part, A.partial, item);
 }
@@ -385,54 +430,87 @@ __device__ inline MinState<R> ms_shfl_xor(MinState<R> v, int off) {
   return o;
 }
 
-// one wave per projection row, four rows per block; each lane keeps up to
-// LONG_REG of its row's multipliers in registers between the two passes
-constexpr int LONG_ROWS_PER_BLOCK = 4;
-constexpr int LONG_REG = 16;
+// one wave per projection row (four rows per block), or for long rows one
+// block per row (long_wpr = 4); each lane keeps up to LONG_REG of its row's
+// multipliers in registers between the two passes
+constexpr int LONG_REG = 8;
 
 template <typename R, bool SOFT, int MODE>
 __device__ void long_rows(const SweepArgs& A, const R* __restrict__ rin, R* __restrict__ out, R omega, R T,
                           R gam, double* red, int32_t item) {
+  __shared__ R xm[4], xm2[4], xs[4];
+  __shared__ int32_t xa[4];
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int32_t j = A.n_short + (item - A.n_short_blocks) * LONG_ROWS_PER_BLOCK + wave;
-  double rowpart = 0.0;
-  if (j < A.n_rows) {
-    const int32_t s = A.rrow_ptr[j], n = A.rrow_ptr[j + 1] - s;
-    MinState<R> st;
-    st.m = rinf<R>();
-    st.m2 = rinf<R>();
-    st.s = R(0);
-    st.a = INT32_MAX;
-    uint32_t wv[LONG_REG];
-    R lv[LONG_REG];
+  const int wpr = A.long_wpr;   // uniform
+  const int sub = wave & (wpr - 1);
+  const int32_t j = A.n_short + (item - A.n_short_blocks) * (4 / wpr) + wave / wpr;
+  const int32_t step = 64 * wpr, i0 = sub * 64 + lane;
+  const bool has = j < A.n_rows;
+  const int32_t s = has ? A.rrow_ptr[j] : 0;
+  const int32_t n = has ? A.rrow_ptr[j + 1] - s : 0;
+  MinState<R> st;
+  st.m = rinf<R>();
+  st.m2 = rinf<R>();
+  st.s = R(0);
+  st.a = INT32_MAX;
+  uint32_t wv[LONG_REG];
+  R lv[LONG_REG];
 #pragma unroll
-    for (int u = 0; u < LONG_REG; ++u) {
-      const int32_t i = lane + 64 * u;
-      wv[u] = i < n ? A.word[s + i] : 0u;
-    }
+  for (int u = 0; u < LONG_REG; ++u) {
+    const int32_t i = i0 + step * u;
+    wv[u] = i < n ? A.word[s + i] : 0u;
+  }
 #pragma unroll
-    for (int u = 0; u < LONG_REG; ++u) {
-      const int32_t i = lane + 64 * u;
-      lv[u] = R(0);
-      if (i < n) {
-        lv[u] = row_lambda<R>(A, rin, wv[u], gam);
-        MinState<R> one;
-        one.m = lv[u];
-        one.m2 = rinf<R>();
-        one.s = R(0);
-        one.a = i;
-        st = ms_combine<R, SOFT>(st, one, T);
-      }
-    }
-    for (int32_t i = lane + 64 * LONG_REG; i < n; i += 64) {   // rows longer than 64 * LONG_REG
+  for (int u = 0; u < LONG_REG; ++u) {
+    const int32_t i = i0 + step * u;
+    lv[u] = R(0);
+    if (i < n) {
+      lv[u] = row_lambda<R>(A, rin, wv[u], gam);
       MinState<R> one;
-      one.m = row_lambda<R>(A, rin, A.word[s + i], gam);
+      one.m = lv[u];
       one.m2 = rinf<R>();
       one.s = R(0);
       one.a = i;
       st = ms_combine<R, SOFT>(st, one, T);
     }
-    for (int off = 32; off > 0; off >>= 1) st = ms_combine<R, SOFT>(st, ms_shfl_xor<R, SOFT>(st, off), T);
+  }
+  for (int32_t i = i0 + step * LONG_REG; i < n; i += step) {   // rows longer than step * LONG_REG
+    MinState<R> one;
+    one.m = row_lambda<R>(A, rin, A.word[s + i], gam);
+    one.m2 = rinf<R>();
+    one.s = R(0);
+    one.a = i;
+    st = ms_combine<R, SOFT>(st, one, T);
+  }
+  for (int off = 32; off > 0; off >>= 1) st = ms_combine<R, SOFT>(st, ms_shfl_xor<R, SOFT>(st, off), T);
+  if (wpr > 1) {
+    // the row's waves combine their states in index order: every wave of
+    // the row ends with the same state
+    if (lane == 0) {
+      xm[wave] = st.m;
+      xm2[wave] = st.m2;
+      xs[wave] = st.s;
+      xa[wave] = st.a;
+    }
+    __syncthreads();
+    const int w0 = wave & ~(wpr - 1);
+    MinState<R> acc;
+    acc.m = xm[w0];
+    acc.m2 = xm2[w0];
+    acc.s = xs[w0];
+    acc.a = xa[w0];
+    for (int q = 1; q < wpr; ++q) {
+      MinState<R> o;
+      o.m = xm[w0 + q];
+      o.m2 = xm2[w0 + q];
+      o.s = xs[w0 + q];
+      o.a = xa[w0 + q];
+      acc = ms_combine<R, SOFT>(acc, o, T);
+    }
+    st = acc;
+  }
+  double rowpart = 0.0;
+  if (has) {
     R rowv = st.m;
     R tot = R(0);
     if (SOFT) {
@@ -462,15 +540,15 @@ __device__ void long_rows(const SweepArgs& A, const R* __restrict__ rin, R* __re
       };
 #pragma unroll
       for (int u = 0; u < LONG_REG; ++u) {
-        const int32_t i = lane + 64 * u;
+        const int32_t i = i0 + step * u;
         if (i < n) finish(i, wv[u], lv[u]);
       }
-      for (int32_t i = lane + 64 * LONG_REG; i < n; i += 64) {
+      for (int32_t i = i0 + step * LONG_REG; i < n; i += step) {
         const uint32_t w = A.word[s + i];
         finish(i, w, row_lambda<R>(A, rin, w, gam));
       }
     }
-    if (lane == 0) rowpart = double(rowv);
+    if (lane == 0 && sub == 0) rowpart = double(rowv);
   }
   double part = block_sum(rowpart, red);
   store_partial(part, A.partial, item);
@@ -552,6 +630,8 @@ __global__ __launch_bounds__(256) void k_reduce_last(const double* partial, int 
   reduce_partials(partial, n, offset, out, red);
 }
 
+constexpr int64_t LONG_BLOCK_ROW = 512;          // mean projection-row length for a block per row
+
 // one sweep launch; with timing events the launch records the kernel's own
 // start and end (hipExtLaunchKernelGGL), as a kernel trace does
 template <typename R, bool SOFT, int MODE>
@@ -612,7 +692,11 @@ dm_status dual_sweep(dm_ctx* ctx, int mode, bool soft, const unsigned char* rin,
   A.chunk_desc = ctx->chunk_desc.p;
   A.n_chunks = ctx->n_chunks;
   A.n_short_blocks = soft ? int32_t((ctx->n_short + 7) / 8) : int32_t((ctx->n_chunks + 3) / 4);
-  const int64_t n_long_blocks = (ctx->n_rows - ctx->n_short + LONG_ROWS_PER_BLOCK - 1) / LONG_ROWS_PER_BLOCK;
+  // projection rows of more than LONG_BLOCK_ROW entries on average get a whole block each
+  const int64_t n_long = ctx->n_rows - ctx->n_short;
+  A.long_wpr = (n_long > 0 && (ctx->nnz - ctx->nnz_short) / n_long > LONG_BLOCK_ROW) ? 4 : 1;
+  const int64_t rows_per_long_block = 4 / A.long_wpr;
+  const int64_t n_long_blocks = (n_long + rows_per_long_block - 1) / rows_per_long_block;
   A.n_short = int32_t(ctx->n_short);
   A.n_rows = int32_t(ctx->n_rows);
   A.dir = ext ? ext->dir : nullptr;
