@@ -191,5 +191,6 @@ extern "C" dm_status dm_build_costs(dm_ctx* ctx, const float* FX, const float* F
   DM_HIP(ctx, hipStreamSynchronize(st));
   ctx->cost_prec = prec;
   ctx->has_cost = true;
+  ++ctx->cost_generation;
   return DM_OK;
 }

@@ -80,6 +80,7 @@ constexpr int REC = 8;          // record stride: 5 multiplier slots, cost, 2 sp
 constexpr int REC_COST = 5;
 constexpr int MAX_SHORT_ROW = 64;
 constexpr int SOFT_MAX_ROW = 24;
+constexpr uint32_t CHUNK_PAD = 0xFFFFFFFFu;   // entry word of an unused chunk slot
 
 // Multipliers of free variable i from its record (slots 0-4 hold s_k, slot 5
 // the cost c_i), with dual feasibility restored: lambda_k = s_k + (c_i -
@@ -159,6 +160,9 @@ struct dm_ctx {
   DArr<uint8_t> var_deg;   // n_free
   int32_t n_chunks = 0;
   DArr<int4> chunk_desc;   // n_chunks wave chunks: (first row, rows, first entry, entries)
+  DArr<unsigned long long> chunk_mask;  // per chunk: bit e set when entry e starts a row
+  DArr<uint32_t> chunk_word;  // 64 per chunk: the chunk's entry words, CHUNK_PAD past its end
+  DArr<int8_t> chunk_b;       // 64 per chunk: right-hand side of each entry's row
 
   // costs
   bool has_cost = false;
@@ -192,8 +196,15 @@ struct dm_ctx {
   std::vector<hipEvent_t> ev_pool;
   size_t ev_used = 0;
 
+  // quasi-Newton session kept between dm_lbfgs_solve calls (history, step
+  // size, Delta_min), owned by lbfgs.hip; invalidated when the costs change
+  void* qn = nullptr;
+  void (*qn_free)(void*) = nullptr;
+  int64_t cost_generation = 0;
+
   ~dm_ctx() {
     for (hipEvent_t e : ev_pool) (void)hipEventDestroy(e);
+    if (qn && qn_free) qn_free(qn);
   }
 };
 

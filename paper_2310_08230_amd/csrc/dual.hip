@@ -112,6 +112,9 @@ struct SweepArgs {
   const int32_t* rrow_ptr;
   const int32_t* rrow_b;
   const int4* chunk_desc;   // (first row, rows, first entry, entries) per chunk
+  const unsigned long long* chunk_mask;   // bit e: entry e of the chunk starts a row
+  const uint32_t* chunk_word;   // 64 words per chunk, CHUNK_PAD past its end
+  const int8_t* chunk_b;        // 64 per chunk: right-hand side of the entry's row
   int32_t n_short_blocks;
   int32_t n_short;
   int32_t n_rows;
@@ -176,37 +179,43 @@ __device__ inline double short_chunk_hard(const SweepArgs& A, const R* __restric
   const int lane = threadIdx.x & 63;
   double rowpart = 0.0;
   if (wc < A.n_chunks) {   // uniform across the wave
-    const int4 d = A.chunk_desc[wc];
-    const int32_t r0 = d.x, nrow = d.y, e0 = d.z, ne = d.w;
-    // lane r < nrow: start of row r (relative), lane nrow: ne, others 64
-    int32_t rstart = lane < nrow ? A.rrow_ptr[r0 + lane] - e0 : (lane == nrow ? ne : 64);
-    const int32_t rb = lane < nrow ? A.rrow_b[r0 + lane] : 0;
-    const bool act = lane < ne;
-    const uint32_t w = act ? A.word[e0 + lane] : 0u;
+    // the padded chunk: words and right-hand sides straight from the chunk index
+    const unsigned long long starts = A.chunk_mask[wc];
+    const uint32_t wp = A.chunk_word[size_t(wc) * 64 + lane];
+    const int32_t b = A.chunk_b[size_t(wc) * 64 + lane];
+    const bool act = wp != CHUNK_PAD;
+    const uint32_t w = act ? wp : 0u;
+    const int32_t ne = __popcll(__ballot(act));
     const R lam = act ? row_lambda<R>(A, rin, w, gam) : R(0);
     const int g = int(w >> 31);
-    // my row: the last row whose start <= lane (rows have >= 2 entries, so nrow <= 32)
-    int32_t myrow = 0;
-    for (int step = 16; step > 0; step >>= 1) {
-      const int32_t cand = myrow + step;
-      const int32_t sc = __shfl(rstart, cand < 64 ? cand : 63);
-      if (cand < nrow && sc <= lane) myrow = cand;
-    }
-    const int32_t s = __shfl(rstart, myrow);
-    const int32_t n = __shfl(rstart, myrow + 1) - s;
-    const int32_t b = __shfl(rb, myrow);
+    // my row from the chunk's row-start mask: its start is the last set bit at
+    // or below this lane, its end the next set bit (or the chunk's end)
+    const unsigned long long le = lane == 63 ? ~0ull : ((2ull << lane) - 1ull);
+    const unsigned long long below = starts & le, above = starts & ~le;
+    const int32_t s = 63 - __clzll(static_cast<long long>(below));   // entry 0 always starts a row
+    const int32_t n = (above ? __ffsll(static_cast<long long>(above)) - 1 : ne) - s;
+
     const unsigned long long negm = __ballot(act && g);
     const unsigned long long rowm = act ? (((n >= 64) ? ~0ull : ((1ull << n) - 1ull)) << s) : 0ull;
     const int32_t P = __popcll(rowm & ~negm);
     const int32_t N = n - P;
     // rank of this entry in its sign group (ties broken by lane)
     const int nmax = wave_max_i(act ? n : 0);
+    // (four independent shuffles per step, so their latencies overlap)
     int32_t rank = 0;
-    for (int q = 0; q < nmax; ++q) {
-      const int src = s + q;
-      const R lq = __shfl(lam, src < 64 ? src : 63);
-      const int gq = int((negm >> (src & 63)) & 1ull);
-      if (act && q < n && gq == g) rank += (lq < lam) || (lq == lam && src < lane);
+    for (int q = 0; q < nmax; q += 4) {
+      R lq[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int src = s + q + u;
+        lq[u] = __shfl(lam, src < 64 ? src : 63);
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int src = s + q + u;
+        const int gq = int((negm >> (src & 63)) & 1ull);
+        if (act && q + u < n && gq == g) rank += (lq[u] < lam) || (lq[u] == lam && src < lane);
+      }
     }
     // sorted position: positive group first, then negative group
     const int dst = act ? s + (g ? P + rank : rank) : lane;
@@ -690,6 +699,9 @@ dm_status dual_sweep(dm_ctx* ctx, int mode, bool soft, const unsigned char* rin,
   A.rrow_ptr = ctx->rrow_ptr.p;
   A.rrow_b = ctx->rrow_b.p;
   A.chunk_desc = ctx->chunk_desc.p;
+  A.chunk_mask = ctx->chunk_mask.p;
+  A.chunk_word = ctx->chunk_word.p;
+  A.chunk_b = ctx->chunk_b.p;
   A.n_chunks = ctx->n_chunks;
   A.n_short_blocks = soft ? int32_t((ctx->n_short + 7) / 8) : int32_t((ctx->n_chunks + 3) / 4);
   // projection rows of more than LONG_BLOCK_ROW entries on average get a whole block each

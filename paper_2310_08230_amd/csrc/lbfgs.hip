@@ -272,17 +272,21 @@ __global__ __launch_bounds__(VB) void k_qn_pair_fin(const double* part_sy, const
 }
 
 // ---------------------------------------------------------------- one-block decisions
+// start of a call: the bound at the imported lambda; a fresh search also
+// resets the step size and Delta_min (a resumed one keeps them)
 __global__ __launch_bounds__(VB) void k_qn_begin(const double* sp, int32_t sn, double offset, QnState* st,
-                                                 double* etrace, double gamma0) {
+                                                 double* etrace, double gamma0, int32_t resume) {
   __shared__ double red[4];
   const double E = offset + sum_partials(sp, sn, red);
   if (threadIdx.x == 0) {
     etrace[0] = E;
+    if (!resume) {
+      st->E0 = E;
+      st->dmin = INFINITY;
+      st->gamma = gamma0;
+      st->gm = gamma0;
+    }
     st->E_init = E;
-    st->E0 = E;
-    st->dmin = INFINITY;
-    st->gamma = gamma0;
-    st->gm = gamma0;
     st->Em = -INFINITY;
     st->step = 0.0;
     st->done = 0;
@@ -319,16 +323,16 @@ __global__ __launch_bounds__(VB) void k_qn_probe(const double* sp, int32_t sn, d
 // after the subgradient sweep at lambda_{k+1} and the history pass: the bound
 // E(lambda_{k+1}), Delta_min after the first iteration, the curvature test
 __global__ __launch_bounds__(VB) void k_qn_hist(const double* sp, int32_t sn, double offset, const double* part_sy,
-                                                const double* part_yy, int32_t hn, int32_t k, double eps,
-                                                QnState* st, double* etrace, double* sy_out, double* yy_out,
-                                                int32_t* accepted) {
+                                                const double* part_yy, int32_t hn, int32_t k, int32_t set_dmin,
+                                                double eps, QnState* st, double* etrace, double* sy_out,
+                                                double* yy_out, int32_t* accepted) {
   __shared__ double red[4];
   const double E = offset + sum_partials(sp, sn, red);
   const double sy = sum_partials(part_sy, hn, red);
   const double yy = sum_partials(part_yy, hn, red);
   if (threadIdx.x != 0) return;
   etrace[k + 1] = E;
-  if (k == 0) st->dmin = 1e-6 * (E - st->E0);
+  if (set_dmin) st->dmin = 1e-6 * (E - st->E0);
   st->E_init = E;
   st->done = 0;
   st->Em = -INFINITY;
@@ -450,6 +454,37 @@ dm_status qn_alloc(dm_ctx* ctx, int nb, QnBuffers<R>& B) {
   return DM_OK;
 }
 
+// search state kept on the context between calls (history pairs, step size,
+// Delta_min), one per message precision
+template <typename R>
+struct QnSession {
+  QnBuffers<R> B;
+  DArr<QnState> st;
+  DArr<int32_t> flag;
+  std::vector<int> order;   // accepted pairs, oldest first
+  int spare = 0;            // buffer of the next candidate pair
+  int m = -1;
+  int64_t n_free = -1, generation = -1;
+};
+
+struct QnSessions {
+  QnSession<float> f32;
+  QnSession<double> f64;
+};
+
+void qn_delete(void* p) { delete static_cast<QnSessions*>(p); }
+
+template <typename R>
+QnSession<R>& session(dm_ctx* ctx) {
+  if (!ctx->qn) {
+    ctx->qn = new QnSessions;
+    ctx->qn_free = qn_delete;
+  }
+  QnSessions* q = static_cast<QnSessions*>(ctx->qn);
+  if constexpr (sizeof(R) == 4) return q->f32;
+  else return q->f64;
+}
+
 template <typename R>
 dm_status lbfgs_impl(dm_ctx* ctx, int32_t iters, const dm_lbfgs_params& P, R* lam, double* lb_trace,
                      double* gamma_trace, int32_t* taken) {
@@ -464,14 +499,26 @@ dm_status lbfgs_impl(dm_ctx* ctx, int32_t iters, const dm_lbfgs_params& P, R* la
   }
   const int m = P.history;
   const int nb = m + 1;   // m history pairs and one candidate
-  QnBuffers<R> B;
-  DM_TRY(qn_alloc<R>(ctx, nb, B));
+  QnSession<R>& S = session<R>(ctx);
+  const bool resume = P.resume != 0 && S.m == m && S.n_free == ctx->n_free &&
+                      S.generation == ctx->cost_generation;
+  if (P.resume != 0 && !resume)
+    return dm_fail(ctx, DM_ERR_STATE,
+                   "resume needs an earlier dm_lbfgs_solve on the same costs with the same precision and history");
+  if (!resume) {
+    DM_TRY(qn_alloc<R>(ctx, nb, S.B));
+    DM_ALLOC(ctx, S.st, 1);
+    DM_ALLOC(ctx, S.flag, 1);
+    S.order.clear();
+    S.spare = 0;
+    S.m = m;
+    S.n_free = ctx->n_free;
+    S.generation = ctx->cost_generation;
+  }
+  QnBuffers<R>& B = S.B;
+  QnState* st = S.st.p;
   DArr<double> etrace;
-  DArr<QnState> st;
-  DArr<int32_t> flag;
   DM_ALLOC(ctx, etrace, size_t(iters) + 1);
-  DM_ALLOC(ctx, st, 1);
-  DM_ALLOC(ctx, flag, 1);
   const Scal sc{B.scal.p, nb};
   const int64_t n = ctx->n_free;
   const unsigned G = vgrid(n);
@@ -481,26 +528,25 @@ dm_status lbfgs_impl(dm_ctx* ctx, int32_t iters, const dm_lbfgs_params& P, R* la
   SweepExt sub;
   sub.gsub = B.g[0].p;
   DM_TRY(dual_sweep<R>(ctx, SWEEP_SUBGRAD, false, ctx->rec[0].p, nullptr, R(0), R(0), nullptr, &sub));
-  k_qn_begin<<<1, VB, 0, stream>>>(ctx->pend_partial, ctx->pend_n, ctx->offset, st.p, etrace.p, P.gamma0);
+  k_qn_begin<<<1, VB, 0, stream>>>(ctx->pend_partial, ctx->pend_n, ctx->offset, st, etrace.p, P.gamma0,
+                                   resume ? 1 : 0);
   DM_LAUNCH_CHECK(ctx);
-  std::vector<int> order;   // accepted pairs, oldest first
-  int spare = 0;
   for (int32_t k = 0; k < iters; ++k) {
-    DM_TRY(direction<R>(ctx, order, B.Sp.data(), B.Yp.data(), B.g[gc].p, B.q.p, sc, B.part.p));
+    DM_TRY(direction<R>(ctx, S.order, B.Sp.data(), B.Yp.data(), B.g[gc].p, B.q.p, sc, B.part.p));
     SweepExt pe;
     pe.dir = B.q.p;
-    pe.gamma = &st.p->gamma;
-    pe.skip = &st.p->done;
+    pe.gamma = &st->gamma;
+    pe.skip = &st->done;
     for (int t = 0; t <= P.max_search; ++t) {
       DM_TRY(dual_sweep<R>(ctx, SWEEP_BOUND, false, ctx->rec[cur].p, nullptr, R(0), R(0), nullptr, &pe));
       k_qn_probe<<<1, VB, 0, stream>>>(ctx->pend_partial, ctx->pend_n, ctx->offset, t, P.max_search, P.step_up,
-                                       P.step_down, st.p, gamma_trace ? gamma_trace + k : nullptr,
+                                       P.step_down, st, gamma_trace ? gamma_trace + k : nullptr,
                                        taken ? taken + k : nullptr);
       DM_LAUNCH_CHECK(ctx);
     }
     SweepExt me;
     me.dir = B.q.p;
-    me.gamma = &st.p->step;
+    me.gamma = &st->step;
     DM_TRY(dual_sweep<R>(ctx, SWEEP_UPDATE, false, ctx->rec[cur].p, ctx->rec[cur ^ 1].p, R(P.omega), R(0),
                          nullptr, &me));
     sub.gsub = B.g[gc ^ 1].p;
@@ -509,29 +555,31 @@ dm_status lbfgs_impl(dm_ctx* ctx, int32_t iters, const dm_lbfgs_params& P, R* la
     const int32_t sn = ctx->pend_n;
     double* psy = B.part.p + 2 * VGRID;
     double* pyy = B.part.p + 3 * VGRID;
+    const int spare = S.spare;
     if (m > 0)
       k_qn_hist_pass<R><<<G, VB, 0, stream>>>(reinterpret_cast<const R*>(ctx->rec[cur].p),
                                                reinterpret_cast<const R*>(ctx->rec[cur ^ 1].p), B.g[gc].p,
                                                B.g[gc ^ 1].p, ctx->var_deg.p, n, B.Sp[spare], B.Yp[spare], psy,
                                                pyy);
-    k_qn_hist<<<1, VB, 0, stream>>>(sp, sn, ctx->offset, psy, pyy, m > 0 ? int32_t(G) : 0, k, P.eps, st.p,
-                                    etrace.p, sc.sy(spare), sc.yy(spare), flag.p);
+    k_qn_hist<<<1, VB, 0, stream>>>(sp, sn, ctx->offset, psy, pyy, m > 0 ? int32_t(G) : 0, k,
+                                    (k == 0 && !resume) ? 1 : 0, P.eps, st, etrace.p, sc.sy(spare),
+                                    sc.yy(spare), S.flag.p);
     DM_LAUNCH_CHECK(ctx);
     cur ^= 1;
     gc ^= 1;
     if (m > 0) {
       int32_t ok = 0;
-      DM_HIP(ctx, hipMemcpyAsync(&ok, flag.p, sizeof(int32_t), hipMemcpyDeviceToHost, stream));
+      DM_HIP(ctx, hipMemcpyAsync(&ok, S.flag.p, sizeof(int32_t), hipMemcpyDeviceToHost, stream));
       DM_HIP(ctx, hipStreamSynchronize(stream));
       if (ok) {
-        order.push_back(spare);
-        if (int(order.size()) > m) {
-          spare = order.front();
-          order.erase(order.begin());
+        S.order.push_back(spare);
+        if (int(S.order.size()) > m) {
+          S.spare = S.order.front();
+          S.order.erase(S.order.begin());
         } else {
           for (int b = 0; b < nb; ++b)
-            if (std::find(order.begin(), order.end(), b) == order.end()) {
-              spare = b;
+            if (std::find(S.order.begin(), S.order.end(), b) == S.order.end()) {
+              S.spare = b;
               break;
             }
         }
@@ -542,7 +590,7 @@ dm_status lbfgs_impl(dm_ctx* ctx, int32_t iters, const dm_lbfgs_params& P, R* la
     DM_HIP(ctx, hipMemcpyAsync(lb_trace, etrace.p, (size_t(iters) + 1) * sizeof(double), hipMemcpyDeviceToDevice,
                                stream));
   DM_TRY(dual_export<R>(ctx, ctx->rec[cur].p, lam));
-  // the work buffers are freed on return: wait for the queued work first
+  // the per-call trace buffer is freed on return: wait for the queued work
   DM_HIP(ctx, hipStreamSynchronize(stream));
   return DM_OK;
 }

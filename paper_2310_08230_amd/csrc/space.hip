@@ -524,6 +524,36 @@ __global__ void k_seg_rows(const int32_t* rrow_ptr, int64_t n_short, int32_t n_s
 
 // fill == false: count the wave chunks of each segment; fill == true: write
 // their (first row, rows, first entry, entries) at the scanned offsets
+// per chunk, the positions (relative to its first entry) where its rows start
+__global__ void k_chunk_mask(const int4* desc, const int32_t* rrow_ptr, int32_t n_chunks,
+                             unsigned long long* mask) {
+  const int32_t c = int32_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (c >= n_chunks) return;
+  const int4 d = desc[c];
+  unsigned long long m = 0ull;
+  for (int32_t r = 0; r < d.y; ++r) m |= 1ull << (rrow_ptr[d.x + r] - d.z);
+  mask[c] = m;
+}
+
+// padded copy of every chunk: 64 entry words (CHUNK_PAD past the chunk's end)
+// and the right-hand side of each entry's row, so that a wave reads its
+// entries without first reading the chunk descriptor
+__global__ void k_chunk_pad(const int4* desc, const unsigned long long* mask, const uint32_t* word,
+                            const int32_t* rrow_b, int32_t n_chunks, uint32_t* pword, int8_t* pb) {
+  const int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (t >= int64_t(n_chunks) * 64) return;
+  const int32_t c = int32_t(t >> 6), e = int32_t(t & 63);
+  const int4 d = desc[c];
+  if (e < d.w) {
+    const unsigned long long below = mask[c] & (e == 63 ? ~0ull : ((2ull << e) - 1ull));
+    pword[t] = word[d.z + e];
+    pb[t] = int8_t(rrow_b[d.x + __popcll(below) - 1]);
+  } else {
+    pword[t] = CHUNK_PAD;
+    pb[t] = 0;
+  }
+}
+
 __global__ void k_pack(const int32_t* seg_row, const int32_t* rrow_ptr, int32_t n_seg, int32_t* count,
                        const int32_t* offset, int4* desc, int fill) {
   int32_t j = int32_t(blockIdx.x) * blockDim.x + threadIdx.x;
@@ -814,6 +844,16 @@ dm_status space_build(dm_ctx* ctx, const int32_t* cand_xy, const int32_t* cand_y
   if (n_seg > 0)
     k_pack<<<grid_for(n_seg, 64), 64, 0, st>>>(seg_row.p, ctx->rrow_ptr.p, n_seg, nullptr, seg_off.p,
                                                ctx->chunk_desc.p, 1);
+  DM_ALLOC(ctx, ctx->chunk_mask, size_t(std::max(n_chunks, 1)));
+  if (n_chunks > 0)
+    k_chunk_mask<<<grid_for(n_chunks, 256), 256, 0, st>>>(ctx->chunk_desc.p, ctx->rrow_ptr.p, n_chunks,
+                                                          ctx->chunk_mask.p);
+  DM_ALLOC(ctx, ctx->chunk_word, size_t(std::max(n_chunks, 1)) * 64);
+  DM_ALLOC(ctx, ctx->chunk_b, size_t(std::max(n_chunks, 1)) * 64);
+  if (n_chunks > 0)
+    k_chunk_pad<<<grid_for(int64_t(n_chunks) * 64, 256), 256, 0, st>>>(
+        ctx->chunk_desc.p, ctx->chunk_mask.p, ctx->rent_word.p, ctx->rrow_b.p, n_chunks, ctx->chunk_word.p,
+        ctx->chunk_b.p);
   DM_LAUNCH_CHECK(ctx);
   DM_HIP(ctx, hipStreamSynchronize(st));
   return DM_OK;
