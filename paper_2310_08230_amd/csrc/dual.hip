@@ -443,6 +443,7 @@ __device__ inline MinState<R> ms_shfl_xor(MinState<R> v, int off) {
 // block per row (long_wpr = 4); each lane keeps up to LONG_REG of its row's
 // multipliers in registers between the two passes
 constexpr int LONG_REG = 8;
+constexpr int32_t LONG_GROUP = 8;   // consecutive projection-row blocks per XCD turn
 
 template <typename R, bool SOFT, int MODE>
 __device__ void long_rows(const SweepArgs& A, const R* __restrict__ rin, R* __restrict__ out, R omega, R T,
@@ -578,14 +579,18 @@ __global__ __launch_bounds__(256) void k_sweep(SweepArgs A, const R* __restrict_
   const R gam = A.gamma ? R(*A.gamma) : R(0);
   // Workgroups are dealt to the 8 XCDs round-robin (block b runs on XCD b % 8).
   // Each XCD takes a contiguous range of short-row chunks, so rows that share
-  // variables share one L2, and every eighth projection-row block; the heavier
+  // variables share one L2, and projection-row blocks in groups of LONG_GROUP
+  // consecutive blocks (consecutive projection rows of one shape gather
+  // neighbouring records), group g of them on XCD g % 8; the heavier
   // projection-row blocks come first on each XCD.
   const int32_t x = int32_t(blockIdx.x % 8u), k = int32_t(blockIdx.x / 8u);
   const int32_t n_long_blocks = A.n_items - A.n_short_blocks;
-  const int32_t lx = n_long_blocks > x ? (n_long_blocks - x + 7) / 8 : 0;
+  const int32_t lx = (n_long_blocks + 8 * LONG_GROUP - 1) / (8 * LONG_GROUP) * LONG_GROUP;
   int32_t item;
   if (k < lx) {
-    item = A.n_short_blocks + k * 8 + x;
+    const int32_t li = ((k / LONG_GROUP) * 8 + x) * LONG_GROUP + k % LONG_GROUP;
+    if (li >= n_long_blocks) return;
+    item = A.n_short_blocks + li;
   } else {
     const int32_t pc = (A.n_short_blocks + 7) / 8;
     const int32_t c = x * pc + (k - lx);
@@ -738,7 +743,8 @@ dm_status dual_sweep(dm_ctx* ctx, int mode, bool soft, const unsigned char* rin,
   R* ro = reinterpret_cast<R*>(out);
   A.n_items = int32_t(nblocks);
   // 8 XCDs x (projection-row blocks per XCD + chunks per XCD), see k_sweep
-  const unsigned grid = unsigned(8 * ((n_long_blocks + 7) / 8 + (A.n_short_blocks + 7) / 8));
+  const int64_t long_slots = (n_long_blocks + 8 * LONG_GROUP - 1) / (8 * LONG_GROUP) * LONG_GROUP;
+  const unsigned grid = unsigned(8 * (long_slots + (A.n_short_blocks + 7) / 8));
   hipEvent_t e0 = nullptr, e1 = nullptr;
   if (ctx->timing) {
     while (ctx->ev_pool.size() < ctx->ev_used + 2) {
