@@ -401,8 +401,12 @@ int build_space(Space& S, const int* cand_xy, const int* cand_yx, int K) {
 // whose entries are all fixed are dropped; a row whose residual lies outside
 // [-N, P] proves the ILP infeasible.
 // ---------------------------------------------------------------------------
-int presolve(Space& S) {
+// fix: optional starting assignment per element (-1 free, 0 / 1 fixed), the
+// confident-variable fixing of the coarse-to-fine appendix
+int presolve(Space& S, const int8_t* fix = nullptr) {
   S.state.assign(size_t(S.nP), -1);
+  if (fix)
+    for (int64_t p = 0; p < S.nP; ++p) S.state[p] = fix[p] < 0 ? int8_t(-1) : int8_t(fix[p] ? 1 : 0);
   bool changed = true;
   while (changed) {
     changed = false;
@@ -1144,6 +1148,63 @@ int or_lbfgs_solve(void* h, int iters, double omega, int m, int K, double eps, d
   }
   if (trace_E) trace_E[iters] = E_now;
   std::copy(L.begin(), L.end(), lam);
+  return OK;
+}
+
+// Confident-variable fixing (Appendix "Coarse-to-fine solving strategy"): at
+// lambda, the min-marginal differences M^j_i of every free variable; a
+// variable agrees when all its M^j_i are < 0 (prefers 1) or all > 0 (prefers
+// 0); the agreeing variables are ranked by |sum_j M^j_i| (sum over its rows in
+// ascending row order; ties to the lower variable) and the top
+// floor(frac * count) are fixed to their preferred values.  fix[p] gets the
+// presolve state of fixed elements, the new fixings, and -1 elsewhere.
+// Returns the number of newly fixed variables in *n_fixed and the number of
+// agreeing ones in *n_agree.
+int or_confident_fix(void* h, const double* lam, double frac, int8_t* fix, int64_t* n_agree, int64_t* n_fixed) {
+  Space& S = *static_cast<Space*>(h);
+  if (!S.has_cost || !(frac >= 0.0 && frac <= 1.0)) return E_ARG;
+  const size_t nnz = S.rent_var.size();
+  std::vector<double> M(nnz);
+  sweep(S, lam, 0.0, M.data(), nullptr, nullptr);
+  struct Cand {
+    double score;
+    int64_t var;
+    int8_t value;
+  };
+  std::vector<Cand> agree;
+  for (size_t i = 0; i < S.free_var.size(); ++i) {
+    bool neg = true, pos = true;
+    double sum = 0.0;
+    for (int64_t e : S.var_ents[i]) {
+      neg = neg && M[e] < 0.0;
+      pos = pos && M[e] > 0.0;
+      sum += M[e];
+    }
+    if (neg || pos) agree.push_back({std::fabs(sum), int64_t(i), int8_t(neg ? 1 : 0)});
+  }
+  std::sort(agree.begin(), agree.end(), [](const Cand& a, const Cand& b) {
+    return a.score > b.score || (a.score == b.score && a.var < b.var);
+  });
+  const size_t take = size_t(std::floor(frac * double(agree.size())));
+  for (int64_t p = 0; p < S.nP; ++p) fix[p] = S.state[p];
+  for (size_t k = 0; k < take; ++k) fix[S.free_var[agree[k].var]] = agree[k].value;
+  if (n_agree) *n_agree = int64_t(agree.size());
+  if (n_fixed) *n_fixed = int64_t(take);
+  return OK;
+}
+
+// Re-run presolve from the given fixings (NULL: none, the original problem)
+// and rebuild the reduced problem on the residual; the constant of variables
+// fixed to 1 follows.
+int or_fix_variables(void* h, const int8_t* fix) {
+  Space& S = *static_cast<Space*>(h);
+  const int st = presolve(S, fix);
+  if (st != OK) return st;
+  if (S.has_cost) {
+    S.offset = 0.0;
+    for (int64_t p = 0; p < S.nP; ++p)
+      if (S.state[p] == 1) S.offset += S.cost[p];
+  }
   return OK;
 }
 

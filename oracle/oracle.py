@@ -59,6 +59,8 @@ def lib():
                                      C.c_double, C.c_double, C.c_double, P, P, P, P]
         L.or_subgradient.argtypes = [P, P, P]
         L.or_project_feasible.argtypes = [P, P]
+        L.or_confident_fix.argtypes = [P, P, C.c_double, P, P, P]
+        L.or_fix_variables.argtypes = [P, P]
         L.or_lbfgs_direction.argtypes = [C.c_int, C.c_int, P, P, P, P]
         L.or_find_step_parabola.argtypes = [C.c_double, C.c_double, C.c_int, C.c_double,
                                             C.c_double, C.c_double, P]
@@ -176,11 +178,14 @@ class Space:
                                       C.byref(st))
         if not self.h:
             raise OracleError(st.value)
-        info = np.zeros(8, np.int64)
-        lib().or_space_info(self.h, _p(info))
-        self.info = dict(zip(self.INFO, (int(x) for x in info)))
+        self.info = self._read_info()
         self.nvx, self.nvy = len(VX), len(VY)
         self.nfx, self.nfy = len(FX), len(FY)
+
+    def _read_info(self):
+        info = np.zeros(8, np.int64)
+        lib().or_space_info(self.h, _p(info))
+        return dict(zip(self.INFO, (int(x) for x in info)))
 
     def __del__(self):
         if getattr(self, "h", None):
@@ -279,6 +284,27 @@ class Space:
         g = np.zeros(self.info["nnz"])
         lib().or_subgradient(self.h, _p(lam), _p(g))
         return g
+
+    def confident_fix(self, lam, frac=0.9):
+        """Fixings of the coarse-to-fine appendix: per element -1 (free) or the
+        value it is fixed to (presolve fixings and the newly fixed confident
+        variables); also the numbers of agreeing and of newly fixed variables."""
+        lam = _c(lam, np.float64)
+        fix = np.zeros(self.info["nP"], np.int8)
+        na, nf = C.c_int64(0), C.c_int64(0)
+        st = lib().or_confident_fix(self.h, _p(lam), float(frac), _p(fix), C.byref(na), C.byref(nf))
+        if st:
+            raise OracleError(st)
+        return fix, na.value, nf.value
+
+    def fix_variables(self, fix=None):
+        """Re-presolve from the fixings (None: the original problem); the
+        reduced problem becomes the residual one."""
+        f = None if fix is None else _c(fix, np.int8)
+        st = lib().or_fix_variables(self.h, _p(f) if f is not None else None)
+        if st:
+            raise OracleError(st)
+        self.info = self._read_info()
 
     def project_feasible(self, d):
         """Subtract from every entry the mean over its variable's entries."""

@@ -433,3 +433,89 @@ def test_feasibility_projection_is_orthogonal():
     assert np.allclose(S.project_feasible(e), e, atol=1e-15)
     f = S.project_feasible(rng.normal(size=S.info["nnz"]))
     assert abs((d - e) @ f) < 1e-10
+
+
+# ---------------------------------------------------------------------------
+# Confident-variable fixing (Appendix "Coarse-to-fine solving strategy")
+# ---------------------------------------------------------------------------
+def test_confident_selection_from_min_marginals():
+    """The oracle's fixings equal a selection recomputed with numpy from its
+    min-marginals: agreeing variables (all M < 0 or all M > 0), ranked by
+    |sum_j M| with ties to the lower variable, the top floor(0.9 n) fixed."""
+    S = _space(make_pair(1, 0, desc_noise=0.5), 16)
+    lam, _, _, _ = S.lbfgs_solve(20)
+    M, _, _ = S.min_marginals(lam)
+    rv = S.get("rent_var")
+    n = S.info["n_free"]
+    neg = np.bincount(rv, weights=(M < 0), minlength=n) == np.bincount(rv, minlength=n)
+    pos = np.bincount(rv, weights=(M > 0), minlength=n) == np.bincount(rv, minlength=n)
+    score = np.abs(np.bincount(rv, weights=M, minlength=n))
+    agree = np.nonzero(neg | pos)[0]
+    order = agree[np.lexsort((agree, -score[agree]))]
+    take = int(np.floor(0.9 * len(agree)))
+    ref = S.get("state").astype(np.int8).copy()
+    fv = S.get("free_var")
+    ref[fv[order[:take]]] = np.where(neg[order[:take]], 1, 0)
+    fix, na, nf = S.confident_fix(lam, 0.9)
+    assert na == len(agree) and nf == take
+    assert np.array_equal(fix, ref)
+
+
+@pytest.mark.parametrize("kind,K,dn", [("tetra", 2, 0.3), ("octa", 3, 0.3)])
+def test_fixed_residual_keeps_exactly_the_matching_solutions(kind, K, dn):
+    """After fixing some variables to the values of one feasible solution, the
+    residual problem's solutions are exactly the original solutions that agree
+    with the fixings (exhaustive enumeration on both)."""
+    p = tiny_pair(kind, kind, 8, 3, 0.01, dn)
+    cxy, cyx = O.knn(p.DX, p.DY, K)
+    S = O.Space(p.VX, p.FX, p.VY, p.FY, cxy, cyx)
+    S.costs(p.DX, p.DY)
+
+    def solutions():
+        rows = reduced_rows(S)
+        sols = enumerate_ilp(rows, S.info["n_free"], np.zeros(S.info["n_free"]), limit=200000)[3]
+        fv, state = S.get("free_var"), S.get("state")
+        full = []
+        for x in sols:
+            y = (state == 1).astype(np.int8)
+            y[fv] = x
+            full.append(y)
+        return full
+    all_sols = solutions()
+    assert len(all_sols) >= 1
+    rng = np.random.default_rng(0)
+    ref = all_sols[rng.integers(len(all_sols))]
+    fv = S.get("free_var")
+    pick = rng.choice(fv, size=max(1, len(fv) // 3), replace=False)
+    fix = S.get("state").astype(np.int8).copy()
+    fix[pick] = ref[pick]
+    S.fix_variables(fix)
+    got = {tuple(x) for x in solutions()}
+    want = {tuple(x) for x in all_sols if np.array_equal(x[pick], ref[pick])}
+    assert got == want
+    S.fix_variables(None)
+    assert {tuple(x) for x in solutions()} == {tuple(x) for x in all_sols}
+
+
+def test_fix_and_solve_residual_reaches_the_optimum():
+    """On an LP-tight pair, fixing 90 % of the agreeing variables and solving
+    the residual with the same dual + rounding gives the ILP optimum (HiGHS)."""
+    S = _space(make_pair(1, 0, desc_noise=0.5), 16)
+    ilp = _lp_ilp(S, integral=True)
+    lam, tE, _, _ = S.lbfgs_solve(60)
+    fix, na, nf = S.confident_fix(lam, 0.9)
+    S.fix_variables(fix)
+    assert S.info["n_free"] < 0.2 * na
+    lam2, _ = S.dual_solve(100)
+    x, p, feas, _ = S.round(lam2)
+    assert feas and S.check_primal(x) == 0
+    assert abs(p - ilp) <= 1e-9 * abs(ilp)
+    S.fix_variables(None)
+
+
+def test_infeasible_fixings_are_reported():
+    S = _space(make_pair(1, 0, desc_noise=1.0), 16)
+    lam, _, _, _ = S.lbfgs_solve(60)
+    fix, _, _ = S.confident_fix(lam, 0.9)
+    with pytest.raises(O.OracleError):
+        S.fix_variables(fix)
