@@ -177,13 +177,17 @@ dm_status dm_dual_solve(dm_ctx* ctx, int32_t iters, double omega, double tempera
  * iteration with omega; then the pair s = lambda_new - lambda_old,
  * y = g_old - g_new joins the history when s^T y >= eps (L-BFGS acting on -E).
  * Dots are summed in FP64 in a fixed order.
+ * resume != 0 continues the search state of the previous call on this
+ * context (history pairs, step size, Delta_min) from the given lambda; it
+ * needs an earlier call with the same msg_prec and history on the same costs
+ * (DM_ERR_STATE otherwise).  resume = 0 starts afresh.
  *  lambda [device] float32 / float64 (msg_prec) [nnz] in/out, feasible on entry.
  *  lb_trace [device] double [iters + 1] out or NULL: E at the start of every
  *  iteration and at the end.  gamma_trace [device] double [iters] out or NULL:
  *  the step size FindStepSize returned.  taken [device] int32 [iters] out or
- *  NULL: 1 where the quasi-Newton step was applied.  Allocates its work
- *  buffers (history of (history + 1) s and y vectors); reads one flag back to
- *  the host per iteration (synchronises). */
+ *  NULL: 1 where the quasi-Newton step was applied.  The context keeps the
+ *  work buffers (history + 1 s and y vectors) until it is destroyed; reads
+ *  one flag back to the host per iteration (synchronises). */
 typedef struct {
   int32_t history;      /* m, number of stored (s, y) pairs, >= 0 */
   int32_t max_search;   /* K, rescalings per FindStepSize, >= 1 */
@@ -192,6 +196,7 @@ typedef struct {
   double step_up;       /* > 1 */
   double step_down;     /* in (0, 1) */
   double gamma0;        /* first step size, >= 0 */
+  int32_t resume;       /* continue the previous call's search state */
 } dm_lbfgs_params;
 dm_status dm_lbfgs_solve(dm_ctx* ctx, int32_t iters, const dm_lbfgs_params* params, int32_t msg_prec,
                          void* lambda, double* lb_trace, double* gamma_trace, int32_t* taken);
@@ -214,6 +219,30 @@ dm_status dm_subgradient(dm_ctx* ctx, int32_t msg_prec, const void* lambda, uint
  *  (msg_prec) [nnz] out.  Enqueue only (allocates work buffers). */
 dm_status dm_lbfgs_direction(dm_ctx* ctx, int32_t msg_prec, int32_t h, const void* S, const int8_t* Y,
                              const uint8_t* g, void* d);
+
+/* Confident-variable fixing (Appendix "Coarse-to-fine solving strategy"):
+ * at lambda, the min-marginal differences M^j_i of every free variable; a
+ * variable agrees when all its M^j_i are < 0 (prefers 1) or all > 0 (prefers
+ * 0); the agreeing variables are ranked by |sum_j M^j_i| (largest first, ties
+ * to the lower variable) and the top floor(frac * count) are fixed to their
+ * preferred values.
+ *  lambda [device] (msg_prec) [nnz]; frac in [0, 1];
+ *  fix [device] int8 [n_prod_tri] out: -1 free, else the value the element is
+ *  fixed to (presolve fixings and the new ones); *n_agree, *n_fixed [host]
+ *  out or NULL.  Synchronises. */
+dm_status dm_confident_fixing(dm_ctx* ctx, int32_t msg_prec, const void* lambda, double frac, int8_t* fix,
+                              int64_t* n_agree, int64_t* n_fixed);
+
+/* Re-run presolve (integer unit propagation) from the given fixings and
+ * replace the reduced problem by the residual one: later calls (multipliers,
+ * dual solves, rounding, ...) work on the residual, and primal vectors still
+ * cover every element, fixed ones included.  fix == NULL restores the
+ * problem without fixings.  If the fixings are infeasible the problem without
+ * fixings is restored and DM_ERR_INFEASIBLE returned.  Multiplier arrays of
+ * the previous problem do not fit the new one (its nnz changes).
+ *  fix [device] int8 [n_prod_tri] or NULL; *info [host] out (new sizes) or
+ *  NULL.  Synchronises. */
+dm_status dm_fix_variables(dm_ctx* ctx, const int8_t* fix, dm_space_info* info);
 
 /* Dual objective (A8; Eq. (D)) at lambda: offset + sum over rows of the row
  * minimum (soft-min for temperature > 0).  Synchronises; *lb [host]. */

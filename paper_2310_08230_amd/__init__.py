@@ -51,7 +51,7 @@ class dm_round_params(C.Structure):
 class dm_lbfgs_params(C.Structure):
     _fields_ = [("history", C.c_int32), ("max_search", C.c_int32), ("omega", C.c_double),
                 ("eps", C.c_double), ("step_up", C.c_double), ("step_down", C.c_double),
-                ("gamma0", C.c_double)]
+                ("gamma0", C.c_double), ("resume", C.c_int32)]
 
 
 def lib():
@@ -82,6 +82,8 @@ def lib():
             "dm_lbfgs_solve": [P, I32, P, I32, P, P, P, P],
             "dm_subgradient": [P, I32, P, P, P],
             "dm_lbfgs_direction": [P, I32, I32, P, P, P, P],
+            "dm_confident_fixing": [P, I32, P, D, P, P, P],
+            "dm_fix_variables": [P, P, P],
         }
         for name, args in sig.items():
             fn = getattr(L, name)
@@ -208,13 +210,14 @@ class Context:
         return lam, (tr[:iters] if trace else None)
 
     def lbfgs_solve(self, lam, iters, history=5, max_search=5, omega=0.5, eps=1e-8, step_up=1.1,
-                    step_down=0.8, gamma0=0.1):
+                    step_down=0.8, gamma0=0.1, resume=False):
         """Quasi-Newton powered MMA (Alg. 1), in place on lam.  Returns lam, the
         bound before every iteration and at the end (iters + 1 values), the
-        step sizes and whether each quasi-Newton step was taken."""
+        step sizes and whether each quasi-Newton step was taken.  resume=True
+        continues the previous call's history, step size and Delta_min."""
         msg_prec = "fp32" if lam.dtype == torch.float32 else "fp64"
         P = dm_lbfgs_params(int(history), int(max_search), float(omega), float(eps), float(step_up),
-                            float(step_down), float(gamma0))
+                            float(step_down), float(gamma0), int(bool(resume)))
         tr = torch.empty(iters + 1, dtype=torch.float64, device=self.device)
         gm = torch.empty(max(iters, 1), dtype=torch.float64, device=self.device)
         tk = torch.empty(max(iters, 1), dtype=torch.int32, device=self.device)
@@ -241,6 +244,28 @@ class Context:
         self._call("dm_lbfgs_direction", PREC[msg_prec], int(h), _ptr(S) if h else None,
                    _ptr(Y) if h else None, _ptr(g), _ptr(d))
         return d
+
+    # -- confident fixing (coarse-to-fine appendix) ----------------------
+    def confident_fixing(self, lam, frac=0.9):
+        """Per element -1 (free) or its fixed value, and the numbers of
+        agreeing and of newly fixed variables."""
+        msg_prec = "fp32" if lam.dtype == torch.float32 else "fp64"
+        fix = torch.empty(self.info["n_prod_tri"], dtype=torch.int8, device=self.device)
+        na, nf = C.c_int64(0), C.c_int64(0)
+        self._call("dm_confident_fixing", PREC[msg_prec], _ptr(lam), float(frac), _ptr(fix), C.byref(na),
+                   C.byref(nf))
+        return fix, na.value, nf.value
+
+    def fix_variables(self, fix=None):
+        """Presolve from the fixings; the context then holds the residual
+        problem (None restores the problem without fixings)."""
+        f = None if fix is None else _dev(fix, torch.int8, self.device)
+        info = dm_space_info()
+        try:
+            self._call("dm_fix_variables", _ptr(f) if f is not None else None, C.byref(info))
+        finally:   # on infeasible fixings the problem without fixings is back
+            self.info = {n: getattr(info, n) for n, _ in dm_space_info._fields_}
+        return self.info
 
     def lower_bound(self, lam, temperature=0.0):
         msg_prec = "fp32" if lam.dtype == torch.float32 else "fp64"

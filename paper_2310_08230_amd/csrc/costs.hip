@@ -123,6 +123,16 @@ __global__ void k_corner_ptr(const uint32_t* key, int64_t n, int64_t nC, int32_t
 
 }  // namespace
 
+// constant of the dual objective: the summed costs of the elements fixed to 1
+dm_status cost_offset(dm_ctx* ctx) {
+  DM_ALLOC(ctx, ctx->scal, 16);
+  k_fixed1_sum<<<1, 1024, 0, ctx->stream>>>(ctx->cost64.p, ctx->state.p, ctx->nP, ctx->scal.p);
+  DM_LAUNCH_CHECK(ctx);
+  DM_HIP(ctx, hipMemcpyAsync(&ctx->offset, ctx->scal.p, sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
+  DM_HIP(ctx, hipStreamSynchronize(ctx->stream));
+  return DM_OK;
+}
+
 extern "C" dm_status dm_build_costs(dm_ctx* ctx, const float* FX, const float* FY, int32_t D, int32_t prec,
                                     float* cost) {
   if (!ctx) return DM_ERR_INVALID_ARG;
@@ -172,10 +182,7 @@ extern "C" dm_status dm_build_costs(dm_ctx* ctx, const float* FX, const float* F
   int e = 0;
   DM_TRY(read_i32(ctx, err.p, &e));
   if (e) return dm_fail(ctx, DM_ERR_NONFINITE, "non-finite element cost");
-  DM_ALLOC(ctx, ctx->scal, 16);
-  k_fixed1_sum<<<1, 1024, 0, st>>>(ctx->cost64.p, ctx->state.p, nP, ctx->scal.p);
-  DM_LAUNCH_CHECK(ctx);
-  DM_HIP(ctx, hipMemcpyAsync(&ctx->offset, ctx->scal.p, sizeof(double), hipMemcpyDeviceToHost, st));
+  DM_TRY(cost_offset(ctx));
   // corners of each candidate pair, ascending (3p+v), for the backward pass
   {
     DArr<uint32_t> key;

@@ -197,7 +197,8 @@ struct dm_ctx {
   size_t ev_used = 0;
 
   // quasi-Newton session kept between dm_lbfgs_solve calls (history, step
-  // size, Delta_min), owned by lbfgs.hip; invalidated when the costs change
+  // size, Delta_min), owned by lbfgs.hip; invalidated when the costs or the
+  // fixed variables change (cost_generation counts those changes)
   void* qn = nullptr;
   void (*qn_free)(void*) = nullptr;
   int64_t cost_generation = 0;
@@ -221,6 +222,8 @@ dm_status scan_u8(dm_ctx* ctx, const uint8_t* in, int32_t* out, size_t n);   // 
 dm_status read_i32(dm_ctx* ctx, const int32_t* dev, int32_t* host);
 dm_status check_finite(dm_ctx* ctx, const float* a, int64_t n);
 dm_status dual_flush(dm_ctx* ctx);  // write the bound of the last sweep launch
+dm_status cost_offset(dm_ctx* ctx); // offset = summed costs of elements fixed to 1 (synchronises)
+dm_status presolve_reduce(dm_ctx* ctx, const int8_t* fix);  // presolve from fixings, reduced problem
 
 // One sweep over all rows of the presolved problem (dual.hip).  Modes: update
 // the multipliers (rin -> out), write min-marginals (or soft marginals) per

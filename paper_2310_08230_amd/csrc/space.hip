@@ -309,6 +309,11 @@ __global__ void k_presolve_vars(int64_t nP, int8_t* state, uint32_t* force, int*
   }
 }
 
+__global__ void k_fix_state(const int8_t* fix, int64_t nP, int8_t* state) {
+  int64_t p = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (p < nP) state[p] = fix[p] < 0 ? int8_t(-1) : int8_t(fix[p] ? 1 : 0);
+}
+
 __global__ void k_free_flags(const int8_t* state, int64_t nP, uint8_t* flag, int* nfix1) {
   int64_t p = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (p >= nP) return;
@@ -720,9 +725,26 @@ dm_status space_build(dm_ctx* ctx, const int32_t* cand_xy, const int32_t* cand_y
   yval.release();
   off.release();
 
+  return presolve_reduce(ctx, nullptr);
+}
+
+// Integer unit propagation to the fixpoint from a starting assignment (fix:
+// per element -1 free or 0 / 1, or NULL for none), then the reduced problem,
+// its row statistics and the wave chunks of its closedness rows.
+dm_status presolve_reduce(dm_ctx* ctx, const int8_t* fix) {
+  hipStream_t st = ctx->stream;
+  const int64_t nP = ctx->nP, nc = ctx->n_closed_full, nrows = ctx->n_rows_full;
+  DArr<int> err;
+  DM_ALLOC(ctx, err, 4);
+  DM_HIP(ctx, hipMemsetAsync(err.p, 0, 4 * sizeof(int), st));
   // ---- presolve rounds
   DM_ALLOC(ctx, ctx->state, size_t(nP));
-  DM_HIP(ctx, hipMemsetAsync(ctx->state.p, 0xFF, size_t(nP), st));
+  if (fix) {
+    if (nP > 0) k_fix_state<<<grid_for(nP, 256), 256, 0, st>>>(fix, nP, ctx->state.p);
+    DM_LAUNCH_CHECK(ctx);
+  } else {
+    DM_HIP(ctx, hipMemsetAsync(ctx->state.p, 0xFF, size_t(nP), st));
+  }
   DArr<uint32_t> force;
   DM_ALLOC(ctx, force, size_t(nP));
   DM_HIP(ctx, hipMemsetAsync(force.p, 0, sizeof(uint32_t) * nP, st));
@@ -859,6 +881,8 @@ dm_status space_build(dm_ctx* ctx, const int32_t* cand_xy, const int32_t* cand_y
   return DM_OK;
 }
 
+static void fill_info(dm_ctx* ctx, dm_space_info* info);
+
 extern "C" dm_status dm_build_product_space(dm_ctx* ctx, const dm_mesh* Xin, const dm_mesh* Yin,
                                             const int32_t* cand_xy, const int32_t* cand_yx, int32_t K,
                                             dm_space_info* info) {
@@ -879,6 +903,33 @@ extern "C" dm_status dm_build_product_space(dm_ctx* ctx, const dm_mesh* Xin, con
   ctx->K = K;
   DM_TRY(space_build(ctx, cand_xy, cand_yx, K));
   ctx->has_space = true;
+  fill_info(ctx, info);
+  return DM_OK;
+}
+
+extern "C" dm_status dm_fix_variables(dm_ctx* ctx, const int8_t* fix, dm_space_info* info) {
+  if (!ctx) return DM_ERR_INVALID_ARG;
+  ctx->err.clear();
+  if (!ctx->has_space) return dm_fail(ctx, DM_ERR_STATE, "no product space built");
+  DM_HIP(ctx, hipSetDevice(ctx->device));
+  DM_TRY(dual_flush(ctx));
+  ++ctx->cost_generation;   // solver state of the previous problem is stale
+  const dm_status s = presolve_reduce(ctx, fix);
+  if (s != DM_OK) {
+    // keep the message, restore the problem without fixings
+    const std::string msg = ctx->err;
+    DM_TRY(presolve_reduce(ctx, nullptr));
+    if (ctx->has_cost) DM_TRY(cost_offset(ctx));
+    ctx->err = msg;
+    if (info) fill_info(ctx, info);
+    return s;
+  }
+  if (ctx->has_cost) DM_TRY(cost_offset(ctx));
+  if (info) fill_info(ctx, info);
+  return DM_OK;
+}
+
+static void fill_info(dm_ctx* ctx, dm_space_info* info) {
   dm_space_info& I = *info;
   I.n_prod_tri = ctx->nP;
   I.n_rows_full = ctx->n_rows_full;
@@ -894,5 +945,4 @@ extern "C" dm_status dm_build_product_space(dm_ctx* ctx, const dm_mesh* Xin, con
   I.n_cand = ctx->nC;
   I.presolve_rounds = ctx->presolve_rounds;
   I.max_short_row = ctx->max_short;
-  return DM_OK;
 }
