@@ -112,6 +112,52 @@ __device__ inline void rec_lambdas(const R* __restrict__ rec, size_t i, bool d5,
   lam[4] = d5 ? s4 + corr : R(0);
 }
 
+// FP64 sum of a 256-thread block in a fixed order: an xor butterfly inside
+// each wave (every lane ends with the same value, since a + b == b + a
+// exactly), then the four wave sums in index order.  red: 4 doubles of LDS.
+__device__ inline double block_sum_256(double v, double* red) {
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+  __syncthreads();
+  const double r = ((red[0] + red[1]) + red[2]) + red[3];
+  __syncthreads();
+  return r;
+}
+
+// Sum of n per-block partials by a 256-thread block, in a fixed order (the
+// same value in every block that calls it).  Thread t takes elements
+// t + 256 k into eight independent accumulators (k mod 8), so its loads do
+// not wait on each other.
+__device__ inline double sum_partials_256(const double* p, int n, double* red) {
+  double a[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+  for (int i = int(threadIdx.x); i < n; i += 256 * 8) {
+#pragma unroll
+    for (int u = 0; u < 8; ++u)
+      if (i + 256 * u < n) a[u] += p[i + 256 * u];
+  }
+  const double v = ((((((a[0] + a[1]) + a[2]) + a[3]) + a[4]) + a[5]) + a[6]) + a[7];
+  return block_sum_256(v, red);
+}
+
+// The same for one 1024-thread block (sixteen waves): for the one-block
+// kernels that sum the partials of a whole sweep launch.  red: 16 doubles.
+__device__ inline double sum_partials_1024(const double* p, int n, double* red) {
+  double a[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+  for (int i = int(threadIdx.x); i < n; i += 1024 * 8) {
+#pragma unroll
+    for (int u = 0; u < 8; ++u)
+      if (i + 1024 * u < n) a[u] += p[i + 1024 * u];
+  }
+  double v = ((((((a[0] + a[1]) + a[2]) + a[3]) + a[4]) + a[5]) + a[6]) + a[7];
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+  __syncthreads();
+  double r = 0.0;
+  for (int w = 0; w < 16; ++w) r += red[w];
+  __syncthreads();
+  return r;
+}
+
 struct dm_ctx {
   int device = 0;
   hipStream_t stream = nullptr;
@@ -230,9 +276,10 @@ dm_status presolve_reduce(dm_ctx* ctx, const int8_t* fix);  // presolve from fix
 // slot to out, bound only, or write each row's minimising assignment.
 enum SweepMode { SWEEP_UPDATE = 0, SWEEP_EVAL = 1, SWEEP_BOUND = 2, SWEEP_SUBGRAD = 3 };
 // Options of the hard sweep used by the quasi-Newton layer: rows see
-// lambda + (*gamma) * dir (dir in the record layout, gamma on the device); the
-// launch does nothing while *skip is nonzero; SWEEP_SUBGRAD writes 1 / 0 per
-// slot to gsub.
+// lambda + (*gamma) * dir (gamma on the device); the launch does nothing while
+// *skip is nonzero; SWEEP_SUBGRAD writes 1 / 0 per slot to gsub.  dir and gsub
+// hold five slot planes of n_free values: slot k of variable i at
+// k * n_free + i.
 struct SweepExt {
   const void* dir = nullptr;
   const double* gamma = nullptr;

@@ -101,9 +101,7 @@ __device__ inline void store_partial(double part, double* partial, int32_t item)
 }
 
 __device__ inline void reduce_partials(const double* partial, int n, double offset, double* out, double* red) {
-  double s = 0.0;
-  for (int i = threadIdx.x; i < n; i += blockDim.x) s += partial[i];
-  double tot = block_sum(s, red);
+  const double tot = sum_partials_256(partial, n, red);
   if (threadIdx.x == 0) *out = offset + tot;
 }
 
@@ -127,20 +125,26 @@ struct SweepArgs {
   double prev_offset;
   double* prev_out;
   // quasi-Newton extensions (hard min only): rows see lambda + gamma * dir
-  // when dir is set (dir in the record layout, gamma a device scalar); the
-  // launch does nothing when *skip is nonzero; MODE_SUBGRAD writes the row's
-  // minimising assignment (1 / 0 per entry) to gsub in the record layout
+  // when dir is set (dir in slot planes: slot k of variable i at
+  // k * plane + i; gamma a device scalar); the launch does nothing when
+  // *skip is nonzero; MODE_SUBGRAD writes the row's minimising assignment
+  // (1 / 0 per entry) to gsub in the same slot planes
+  int64_t plane;
   const void* dir;
   const double* gamma;
   const int32_t* skip;
   uint8_t* gsub;
 };
 
+__device__ inline size_t slot_index(const SweepArgs& A, uint32_t w) {
+  return size_t((w >> W_SLOT_SHIFT) & 7u) * size_t(A.plane) + size_t(w & W_VAR_MASK);
+}
+
 // multiplier seen by the rows: the record's, moved along dir when one is set
 template <typename R>
 __device__ inline R row_lambda(const SweepArgs& A, const R* __restrict__ rin, uint32_t w, R gam) {
   R v = cur_lambda<R>(rin, w);
-  if (A.dir) v += gam * static_cast<const R*>(A.dir)[size_t(w & W_VAR_MASK) * REC + ((w >> W_SLOT_SHIFT) & 7u)];
+  if (A.dir) v += gam * static_cast<const R*>(A.dir)[slot_index(A, w)];
   return v;
 }
 
@@ -307,7 +311,7 @@ __device__ inline double short_chunk_hard(const SweepArgs& A, const R* __restric
       if (MODE == MODE_UPDATE) write_out<R>(out, w, lam - omega * M);
       if (MODE == MODE_EVAL) write_out<R>(out, w, M);
       if (MODE == MODE_SUBGRAD)
-        A.gsub[size_t(w & W_VAR_MASK) * REC + ((w >> W_SLOT_SHIFT) & 7u)] = uint8_t(rank < kbest ? 1 : 0);
+        A.gsub[slot_index(A, w)] = uint8_t(rank < kbest ? 1 : 0);
       if (lane == s) rowpart = double(rmin);
     }
   }
@@ -546,7 +550,7 @@ __device__ void long_rows(const SweepArgs& A, const R* __restrict__ rin, R* __re
         if (MODE == MODE_UPDATE) write_out<R>(out, w, lam - omega * M);
         if (MODE == MODE_EVAL) write_out<R>(out, w, SOFT ? mu : M);
         if (MODE == MODE_SUBGRAD)
-          A.gsub[size_t(w & W_VAR_MASK) * REC + ((w >> W_SLOT_SHIFT) & 7u)] = uint8_t(i == st.a ? 1 : 0);
+          A.gsub[slot_index(A, w)] = uint8_t(i == st.a ? 1 : 0);
       };
 #pragma unroll
       for (int u = 0; u < LONG_REG; ++u) {
@@ -716,6 +720,7 @@ dm_status dual_sweep(dm_ctx* ctx, int mode, bool soft, const unsigned char* rin,
   const int64_t n_long_blocks = (n_long + rows_per_long_block - 1) / rows_per_long_block;
   A.n_short = int32_t(ctx->n_short);
   A.n_rows = int32_t(ctx->n_rows);
+  A.plane = ctx->n_free;
   A.dir = ext ? ext->dir : nullptr;
   A.gamma = ext ? ext->gamma : nullptr;
   A.skip = ext ? ext->skip : nullptr;

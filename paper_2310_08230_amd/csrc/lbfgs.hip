@@ -2,11 +2,12 @@
 // Updates") on top of the Jacobi sweep of dual.hip.
 //
 // Vectors with one value per multiplier (the subgradient g, the history pairs
-// s and y, the direction q / d) use the record layout of the multipliers: REC
-// slots per free variable, slots 0-4 as in the records (slot 4 only for
-// variables with five rows), the rest unused.  g and y only take the values
-// 0/1 and -1/0/1 and are stored as bytes, so a history pair costs 5 reals and
-// 5 bytes per variable.
+// s and y, the direction q / d) are five slot planes of n_free values: slot k
+// of variable i (k as in the records; slot 4 only for variables with five
+// rows, zero otherwise) at k * n_free + i, so every pass reads and writes
+// whole planes coalesced.  g and y only take the values 0/1 and -1/0/1 and
+// are stored as bytes, so a history pair costs 5 reals and 5 bytes per
+// variable.
 //
 // One iteration, as launched by the host loop below:
 //  1. direction: 2h + 1 variable-major passes over the last h accepted pairs.
@@ -46,59 +47,32 @@ struct QnState {
   int32_t pad;
 };
 
-__device__ inline double bsum(double v, double* red) {
-  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
-  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
-  __syncthreads();
-  const double r = ((red[0] + red[1]) + red[2]) + red[3];
-  __syncthreads();
-  return r;
-}
+__device__ inline double bsum(double v, double* red) { return block_sum_256(v, red); }
 
 // sum of n per-block partials in a fixed order; every block gets the same value
-__device__ inline double sum_partials(const double* p, int n, double* red) {
-  double v = 0.0;
-  for (int i = threadIdx.x; i < n; i += VB) v += p[i];
-  return bsum(v, red);
+__device__ inline double sum_partials(const double* p, int n, double* red) { return sum_partials_256(p, n, red); }
+
+// vectors hold five slot planes of n values: slot k of variable i at k n + i
+template <typename R>
+__device__ inline void load5(const R* __restrict__ a, int64_t i, int64_t n, double v[5]) {
+#pragma unroll
+  for (int k = 0; k < 5; ++k) v[k] = double(a[k * n + i]);
 }
 
 template <typename R>
-__device__ inline void load5(const R* __restrict__ a, int64_t i, double v[5]) {
-  const R* r = a + size_t(i) * REC;
-  if constexpr (sizeof(R) == 4) {
-    const float4 lo = *reinterpret_cast<const float4*>(r);
-    v[0] = lo.x, v[1] = lo.y, v[2] = lo.z, v[3] = lo.w;
-  } else {
-    const double2 a0 = *reinterpret_cast<const double2*>(r);
-    const double2 a1 = *reinterpret_cast<const double2*>(r + 2);
-    v[0] = a0.x, v[1] = a0.y, v[2] = a1.x, v[3] = a1.y;
-  }
-  v[4] = double(r[4]);
+__device__ inline void store5(R* __restrict__ a, int64_t i, int64_t n, const double v[5]) {
+#pragma unroll
+  for (int k = 0; k < 5; ++k) a[k * n + i] = R(v[k]);
 }
 
-template <typename R>
-__device__ inline void store5(R* __restrict__ a, int64_t i, const double v[5]) {
-  R* r = a + size_t(i) * REC;
-  if constexpr (sizeof(R) == 4) {
-    *reinterpret_cast<float4*>(r) = make_float4(float(v[0]), float(v[1]), float(v[2]), float(v[3]));
-  } else {
-    *reinterpret_cast<double2*>(r) = make_double2(v[0], v[1]);
-    *reinterpret_cast<double2*>(r + 2) = make_double2(v[2], v[3]);
-  }
-  r[4] = R(v[4]);
+__device__ inline void load5_u8(const uint8_t* __restrict__ a, int64_t i, int64_t n, double v[5]) {
+#pragma unroll
+  for (int k = 0; k < 5; ++k) v[k] = double(a[k * n + i]);
 }
 
-// five byte slots of a record (8-byte aligned)
-__device__ inline void load5_u8(const uint8_t* __restrict__ a, int64_t i, double v[5]) {
-  const uint2 u = *reinterpret_cast<const uint2*>(a + size_t(i) * REC);
-  for (int k = 0; k < 4; ++k) v[k] = double((u.x >> (8 * k)) & 0xFFu);
-  v[4] = double(u.y & 0xFFu);
-}
-
-__device__ inline void load5_i8(const int8_t* __restrict__ a, int64_t i, double v[5]) {
-  const uint2 u = *reinterpret_cast<const uint2*>(a + size_t(i) * REC);
-  for (int k = 0; k < 4; ++k) v[k] = double(int8_t((u.x >> (8 * k)) & 0xFFu));
-  v[4] = double(int8_t(u.y & 0xFFu));
+__device__ inline void load5_i8(const int8_t* __restrict__ a, int64_t i, int64_t n, double v[5]) {
+#pragma unroll
+  for (int k = 0; k < 5; ++k) v[k] = double(a[k * n + i]);
 }
 
 __device__ inline double dot5(const double a[5], const double b[5]) {
@@ -119,9 +93,9 @@ template <typename R>
 __global__ __launch_bounds__(VB) void k_qn_project_g(const uint8_t* g8, const uint8_t* deg, int64_t n, R* d) {
   for (int64_t i = int64_t(blockIdx.x) * VB + threadIdx.x; i < n; i += int64_t(gridDim.x) * VB) {
     double v[5];
-    load5_u8(g8, i, v);
+    load5_u8(g8, i, n, v);
     project5(v, deg[i] == 5);
-    store5<R>(d, i, v);
+    store5<R>(d, i, n, v);
   }
 }
 
@@ -132,8 +106,8 @@ __global__ __launch_bounds__(VB) void k_qn_first(const uint8_t* g8, const R* s, 
   double acc = 0.0;
   for (int64_t i = int64_t(blockIdx.x) * VB + threadIdx.x; i < n; i += int64_t(gridDim.x) * VB) {
     double gv[5], sv[5];
-    load5_u8(g8, i, gv);
-    load5<R>(s, i, sv);
+    load5_u8(g8, i, n, gv);
+    load5<R>(s, i, n, sv);
     acc += dot5(sv, gv);
   }
   const double b = bsum(acc, red);
@@ -154,13 +128,13 @@ __global__ __launch_bounds__(VB) void k_qn_loop1(const uint8_t* g8, const R* q_i
   double acc = 0.0;
   for (int64_t i = int64_t(blockIdx.x) * VB + threadIdx.x; i < n; i += int64_t(gridDim.x) * VB) {
     double qv[5], yv[5], nv[5];
-    if (g8) load5_u8(g8, i, qv);
-    else load5<R>(q_in, i, qv);
-    load5_i8(y, i, yv);
+    if (g8) load5_u8(g8, i, n, qv);
+    else load5<R>(q_in, i, n, qv);
+    load5_i8(y, i, n, yv);
     for (int k = 0; k < 5; ++k) qv[k] = double(R(qv[k] - alpha * yv[k]));
-    store5<R>(q_out, i, qv);
-    if (s_next) load5<R>(s_next, i, nv);
-    else load5_i8(y_next, i, nv);
+    store5<R>(q_out, i, n, qv);
+    if (s_next) load5<R>(s_next, i, n, nv);
+    else load5_i8(y_next, i, n, nv);
     acc += dot5(nv, qv);
   }
   const double b = bsum(acc, red);
@@ -182,18 +156,18 @@ __global__ __launch_bounds__(VB) void k_qn_loop2(const R* q_in, const R* s, cons
   double acc = 0.0;
   for (int64_t i = int64_t(blockIdx.x) * VB + threadIdx.x; i < n; i += int64_t(gridDim.x) * VB) {
     double qv[5], sv[5];
-    load5<R>(q_in, i, qv);
-    load5<R>(s, i, sv);
+    load5<R>(q_in, i, n, qv);
+    load5<R>(s, i, n, sv);
     for (int k = 0; k < 5; ++k) qv[k] = h0 * qv[k] + coef * sv[k];
     if (y_next) {
       for (int k = 0; k < 5; ++k) qv[k] = double(R(qv[k]));
       double yv[5];
-      load5_i8(y_next, i, yv);
+      load5_i8(y_next, i, n, yv);
       acc += dot5(yv, qv);
     } else {
       project5(qv, deg[i] == 5);
     }
-    store5<R>(q_out, i, qv);
+    store5<R>(q_out, i, n, qv);
   }
   if (y_next) {
     const double b = bsum(acc, red);
@@ -216,18 +190,14 @@ __global__ __launch_bounds__(VB) void k_qn_hist_pass(const R* rec_old, const R* 
     rec_lambdas<R>(rec_old, size_t(i), d5, lo);
     rec_lambdas<R>(rec_new, size_t(i), d5, ln);
     double go[5], gn[5], sv[5], yv[5];
-    load5_u8(g_old, i, go);
-    load5_u8(g_new, i, gn);
-    uint32_t packed_lo = 0, packed_hi = 0;
+    load5_u8(g_old, i, n, go);
+    load5_u8(g_new, i, n, gn);
     for (int k = 0; k < 5; ++k) {
       sv[k] = double(R(ln[k] - lo[k]));
       yv[k] = go[k] - gn[k];
-      const uint32_t byte = uint32_t(uint8_t(int8_t(yv[k])));
-      if (k < 4) packed_lo |= byte << (8 * k);
-      else packed_hi = byte;
+      y_out[k * n + i] = int8_t(yv[k]);
     }
-    store5<R>(s_out, i, sv);
-    *reinterpret_cast<uint2*>(y_out + size_t(i) * REC) = make_uint2(packed_lo, packed_hi);
+    store5<R>(s_out, i, n, sv);
     a_sy += dot5(sv, yv);
     a_yy += dot5(yv, yv);
   }
@@ -247,8 +217,8 @@ __global__ __launch_bounds__(VB) void k_qn_pair_dots(const R* s, const int8_t* y
   double a_sy = 0.0, a_yy = 0.0;
   for (int64_t i = int64_t(blockIdx.x) * VB + threadIdx.x; i < n; i += int64_t(gridDim.x) * VB) {
     double sv[5], yv[5];
-    load5<R>(s, i, sv);
-    load5_i8(y, i, yv);
+    load5<R>(s, i, n, sv);
+    load5_i8(y, i, n, yv);
     a_sy += dot5(sv, yv);
     a_yy += dot5(yv, yv);
   }
@@ -260,11 +230,11 @@ __global__ __launch_bounds__(VB) void k_qn_pair_dots(const R* s, const int8_t* y
   }
 }
 
-__global__ __launch_bounds__(VB) void k_qn_pair_fin(const double* part_sy, const double* part_yy, int32_t n,
+__global__ __launch_bounds__(1024) void k_qn_pair_fin(const double* part_sy, const double* part_yy, int32_t n,
                                                     double* sy, double* yy) {
-  __shared__ double red[4];
-  const double a = sum_partials(part_sy, n, red);
-  const double b = sum_partials(part_yy, n, red);
+  __shared__ double red[16];
+  const double a = sum_partials_1024(part_sy, n, red);
+  const double b = sum_partials_1024(part_yy, n, red);
   if (threadIdx.x == 0) {
     *sy = a;
     *yy = b;
@@ -274,10 +244,10 @@ __global__ __launch_bounds__(VB) void k_qn_pair_fin(const double* part_sy, const
 // ---------------------------------------------------------------- one-block decisions
 // start of a call: the bound at the imported lambda; a fresh search also
 // resets the step size and Delta_min (a resumed one keeps them)
-__global__ __launch_bounds__(VB) void k_qn_begin(const double* sp, int32_t sn, double offset, QnState* st,
+__global__ __launch_bounds__(1024) void k_qn_begin(const double* sp, int32_t sn, double offset, QnState* st,
                                                  double* etrace, double gamma0, int32_t resume) {
-  __shared__ double red[4];
-  const double E = offset + sum_partials(sp, sn, red);
+  __shared__ double red[16];
+  const double E = offset + sum_partials_1024(sp, sn, red);
   if (threadIdx.x == 0) {
     etrace[0] = E;
     if (!resume) {
@@ -296,12 +266,12 @@ __global__ __launch_bounds__(VB) void k_qn_begin(const double* sp, int32_t sn, d
 // FindStepSize after probe t (t = 0: the previous step size; t = 1..K: the
 // rescaled ones): keep the best trial, stop after a gain of Delta_min or at
 // t = K, otherwise rescale gamma by the verdict of this trial against E(lambda)
-__global__ __launch_bounds__(VB) void k_qn_probe(const double* sp, int32_t sn, double offset, int32_t t, int32_t K,
+__global__ __launch_bounds__(1024) void k_qn_probe(const double* sp, int32_t sn, double offset, int32_t t, int32_t K,
                                                  double up, double down, QnState* st, double* gtrace,
                                                  int32_t* taken) {
-  __shared__ double red[4];
+  __shared__ double red[16];
   if (st->done) return;   // uniform
-  const double E = offset + sum_partials(sp, sn, red);
+  const double E = offset + sum_partials_1024(sp, sn, red);
   if (threadIdx.x != 0) return;
   if (t == 0 || E >= st->Em) {
     st->gm = st->gamma;
@@ -322,14 +292,14 @@ __global__ __launch_bounds__(VB) void k_qn_probe(const double* sp, int32_t sn, d
 
 // after the subgradient sweep at lambda_{k+1} and the history pass: the bound
 // E(lambda_{k+1}), Delta_min after the first iteration, the curvature test
-__global__ __launch_bounds__(VB) void k_qn_hist(const double* sp, int32_t sn, double offset, const double* part_sy,
+__global__ __launch_bounds__(1024) void k_qn_hist(const double* sp, int32_t sn, double offset, const double* part_sy,
                                                 const double* part_yy, int32_t hn, int32_t k, int32_t set_dmin,
                                                 double eps, QnState* st, double* etrace, double* sy_out,
                                                 double* yy_out, int32_t* accepted) {
-  __shared__ double red[4];
-  const double E = offset + sum_partials(sp, sn, red);
-  const double sy = sum_partials(part_sy, hn, red);
-  const double yy = sum_partials(part_yy, hn, red);
+  __shared__ double red[16];
+  const double E = offset + sum_partials_1024(sp, sn, red);
+  const double sy = sum_partials_1024(part_sy, hn, red);
+  const double yy = sum_partials_1024(part_yy, hn, red);
   if (threadIdx.x != 0) return;
   etrace[k + 1] = E;
   if (set_dmin) st->dmin = 1e-6 * (E - st->E0);
@@ -345,16 +315,17 @@ __global__ __launch_bounds__(VB) void k_qn_hist(const double* sp, int32_t sn, do
 }
 
 // ---------------------------------------------------------------- layout conversion
+// entry order <-> slot planes
 template <typename T>
-__global__ void k_scatter(const T* v, const uint32_t* word, int64_t nnz, T* rec) {
+__global__ void k_scatter(const T* v, const uint32_t* word, int64_t nnz, int64_t n, T* planes) {
   const int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (e < nnz) rec[size_t(word[e] & W_VAR_MASK) * REC + ((word[e] >> W_SLOT_SHIFT) & 7u)] = v[e];
+  if (e < nnz) planes[int64_t((word[e] >> W_SLOT_SHIFT) & 7u) * n + (word[e] & W_VAR_MASK)] = v[e];
 }
 
 template <typename T>
-__global__ void k_gather(const T* rec, const uint32_t* word, int64_t nnz, T* v) {
+__global__ void k_gather(const T* planes, const uint32_t* word, int64_t nnz, int64_t n, T* v) {
   const int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (e < nnz) v[e] = rec[size_t(word[e] & W_VAR_MASK) * REC + ((word[e] >> W_SLOT_SHIFT) & 7u)];
+  if (e < nnz) v[e] = planes[int64_t((word[e] >> W_SLOT_SHIFT) & 7u) * n + (word[e] & W_VAR_MASK)];
 }
 
 __global__ void k_fill_f64(double* a, int64_t n, double v) {
@@ -431,7 +402,7 @@ struct QnBuffers {
 
 template <typename R>
 dm_status qn_alloc(dm_ctx* ctx, int nb, QnBuffers<R>& B) {
-  const size_t rec = size_t(std::max<int64_t>(ctx->n_free, 1)) * REC;
+  const size_t rec = size_t(std::max<int64_t>(ctx->n_free, 1)) * 5;   // five slot planes
   DM_ALLOC(ctx, B.S, rec * nb);
   DM_ALLOC(ctx, B.Y, rec * nb);
   DM_ALLOC(ctx, B.q, rec);
@@ -528,7 +499,7 @@ dm_status lbfgs_impl(dm_ctx* ctx, int32_t iters, const dm_lbfgs_params& P, R* la
   SweepExt sub;
   sub.gsub = B.g[0].p;
   DM_TRY(dual_sweep<R>(ctx, SWEEP_SUBGRAD, false, ctx->rec[0].p, nullptr, R(0), R(0), nullptr, &sub));
-  k_qn_begin<<<1, VB, 0, stream>>>(ctx->pend_partial, ctx->pend_n, ctx->offset, st, etrace.p, P.gamma0,
+  k_qn_begin<<<1, 1024, 0, stream>>>(ctx->pend_partial, ctx->pend_n, ctx->offset, st, etrace.p, P.gamma0,
                                    resume ? 1 : 0);
   DM_LAUNCH_CHECK(ctx);
   for (int32_t k = 0; k < iters; ++k) {
@@ -539,10 +510,19 @@ dm_status lbfgs_impl(dm_ctx* ctx, int32_t iters, const dm_lbfgs_params& P, R* la
     pe.skip = &st->done;
     for (int t = 0; t <= P.max_search; ++t) {
       DM_TRY(dual_sweep<R>(ctx, SWEEP_BOUND, false, ctx->rec[cur].p, nullptr, R(0), R(0), nullptr, &pe));
-      k_qn_probe<<<1, VB, 0, stream>>>(ctx->pend_partial, ctx->pend_n, ctx->offset, t, P.max_search, P.step_up,
-                                       P.step_down, st, gamma_trace ? gamma_trace + k : nullptr,
-                                       taken ? taken + k : nullptr);
+      k_qn_probe<<<1, 1024, 0, stream>>>(ctx->pend_partial, ctx->pend_n, ctx->offset, t, P.max_search, P.step_up,
+                                         P.step_down, st, gamma_trace ? gamma_trace + k : nullptr,
+                                         taken ? taken + k : nullptr);
       DM_LAUNCH_CHECK(ctx);
+      // the search usually stops at the second trial: one read of the flag
+      // then spares launching the remaining probes (a skipped launch still
+      // dispatches every workgroup of the sweep grid)
+      if (t == 1 && t < P.max_search) {
+        int32_t done = 0;
+        DM_HIP(ctx, hipMemcpyAsync(&done, &st->done, sizeof(int32_t), hipMemcpyDeviceToHost, stream));
+        DM_HIP(ctx, hipStreamSynchronize(stream));
+        if (done) break;
+      }
     }
     SweepExt me;
     me.dir = B.q.p;
@@ -561,7 +541,7 @@ dm_status lbfgs_impl(dm_ctx* ctx, int32_t iters, const dm_lbfgs_params& P, R* la
                                                reinterpret_cast<const R*>(ctx->rec[cur ^ 1].p), B.g[gc].p,
                                                B.g[gc ^ 1].p, ctx->var_deg.p, n, B.Sp[spare], B.Yp[spare], psy,
                                                pyy);
-    k_qn_hist<<<1, VB, 0, stream>>>(sp, sn, ctx->offset, psy, pyy, m > 0 ? int32_t(G) : 0, k,
+    k_qn_hist<<<1, 1024, 0, stream>>>(sp, sn, ctx->offset, psy, pyy, m > 0 ? int32_t(G) : 0, k,
                                     (k == 0 && !resume) ? 1 : 0, P.eps, st, etrace.p, sc.sy(spare),
                                     sc.yy(spare), S.flag.p);
     DM_LAUNCH_CHECK(ctx);
@@ -601,7 +581,7 @@ dm_status subgradient_impl(dm_ctx* ctx, const R* lam, uint8_t* g, double* lb) {
   DArr<uint8_t> g8;
   DM_TRY(dual_flush(ctx));
   DM_TRY(dual_import<R>(ctx, lam, bufs));
-  DM_ALLOC(ctx, g8, size_t(std::max<int64_t>(ctx->n_free, 1)) * REC);
+  DM_ALLOC(ctx, g8, size_t(std::max<int64_t>(ctx->n_free, 1)) * 5);
   DM_HIP(ctx, hipMemsetAsync(g8.p, 0, g8.n, ctx->stream));
   DM_ALLOC(ctx, ctx->scal, 16);
   SweepExt sub;
@@ -609,7 +589,8 @@ dm_status subgradient_impl(dm_ctx* ctx, const R* lam, uint8_t* g, double* lb) {
   DM_TRY(dual_sweep<R>(ctx, SWEEP_SUBGRAD, false, bufs[0].p, nullptr, R(0), R(0), ctx->scal.p, &sub));
   DM_TRY(dual_flush(ctx));
   if (ctx->nnz > 0)
-    k_gather<uint8_t><<<grid_for(ctx->nnz, 256), 256, 0, ctx->stream>>>(g8.p, ctx->rent_word.p, ctx->nnz, g);
+    k_gather<uint8_t><<<grid_for(ctx->nnz, 256), 256, 0, ctx->stream>>>(g8.p, ctx->rent_word.p, ctx->nnz,
+                                                                        ctx->n_free, g);
   DM_LAUNCH_CHECK(ctx);
   double v = 0.0;
   DM_HIP(ctx, hipMemcpyAsync(&v, ctx->scal.p, sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
@@ -628,17 +609,17 @@ dm_status direction_impl(dm_ctx* ctx, int32_t h, const R* S, const int8_t* Y, co
   const unsigned G = vgrid(n);
   const unsigned E = grid_for(nnz, 256);
   std::vector<int> order;
-  k_scatter<uint8_t><<<E, 256, 0, ctx->stream>>>(g, ctx->rent_word.p, nnz, B.g[0].p);
+  k_scatter<uint8_t><<<E, 256, 0, ctx->stream>>>(g, ctx->rent_word.p, nnz, n, B.g[0].p);
   for (int b = 0; b < h; ++b) {
-    k_scatter<R><<<E, 256, 0, ctx->stream>>>(S + size_t(b) * nnz, ctx->rent_word.p, nnz, B.Sp[b]);
-    k_scatter<int8_t><<<E, 256, 0, ctx->stream>>>(Y + size_t(b) * nnz, ctx->rent_word.p, nnz, B.Yp[b]);
+    k_scatter<R><<<E, 256, 0, ctx->stream>>>(S + size_t(b) * nnz, ctx->rent_word.p, nnz, n, B.Sp[b]);
+    k_scatter<int8_t><<<E, 256, 0, ctx->stream>>>(Y + size_t(b) * nnz, ctx->rent_word.p, nnz, n, B.Yp[b]);
     k_qn_pair_dots<R><<<G, VB, 0, ctx->stream>>>(B.Sp[b], B.Yp[b], n, B.part.p, B.part.p + VGRID);
-    k_qn_pair_fin<<<1, VB, 0, ctx->stream>>>(B.part.p, B.part.p + VGRID, int32_t(G), sc.sy(b), sc.yy(b));
+    k_qn_pair_fin<<<1, 1024, 0, ctx->stream>>>(B.part.p, B.part.p + VGRID, int32_t(G), sc.sy(b), sc.yy(b));
     order.push_back(b);
   }
   DM_LAUNCH_CHECK(ctx);
   DM_TRY(direction<R>(ctx, order, B.Sp.data(), B.Yp.data(), B.g[0].p, B.q.p, sc, B.part.p));
-  k_gather<R><<<E, 256, 0, ctx->stream>>>(B.q.p, ctx->rent_word.p, nnz, d);
+  k_gather<R><<<E, 256, 0, ctx->stream>>>(B.q.p, ctx->rent_word.p, nnz, n, d);
   DM_LAUNCH_CHECK(ctx);
   DM_HIP(ctx, hipStreamSynchronize(ctx->stream));
   return DM_OK;
