@@ -78,12 +78,16 @@ typedef struct {
 } dm_space_info;
 
 /* Create a context on HIP device `device`; work is enqueued on `hip_stream`
- * (a hipStream_t, may be NULL for the default stream). */
+ * (a hipStream_t, may be NULL for the default stream).  The context's device
+ * memory is allocated and freed stream-ordered on that stream (the device's
+ * default memory pool, set to keep freed memory for reuse), so the stream
+ * must stay valid until dm_destroy. */
 dm_status dm_create(int32_t device, void* hip_stream, dm_ctx** out);
 dm_status dm_destroy(dm_ctx* ctx);
 /* Message of the last error on ctx (empty string if none); owned by ctx. */
 const char* dm_last_error(const dm_ctx* ctx);
-/* Rebind the stream used by later calls. */
+/* Rebind the stream used by later calls; when it changes, the previous
+ * stream is synchronised first. */
 dm_status dm_set_stream(dm_ctx* ctx, void* hip_stream);
 
 /* Candidate vertex pairs (A2).  Distances d(m,n) = ||F_X(m) - F_Y(n)||_2 from

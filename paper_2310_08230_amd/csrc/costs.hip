@@ -89,10 +89,17 @@ __global__ void k_elem_cost(const int32_t* pv, const int32_t* cidx, int64_t nP, 
 __global__ __launch_bounds__(1024) void k_fixed1_sum(const double* c, const int8_t* state, int64_t nP,
                                                      double* out) {
   __shared__ double red[1024];
-  double s = 0.0;
-  for (int64_t p = threadIdx.x; p < nP; p += blockDim.x)
-    if (state[p] == 1) s += c[p];
-  red[threadIdx.x] = s;
+  // eight independent accumulators per thread (fixed order), so the loads of
+  // a thread do not wait on each other
+  double a[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+  for (int64_t p = threadIdx.x; p < nP; p += 8 * int64_t(blockDim.x)) {
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int64_t q = p + int64_t(u) * blockDim.x;
+      if (q < nP && state[q] == 1) a[u] += c[q];
+    }
+  }
+  red[threadIdx.x] = ((((((a[0] + a[1]) + a[2]) + a[3]) + a[4]) + a[5]) + a[6]) + a[7];
   __syncthreads();
   for (int w = blockDim.x / 2; w > 0; w >>= 1) {
     if (int(threadIdx.x) < w) red[threadIdx.x] += red[threadIdx.x + w];

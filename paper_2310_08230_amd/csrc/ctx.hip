@@ -26,6 +26,13 @@ extern "C" dm_status dm_create(int32_t device, void* hip_stream, dm_ctx** out) {
   int n = 0;
   if (hipGetDeviceCount(&n) != hipSuccess || device < 0 || device >= n) return DM_ERR_INVALID_ARG;
   if (hipSetDevice(device) != hipSuccess) return DM_ERR_HIP;
+  // keep memory freed to the device's pool for reuse instead of returning it
+  // at every synchronisation (the library's temporaries come and go per call)
+  hipMemPool_t pool = nullptr;
+  if (hipDeviceGetDefaultMemPool(&pool, device) == hipSuccess && pool) {
+    uint64_t keep = UINT64_MAX;
+    (void)hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &keep);
+  }
   dm_ctx* c = new dm_ctx();
   c->device = device;
   c->stream = static_cast<hipStream_t>(hip_stream);
@@ -45,7 +52,14 @@ extern "C" const char* dm_last_error(const dm_ctx* ctx) { return ctx ? ctx->err.
 
 extern "C" dm_status dm_set_stream(dm_ctx* ctx, void* hip_stream) {
   if (!ctx) return DM_ERR_INVALID_ARG;
-  ctx->stream = static_cast<hipStream_t>(hip_stream);
+  hipStream_t s = static_cast<hipStream_t>(hip_stream);
+  // the context's buffers are ordered on its stream: finish the old stream's
+  // work before later calls order work (and frees) on the new one
+  if (s != ctx->stream) {
+    DM_HIP(ctx, hipSetDevice(ctx->device));
+    DM_HIP(ctx, hipStreamSynchronize(ctx->stream));
+  }
+  ctx->stream = s;
   return DM_OK;
 }
 

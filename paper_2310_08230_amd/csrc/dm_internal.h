@@ -33,31 +33,37 @@ dm_status dm_fail(dm_ctx* ctx, dm_status code, const char* fmt, ...);
 #define DM_LAUNCH_CHECK(ctx) DM_HIP(ctx, hipGetLastError())
 
 // ---------------------------------------------------------------------------
-// owned device array
+// owned device array.  Allocations and frees are stream-ordered on the
+// context's stream (hipMallocAsync / hipFreeAsync from the device's memory
+// pool, which keeps freed memory for reuse): the temporaries of the build
+// steps cost no device-wide synchronisation.  A block freed on a stream is
+// reused only by work ordered after the free on that stream.
 // ---------------------------------------------------------------------------
 template <typename T>
 struct DArr {
   T* p = nullptr;
   size_t n = 0;
+  hipStream_t s = nullptr;   // stream the block was allocated on
   DArr() = default;
   DArr(const DArr&) = delete;
   DArr& operator=(const DArr&) = delete;
   ~DArr() { release(); }
   void release() {
-    if (p) (void)hipFree(p);
+    if (p) (void)hipFreeAsync(p, s);
     p = nullptr;
     n = 0;
   }
-  hipError_t resize(size_t count) {
+  hipError_t resize(size_t count, hipStream_t stream) {
     if (count == n && p) return hipSuccess;
     release();
     n = count;
+    s = stream;
     if (count == 0) return hipSuccess;
-    return hipMalloc(reinterpret_cast<void**>(&p), count * sizeof(T));
+    return hipMallocAsync(reinterpret_cast<void**>(&p), count * sizeof(T), stream);
   }
 };
 
-#define DM_ALLOC(ctx, arr, count) DM_HIP(ctx, (arr).resize(count))
+#define DM_ALLOC(ctx, arr, count) DM_HIP(ctx, (arr).resize(count, (ctx)->stream))
 
 struct MeshDev {
   int32_t nv = 0, nf = 0, ne = 0;

@@ -566,8 +566,20 @@ __global__ void k_pack(const int32_t* seg_row, const int32_t* rrow_ptr, int32_t 
   int32_t r = seg_row[j], r1 = seg_row[j + 1];
   int32_t c = 0, o = fill ? offset[j] : 0;
   while (r < r1) {
-    int32_t r0 = r, e0 = rrow_ptr[r];
-    while (r < r1 && rrow_ptr[r + 1] - e0 <= 64) ++r;
+    const int32_t r0 = r, e0 = rrow_ptr[r];
+    // extend the chunk while the next row still fits, reading eight row
+    // pointers per step (independent loads) instead of one
+    for (;;) {
+      int32_t v[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) v[u] = r + 1 + u <= r1 ? rrow_ptr[r + 1 + u] : INT32_MAX;
+      int adv = 0;
+#pragma unroll
+      for (int u = 0; u < 8; ++u)
+        if (adv == u && r + u < r1 && v[u] - e0 <= 64) adv = u + 1;
+      r += adv;
+      if (adv < 8) break;
+    }
     if (fill) desc[o + c] = make_int4(r0, r - r0, e0, rrow_ptr[r] - e0);
     ++c;
   }
