@@ -847,7 +847,8 @@ extern "C" dm_status dm_dual_solve(dm_ctx* ctx, int32_t iters, double omega, dou
                                    int32_t msg_prec, void* lambda, double* lb_trace) {
   DM_TRY(check_solver(ctx, msg_prec));
   ctx->err.clear();
-  if (iters < 0 || !lambda) return dm_fail(ctx, DM_ERR_INVALID_ARG, "dm_dual_solve: bad arguments");
+  if (iters < 0 || (!lambda && ctx->nnz > 0))
+    return dm_fail(ctx, DM_ERR_INVALID_ARG, "dm_dual_solve: bad arguments");
   if (!(omega > 0.0 && omega <= 1.0)) return dm_fail(ctx, DM_ERR_INVALID_ARG, "omega must be in (0, 1]");
   if (!(temperature >= 0.0)) return dm_fail(ctx, DM_ERR_INVALID_ARG, "temperature must be >= 0");
   DM_HIP(ctx, hipSetDevice(ctx->device));
@@ -858,7 +859,7 @@ extern "C" dm_status dm_dual_solve(dm_ctx* ctx, int32_t iters, double omega, dou
 
 extern "C" dm_status dm_init_lambda(dm_ctx* ctx, int32_t msg_prec, void* lambda) {
   DM_TRY(check_solver(ctx, msg_prec));
-  if (!lambda) return dm_fail(ctx, DM_ERR_INVALID_ARG, "dm_init_lambda: NULL lambda");
+  if (!lambda && ctx->nnz > 0) return dm_fail(ctx, DM_ERR_INVALID_ARG, "dm_init_lambda: NULL lambda");
   DM_HIP(ctx, hipSetDevice(ctx->device));
   if (ctx->nnz == 0) return DM_OK;
   if (msg_prec == DM_PREC_FP32)
@@ -886,7 +887,7 @@ static dm_status bound_impl(dm_ctx* ctx, const R* lam, R T, double* out) {
 extern "C" dm_status dm_lower_bound(dm_ctx* ctx, const void* lambda, double temperature, int32_t msg_prec,
                                     double* lb) {
   DM_TRY(check_solver(ctx, msg_prec));
-  if (!lambda || !lb) return dm_fail(ctx, DM_ERR_INVALID_ARG, "dm_lower_bound: NULL argument");
+  if ((!lambda && ctx->nnz > 0) || !lb) return dm_fail(ctx, DM_ERR_INVALID_ARG, "dm_lower_bound: NULL argument");
   if (!(temperature >= 0.0)) return dm_fail(ctx, DM_ERR_INVALID_ARG, "temperature must be >= 0");
   DM_HIP(ctx, hipSetDevice(ctx->device));
   if (msg_prec == DM_PREC_FP32)

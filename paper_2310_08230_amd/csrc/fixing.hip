@@ -117,7 +117,7 @@ extern "C" dm_status dm_confident_fixing(dm_ctx* ctx, int32_t msg_prec, const vo
   if (!ctx->has_cost) return dm_fail(ctx, DM_ERR_STATE, "no costs built");
   if (msg_prec != DM_PREC_FP32 && msg_prec != DM_PREC_FP64)
     return dm_fail(ctx, DM_ERR_INVALID_ARG, "message precision must be FP32 or FP64");
-  if (!lambda || !fix || !(frac >= 0.0 && frac <= 1.0))
+  if ((!lambda && ctx->nnz > 0) || !fix || !(frac >= 0.0 && frac <= 1.0))
     return dm_fail(ctx, DM_ERR_INVALID_ARG, "dm_confident_fixing: bad arguments");
   DM_HIP(ctx, hipSetDevice(ctx->device));
   if (msg_prec == DM_PREC_FP32)

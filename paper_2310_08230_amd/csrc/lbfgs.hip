@@ -640,7 +640,8 @@ extern "C" dm_status dm_lbfgs_solve(dm_ctx* ctx, int32_t iters, const dm_lbfgs_p
                                     void* lambda, double* lb_trace, double* gamma_trace, int32_t* taken) {
   DM_TRY(check_ready(ctx, msg_prec));
   ctx->err.clear();
-  if (!params || !lambda || iters < 0) return dm_fail(ctx, DM_ERR_INVALID_ARG, "dm_lbfgs_solve: bad arguments");
+  if (!params || (!lambda && ctx->nnz > 0) || iters < 0)
+    return dm_fail(ctx, DM_ERR_INVALID_ARG, "dm_lbfgs_solve: bad arguments");
   const dm_lbfgs_params& P = *params;
   if (P.history < 0 || P.history > 64) return dm_fail(ctx, DM_ERR_INVALID_ARG, "history must be in [0, 64]");
   if (P.max_search < 1 || P.max_search > 64)
@@ -658,7 +659,7 @@ extern "C" dm_status dm_lbfgs_solve(dm_ctx* ctx, int32_t iters, const dm_lbfgs_p
 extern "C" dm_status dm_subgradient(dm_ctx* ctx, int32_t msg_prec, const void* lambda, uint8_t* g, double* lb) {
   DM_TRY(check_ready(ctx, msg_prec));
   ctx->err.clear();
-  if (!lambda || !g) return dm_fail(ctx, DM_ERR_INVALID_ARG, "dm_subgradient: NULL argument");
+  if ((!lambda || !g) && ctx->nnz > 0) return dm_fail(ctx, DM_ERR_INVALID_ARG, "dm_subgradient: NULL argument");
   DM_HIP(ctx, hipSetDevice(ctx->device));
   if (msg_prec == DM_PREC_FP32) return subgradient_impl<float>(ctx, static_cast<const float*>(lambda), g, lb);
   return subgradient_impl<double>(ctx, static_cast<const double*>(lambda), g, lb);

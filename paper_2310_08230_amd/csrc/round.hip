@@ -50,11 +50,19 @@ __global__ void k_agree(const R* mrec, const uint8_t* deg, int64_t nfree, int8_t
   if (p < 0) atomicAdd(reinterpret_cast<unsigned long long*>(count), 1ull);
 }
 
+// one-block sums in a fixed order; eight independent accumulators per thread
+// keep its loads from waiting on each other
 __global__ __launch_bounds__(1024) void k_sum_f64(const double* a, int64_t n, double* out) {
   __shared__ double red[1024];
-  double s = 0.0;
-  for (int64_t i = threadIdx.x; i < n; i += blockDim.x) s += a[i];
-  red[threadIdx.x] = s;
+  double acc[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+  for (int64_t i = threadIdx.x; i < n; i += 8 * int64_t(blockDim.x)) {
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int64_t q = i + int64_t(u) * blockDim.x;
+      if (q < n) acc[u] += a[q];
+    }
+  }
+  red[threadIdx.x] = ((((((acc[0] + acc[1]) + acc[2]) + acc[3]) + acc[4]) + acc[5]) + acc[6]) + acc[7];
   __syncthreads();
   for (int w = blockDim.x / 2; w > 0; w >>= 1) {
     if (int(threadIdx.x) < w) red[threadIdx.x] += red[threadIdx.x + w];
@@ -96,10 +104,15 @@ __global__ __launch_bounds__(256) void k_violations_proj(const int32_t* row_ptr,
 
 __global__ __launch_bounds__(1024) void k_primal_obj(const double* c, const uint8_t* x, int64_t nP, double* out) {
   __shared__ double red[1024];
-  double s = 0.0;
-  for (int64_t p = threadIdx.x; p < nP; p += blockDim.x)
-    if (x[p]) s += c[p];
-  red[threadIdx.x] = s;
+  double acc[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+  for (int64_t p = threadIdx.x; p < nP; p += 8 * int64_t(blockDim.x)) {
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int64_t q = p + int64_t(u) * blockDim.x;
+      if (q < nP && x[q]) acc[u] += c[q];
+    }
+  }
+  red[threadIdx.x] = ((((((acc[0] + acc[1]) + acc[2]) + acc[3]) + acc[4]) + acc[5]) + acc[6]) + acc[7];
   __syncthreads();
   for (int w = blockDim.x / 2; w > 0; w >>= 1) {
     if (int(threadIdx.x) < w) red[threadIdx.x] += red[threadIdx.x + w];
@@ -207,7 +220,7 @@ extern "C" dm_status dm_round_primal(dm_ctx* ctx, const dm_round_params* params,
   if (!ctx) return DM_ERR_INVALID_ARG;
   ctx->err.clear();
   if (!ctx->has_space || !ctx->has_cost) return dm_fail(ctx, DM_ERR_STATE, "dm_round_primal: build space and costs first");
-  if (!params || !lambda || !x || !primal_obj || !feasible || !rounds_used)
+  if (!params || (!lambda && ctx->nnz > 0) || !x || !primal_obj || !feasible || !rounds_used)
     return dm_fail(ctx, DM_ERR_INVALID_ARG, "dm_round_primal: NULL argument");
   const dm_round_params& P = *params;
   if (P.rounds < 0 || P.iters_per_round < 0 || !(P.gamma > 0.0) || !(P.omega > 0.0 && P.omega <= 1.0))

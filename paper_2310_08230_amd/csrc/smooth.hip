@@ -125,7 +125,7 @@ extern "C" dm_status dm_smoothed_backward(dm_ctx* ctx, const void* lambda, doubl
   if (!ctx) return DM_ERR_INVALID_ARG;
   ctx->err.clear();
   if (!ctx->has_space || !ctx->has_cost) return dm_fail(ctx, DM_ERR_STATE, "dm_smoothed_backward: build space and costs first");
-  if (!lambda || !FX || !FY || !gFX || !gFY || D < 1)
+  if ((!lambda && ctx->nnz > 0) || !FX || !FY || !gFX || !gFY || D < 1)
     return dm_fail(ctx, DM_ERR_INVALID_ARG, "dm_smoothed_backward: bad arguments");
   if (!(temperature > 0.0)) return dm_fail(ctx, DM_ERR_INVALID_ARG, "dm_smoothed_backward: temperature must be > 0");
   DM_HIP(ctx, hipSetDevice(ctx->device));

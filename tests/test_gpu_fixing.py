@@ -133,3 +133,30 @@ def test_fixing_full_size():
         say(f"  fixings infeasible: {e}")
     ctx.fix_variables(None)
     assert ctx.info == info0
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_everything_fixed_leaves_an_empty_residual(prec):
+    """Fixing every variable to a feasible primal leaves no free variable and
+    no row: multipliers are empty, every solver returns the constant bound
+    (the primal objective itself), and rounding returns that primal."""
+    p = make_pair(1, 0)
+    S, ctx = both(p, 6, "fp64")
+    lam, _ = ctx.dual_solve(ctx.init_lambda(prec), 50, 0.5)
+    x, pobj, feas, _ = ctx.round_primal(lam)
+    assert feas
+    info = ctx.fix_variables(x.to(torch.int8))
+    assert info["n_free"] == 0 and info["n_rows"] == 0 and info["nnz"] == 0
+    lam0 = ctx.init_lambda(prec)
+    assert lam0.numel() == 0
+    _, tr = ctx.dual_solve(lam0, 3, 0.5)
+    assert np.allclose(np_(tr), pobj, rtol=1e-12)
+    _, qtr, _, qtk = ctx.lbfgs_solve(lam0, 3)
+    assert np.allclose(np_(qtr), pobj, rtol=1e-12) and not np_(qtk).any()
+    assert abs(ctx.lower_bound(lam0) - pobj) <= 1e-12 * abs(pobj)
+    x2, p2, feas2, _ = ctx.round_primal(lam0)
+    assert feas2 and torch.equal(x2, x) and abs(p2 - pobj) <= 1e-12 * abs(pobj)
+    fix, na, nf = ctx.confident_fixing(lam0, 0.9)
+    assert na == 0 and nf == 0 and torch.equal(fix, x.to(torch.int8))
+    ctx.fix_variables(None)
+    assert ctx.info["n_free"] == S.info["n_free"]
