@@ -44,6 +44,7 @@ def parse():
     ap.add_argument("--iters", type=int, default=None)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-gap", action="store_true")
+    ap.add_argument("--no-pairs", action="store_true", help="skip the per-pair sweep rooflines")
     ap.add_argument("--cpu-sample-iters", type=int, default=100)
     return ap.parse_args()
 
@@ -86,6 +87,29 @@ class Workload:
             out.update(pobj=pobj, feasible=feas, rounds=rounds,
                        gap=(pobj - dmax) / pobj if pobj else 0.0)
         return out
+
+
+def sweep_roofline(cfg, seed, iters=200):
+    """Sweep kernel of one pair, timed per launch by the kernel's own events
+    over ``iters`` Jacobi iterations: microseconds per launch and algorithmic
+    GB/s (12 B per nonzero + 4 B per row) against the HBM peak."""
+    w = Workload(cfg, seed)
+    c = w.ctx
+    cxy, cyx = c.knn_candidates(w.DX, w.DY, w.spec.k, w.knn_prec)
+    info = c.build_product_space(w.VX, w.FX, w.VY, w.FY, cxy, cyx)
+    c.build_costs(w.DX, w.DY, w.cost)
+    lam = c.init_lambda(w.msg)
+    c.dual_solve(lam, 20, w.spec.omega, trace=False)
+    c.timing(True)
+    c.dual_solve(lam, iters, w.spec.omega)
+    n, ms = c.timing_read()
+    c.timing(False)
+    us = ms * 1e3 / max(n, 1)
+    nbytes = BYTES_PER_NNZ * info["nnz"] + BYTES_PER_ROW * info["n_rows"]
+    gbs = nbytes / (us * 1e-6) / 1e9
+    return {"pair": f"{w.spec.faces_x}/{w.spec.faces_y} faces", "nnz": info["nnz"], "rows": info["n_rows"],
+            "avg_launch_us": round(us, 2), "bytes_per_launch": nbytes, "achieved_GBps": round(gbs, 1),
+            "frac": round(gbs / HBM_PEAK_GBS, 4)}
 
 
 def time_to_gap(cfg, seed, smoothed=False, check_every=50, max_iters=2000, smooth_iters=50, solver="jacobi",
@@ -195,7 +219,7 @@ def copy_calibration(nbytes, reps=5):
 
 
 def summarize_counters(fetch_csv, write_csv, copy_fetch_csv, copy_write_csv, out_json, copy_bytes,
-                       command=""):
+                       command="", workload="plain_fp32_500 (config 2, seed 0)"):
     """Turn rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE collections (KiB per
     dispatch) of the sweep kernel and of a plain copy of ``copy_bytes`` bytes
     into HBM bytes per sweep launch; writes the summary JSON used by the
@@ -218,7 +242,7 @@ def summarize_counters(fetch_csv, write_csv, copy_fetch_csv, copy_write_csv, out
     fetch_b = f * ffac * 1024.0
     write_b = wv * wfac * 1024.0
     src = os.path.join(ROOT, "paper_2310_08230_amd", "csrc", "dual.hip")
-    rec = {"kernel": "k_sweep<float,false,MODE_UPDATE>", "workload": "plain_fp32_500 (config 2, seed 0)",
+    rec = {"kernel": "k_sweep<float,false,MODE_UPDATE>", "workload": workload,
            "fetch_kib_median": f, "write_kib_median": wv, "dispatches": [nf, nw],
            "copy_calibration": {"bytes": copy_bytes, "fetch_kib": cf, "write_kib": cw,
                                 "fetch_factor": ffac, "write_factor": wfac},
@@ -250,7 +274,8 @@ def summarize_trace(stats_csv, out_txt, command):
 
 def main():
     if len(sys.argv) > 1 and sys.argv[1] == "--summarize-counters":
-        summarize_counters(*sys.argv[2:7], int(sys.argv[7]), " ".join(sys.argv[8:]))
+        # fetch write copy_fetch copy_write out_json copy_bytes workload command...
+        summarize_counters(*sys.argv[2:7], int(sys.argv[7]), " ".join(sys.argv[9:]), sys.argv[8])
         return
     if len(sys.argv) > 1 and sys.argv[1] == "--copy-calibration":
         copy_calibration(int(sys.argv[2]))
@@ -318,6 +343,11 @@ def main():
            "roofline": roof,
            "sweep_iters_per_s": round(w.iters / solve_s, 1),
            "gap_at_end": r["gap"], "primal_feasible": r["feasible"]}
+    out["sweep_by_pair"] = {}
+    for cfg in (() if a.no_pairs else (3, 5)):
+        log(f"[bench] sweep roofline, config {cfg}")
+        out["sweep_by_pair"][f"config_{cfg}"] = sweep_roofline(cfg, a.seed)
+        log(f"[bench]   {out['sweep_by_pair'][f'config_{cfg}']}")
     if not a.no_gap:
         gaps = {}
         # (name, config, smoothed, Jacobi check interval, quasi-Newton check interval)
