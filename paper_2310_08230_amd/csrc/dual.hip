@@ -54,15 +54,38 @@ template <>
 __device__ inline float r_log<float>(float x) { return logf(x); }
 template <>
 __device__ inline double r_log<double>(double x) { return log(x); }
+template <typename R>
+__device__ inline R r_log1p(R x);
+template <>
+__device__ inline float r_log1p<float>(float x) { return log1pf(x); }
+template <>
+__device__ inline double r_log1p<double>(double x) { return log1p(x); }
 
-// soft-min of two values (hard min when T == 0)
+// soft-min of two values (hard min when T == 0):
+// -T log(e^{-a/T} + e^{-b/T}) = min(a, b) - T log1p(e^{-|a-b|/T})
 template <typename R, bool SOFT>
 __device__ inline R smin2(R a, R b, R T) {
   if (!SOFT) return a < b ? a : b;
   if (a == rinf<R>()) return b;
   if (b == rinf<R>()) return a;
-  R m = a < b ? a : b;
-  return m - T * r_log<R>(r_exp<R>(-(a - m) / T) + r_exp<R>(-(b - m) / T));
+  const R m = a < b ? a : b, d = a < b ? b - a : a - b;
+  return m - T * r_log1p<R>(r_exp<R>(-d / T));
+}
+
+// soft-min over the 32 lanes of a segment, every lane gets the result: the
+// hard minimum, one exponential per lane, a sum, one logarithm (inf when every
+// lane holds inf)
+template <typename R>
+__device__ inline R seg_softmin32(R x, R T) {
+  R m = x;
+  for (int off = 16; off > 0; off >>= 1) {
+    const R o = __shfl_xor(m, off, 32);
+    m = o < m ? o : m;
+  }
+  if (m == rinf<R>()) return m;
+  R e = x == rinf<R>() ? R(0) : r_exp<R>(-(x - m) / T);
+  for (int off = 16; off > 0; off >>= 1) e += __shfl_xor(e, off, 32);
+  return m - T * r_log<R>(e);
 }
 
 // multiplier of entry word w from the previous record buffer, with dual
@@ -382,10 +405,8 @@ __device__ void short_rows_soft(const SweepArgs& A, const R* __restrict__ rin, R
       if (lane + a < 0 || lane + a > 31 || !valid) sh = rinf<R>();
       R x1 = (Fl == rinf<R>() || sh == rinf<R>()) ? rinf<R>() : Fl + lamL[l] + sh;
       R x0 = (Fl == rinf<R>() || Bv == rinf<R>()) ? rinf<R>() : Fl + Bv;
-      for (int off = 16; off > 0; off >>= 1) {
-        x1 = smin2<R, true>(x1, __shfl_xor(x1, off, 32), T);
-        x0 = smin2<R, true>(x0, __shfl_xor(x0, off, 32), T);
-      }
+      x1 = seg_softmin32<R>(x1, T);
+      x0 = seg_softmin32<R>(x0, T);
       if (lane == l) {
         myM = x1 - x0;
         my1 = x1;
