@@ -215,6 +215,8 @@ struct dm_ctx {
   DArr<unsigned long long> chunk_mask;  // per chunk: bit e set when entry e starts a row
   DArr<uint32_t> chunk_word;  // 64 per chunk: the chunk's entry words, CHUNK_PAD past its end
   DArr<int8_t> chunk_b;       // 64 per chunk: right-hand side of each entry's row
+  DArr<int32_t> soft_row;     // short rows sorted (stably) by length, for the smoothed sweep
+  int64_t soft_c8 = 0, soft_c16 = 0;   // how many of them have <= 7 / 8..15 entries
 
   // costs
   bool has_cost = false;

@@ -72,19 +72,63 @@ __device__ inline R smin2(R a, R b, R T) {
   return m - T * r_log1p<R>(r_exp<R>(-d / T));
 }
 
-// soft-min over the 32 lanes of a segment, every lane gets the result: the
+// One DPP lane move (a VALU operation): ctrl 0xB1 swaps neighbours (quad
+// permutation 1,0,3,2), 0x4E swaps pairs (2,3,0,1), 0x141 mirrors each group of
+// eight lanes, 0x140 each row of sixteen; 0x138 shifts the whole wave by one
+// lane (lane i reads lane i - 1), 0x130 the other way (lane i reads i + 1).
+// A lane whose source is missing reads 0; callers mask those lanes.
+template <int CTRL, typename R>
+__device__ inline R dpp_move(R v) {
+  if constexpr (sizeof(R) == 4) {
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, false));
+  } else {
+    const long long bits = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_update_dpp(0, int(bits & 0xFFFFFFFFll), CTRL, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, int(bits >> 32), CTRL, 0xF, 0xF, false);
+    return __longlong_as_double((static_cast<long long>(hi) << 32) | (static_cast<long long>(lo) & 0xFFFFFFFFll));
+  }
+}
+
+// min / sum over the W lanes (W = 8, 16 or 32) of an aligned segment, the same
+// value in every lane: DPP steps within each sixteen-lane row (every pairing
+// is symmetric, so all lanes form the same sums), one shuffle joins two rows
+template <int W, typename R>
+__device__ inline R seg_min(R v) {
+  R o = dpp_move<0xB1>(v);
+  v = o < v ? o : v;
+  o = dpp_move<0x4E>(v);
+  v = o < v ? o : v;
+  o = dpp_move<0x141>(v);
+  v = o < v ? o : v;
+  if constexpr (W >= 16) {
+    o = dpp_move<0x140>(v);
+    v = o < v ? o : v;
+  }
+  if constexpr (W == 32) {
+    o = __shfl_xor(v, 16, 32);
+    v = o < v ? o : v;
+  }
+  return v;
+}
+
+template <int W, typename R>
+__device__ inline R seg_sum(R v) {
+  v += dpp_move<0xB1>(v);
+  v += dpp_move<0x4E>(v);
+  v += dpp_move<0x141>(v);
+  if constexpr (W >= 16) v += dpp_move<0x140>(v);
+  if constexpr (W == 32) v += __shfl_xor(v, 16, 32);
+  return v;
+}
+
+// soft-min over the W lanes of a segment, every lane gets the result: the
 // hard minimum, one exponential per lane, a sum, one logarithm (inf when every
 // lane holds inf)
-template <typename R>
-__device__ inline R seg_softmin32(R x, R T) {
-  R m = x;
-  for (int off = 16; off > 0; off >>= 1) {
-    const R o = __shfl_xor(m, off, 32);
-    m = o < m ? o : m;
-  }
+template <int W, typename R>
+__device__ inline R seg_softmin(R x, R T) {
+  const R m = seg_min<W, R>(x);
   if (m == rinf<R>()) return m;
-  R e = x == rinf<R>() ? R(0) : r_exp<R>(-(x - m) / T);
-  for (int off = 16; off > 0; off >>= 1) e += __shfl_xor(e, off, 32);
+  const R e = seg_sum<W, R>(x == rinf<R>() ? R(0) : r_exp<R>(-(x - m) / T));
   return m - T * r_log<R>(e);
 }
 
@@ -131,6 +175,8 @@ __device__ inline void reduce_partials(const double* partial, int n, double offs
 struct SweepArgs {
   const uint32_t* word;
   const int32_t* rrow_ptr;
+  const int32_t* soft_row;  // short rows in order of length (smoothed form)
+  int32_t soft_c8, soft_c16;  // short rows of at most 7 / of 8 to 15 entries
   const int32_t* rrow_b;
   const int4* chunk_desc;   // (first row, rows, first entry, entries) per chunk
   const unsigned long long* chunk_mask;   // bit e: entry e of the chunk starts a row
@@ -353,22 +399,30 @@ __device__ void short_wave_hard(const SweepArgs& A, const R* __restrict__ rin, R
 }
 
 // ---------------------------------------------------------------- short rows, soft min
-// one 32-lane segment per row; lane j holds the partial sum sigma = j - N of
-// the recursion F_{l+1}(sigma) = smin(F_l(sigma), F_l(sigma - a_l) + lam_l),
-// B_l(sigma) = smin(B_{l+1}(sigma), B_{l+1}(sigma + a_l) + lam_l)
-template <typename R, int MODE>
+// One W-lane segment per row (W = 8, 16, 32 for rows of at most 7, 15, 24
+// entries; the rows are taken in order of length from soft_row); lane j holds
+// the partial sum sigma = j - N of the recursion
+// F_{l+1}(sigma) = smin(F_l(sigma), F_l(sigma - a_l) + lam_l),
+// B_l(sigma) = smin(B_{l+1}(sigma), B_{l+1}(sigma + a_l) + lam_l).
+// Rows [row0, row1) of soft_row belong to this width; blk counts the blocks of
+// this width, item is the block's index among all blocks.
+template <typename R, int MODE, int W>
 __device__ void short_rows_soft(const SweepArgs& A, const R* __restrict__ rin, R* __restrict__ out, R omega,
-                                R T, unsigned char* smem, double* red, int32_t item) {
-  const int seg = threadIdx.x >> 5, lane = threadIdx.x & 31;
-  R* Ftab = reinterpret_cast<R*>(smem) + seg * (SOFT_MAX_ROW * 32);
-  R* lamL = reinterpret_cast<R*>(smem) + 8 * SOFT_MAX_ROW * 32 + seg * 32;
-  int8_t* aL = reinterpret_cast<int8_t*>(reinterpret_cast<R*>(smem) + 8 * SOFT_MAX_ROW * 32 + 8 * 32) + seg * 32;
-  const int32_t j = item * 8 + seg;
-  const bool act = j < A.n_short;
+                                R T, unsigned char* smem, double* red, int32_t item, int32_t blk, int32_t row0,
+                                int32_t row1) {
+  constexpr int RPB = 256 / W;                            // rows per block
+  constexpr int NMAX = W == 32 ? SOFT_MAX_ROW : W - 1;    // entries per row at most
+  const int seg = threadIdx.x / W, lane = threadIdx.x % W;
+  R* Ftab = reinterpret_cast<R*>(smem) + seg * (NMAX * W);
+  R* lamL = reinterpret_cast<R*>(smem) + 256 * SOFT_MAX_ROW + seg * W;
+  int8_t* aL = reinterpret_cast<int8_t*>(reinterpret_cast<R*>(smem) + 256 * SOFT_MAX_ROW + 256) + seg * W;
+  const int32_t r = row0 + blk * RPB + seg;
+  const bool act = r < row1;
   int32_t s = 0, n = 0, b = 0;
   uint32_t w = 0;
   R mylam = R(0);
   if (act) {
+    const int32_t j = A.soft_row[r];
     s = A.rrow_ptr[j];
     n = A.rrow_ptr[j + 1] - s;
     b = A.rrow_b[j];
@@ -389,10 +443,10 @@ __device__ void short_rows_soft(const SweepArgs& A, const R* __restrict__ rin, R
     const bool valid = lane <= P + N;
     R F = (valid && sigma == 0) ? R(0) : rinf<R>();
     for (int32_t l = 0; l < n; ++l) {
-      Ftab[l * 32 + lane] = F;   // read back below by the same lane only
+      Ftab[l * W + lane] = F;   // read back below by the same lane only
       const int a = aL[l];
-      R sh = __shfl(F, lane - a, 32);
-      if (lane - a < 0 || lane - a > 31 || !valid) sh = rinf<R>();
+      R sh = a > 0 ? dpp_move<0x138>(F) : dpp_move<0x130>(F);   // F[lane - a]
+      if (lane - a < 0 || lane - a >= W || !valid) sh = rinf<R>();
       F = smin2<R, true>(F, sh + lamL[l], T);
       if (!valid) F = rinf<R>();
     }
@@ -400,13 +454,13 @@ __device__ void short_rows_soft(const SweepArgs& A, const R* __restrict__ rin, R
     R myM = R(0), my1 = R(0);
     for (int32_t l = n - 1; l >= 0; --l) {
       const int a = aL[l];
-      const R Fl = Ftab[l * 32 + lane];
-      R sh = __shfl(Bv, lane + a, 32);
-      if (lane + a < 0 || lane + a > 31 || !valid) sh = rinf<R>();
+      const R Fl = Ftab[l * W + lane];
+      R sh = a > 0 ? dpp_move<0x130>(Bv) : dpp_move<0x138>(Bv);  // Bv[lane + a]
+      if (lane + a < 0 || lane + a >= W || !valid) sh = rinf<R>();
       R x1 = (Fl == rinf<R>() || sh == rinf<R>()) ? rinf<R>() : Fl + lamL[l] + sh;
       R x0 = (Fl == rinf<R>() || Bv == rinf<R>()) ? rinf<R>() : Fl + Bv;
-      x1 = seg_softmin32<R>(x1, T);
-      x0 = seg_softmin32<R>(x0, T);
+      x1 = seg_softmin<W, R>(x1, T);
+      x0 = seg_softmin<W, R>(x0, T);
       if (lane == l) {
         myM = x1 - x0;
         my1 = x1;
@@ -415,7 +469,7 @@ __device__ void short_rows_soft(const SweepArgs& A, const R* __restrict__ rin, R
       if (!valid) Bv = rinf<R>();
     }
     // soft row value B_0(0) sits on lane N
-    const R rowv = __shfl(Bv, N, 32);
+    const R rowv = __shfl(Bv, N, W);
     if (lane < n) {
       if (MODE == MODE_UPDATE) write_out<R>(out, w, mylam - omega * myM);
       if (MODE == MODE_EVAL) write_out<R>(out, w, r_exp<R>(-(my1 - rowv) / T));
@@ -591,7 +645,7 @@ __device__ void long_rows(const SweepArgs& A, const R* __restrict__ rin, R* __re
 
 template <typename R, bool SOFT>
 constexpr size_t smem_bytes() {
-  return SOFT ? (8 * SOFT_MAX_ROW * 32 + 8 * 32) * sizeof(R) + 8 * 32 : 16;
+  return SOFT ? (256 * SOFT_MAX_ROW + 256) * sizeof(R) + 256 : 16;
 }
 
 template <typename R, bool SOFT, int MODE>
@@ -623,7 +677,17 @@ __global__ __launch_bounds__(256) void k_sweep(SweepArgs A, const R* __restrict_
     item = c;
   }
   if (item < A.n_short_blocks) {
-    if (SOFT) short_rows_soft<R, MODE>(A, rin, out, omega, T, smem, red, item);
+    if (SOFT) {
+      const int32_t nb8 = (A.soft_c8 + 31) / 32, nb16 = (A.soft_c16 + 15) / 16;
+      const int32_t c816 = A.soft_c8 + A.soft_c16;
+      if (item < nb8)
+        short_rows_soft<R, MODE, 8>(A, rin, out, omega, T, smem, red, item, item, 0, A.soft_c8);
+      else if (item < nb8 + nb16)
+        short_rows_soft<R, MODE, 16>(A, rin, out, omega, T, smem, red, item, item - nb8, A.soft_c8, c816);
+      else
+        short_rows_soft<R, MODE, 32>(A, rin, out, omega, T, smem, red, item, item - nb8 - nb16, c816,
+                                     A.n_short);
+    }
     else short_wave_hard<R, MODE>(A, rin, out, omega, gam, red, item);
   } else {
     long_rows<R, SOFT, MODE>(A, rin, out, omega, T, gam, red, item);
@@ -733,7 +797,12 @@ dm_status dual_sweep(dm_ctx* ctx, int mode, bool soft, const unsigned char* rin,
   A.chunk_word = ctx->chunk_word.p;
   A.chunk_b = ctx->chunk_b.p;
   A.n_chunks = ctx->n_chunks;
-  A.n_short_blocks = soft ? int32_t((ctx->n_short + 7) / 8) : int32_t((ctx->n_chunks + 3) / 4);
+  A.soft_row = ctx->soft_row.p;
+  A.soft_c8 = int32_t(ctx->soft_c8);
+  A.soft_c16 = int32_t(ctx->soft_c16);
+  const int64_t soft_blocks =
+      (ctx->soft_c8 + 31) / 32 + (ctx->soft_c16 + 15) / 16 + (ctx->n_short - ctx->soft_c8 - ctx->soft_c16 + 7) / 8;
+  A.n_short_blocks = soft ? int32_t(soft_blocks) : int32_t((ctx->n_chunks + 3) / 4);
   // projection rows of more than LONG_BLOCK_ROW entries on average get a whole block each
   const int64_t n_long = ctx->n_rows - ctx->n_short;
   A.long_wpr = (n_long > 0 && (ctx->nnz - ctx->nnz_short) / n_long > LONG_BLOCK_ROW) ? 4 : 1;
@@ -754,7 +823,7 @@ dm_status dual_sweep(dm_ctx* ctx, int mode, bool soft, const unsigned char* rin,
     return DM_OK;
   }
   // two halves of the partial buffer alternate between consecutive launches
-  const int64_t cap = std::max<int64_t>(ctx->n_chunks, (ctx->n_short + 7) / 8) + n_long_blocks;
+  const int64_t cap = std::max<int64_t>((ctx->n_chunks + 3) / 4, soft_blocks) + n_long_blocks;
   if (ctx->partial.n < size_t(2 * cap)) {
     DM_TRY(dual_flush(ctx));
     DM_ALLOC(ctx, ctx->partial, size_t(2 * cap));

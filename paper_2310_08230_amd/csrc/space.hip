@@ -504,6 +504,22 @@ __global__ void k_row_stats(const int32_t* rrow_ptr, const int32_t* rrow_b, cons
   }
 }
 
+__global__ void k_row_len(const int32_t* rrow_ptr, int64_t n_short, uint32_t* len, int32_t* row) {
+  int64_t j = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (j >= n_short) return;
+  len[j] = uint32_t(rrow_ptr[j + 1] - rrow_ptr[j]);
+  row[j] = int32_t(j);
+}
+
+// bound[0] / bound[1]: how many of the sorted lengths are <= 7 / <= 15
+__global__ void k_len_bounds(const uint32_t* len, int64_t n, int32_t* bound) {
+  int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const uint32_t nxt = i + 1 < n ? len[i + 1] : 0xFFFFFFFFu;
+  if (len[i] <= 7 && nxt > 7) bound[0] = int32_t(i + 1);
+  if (len[i] <= 15 && nxt > 15) bound[1] = int32_t(i + 1);
+}
+
 // Short rows are packed greedily, in row order, into wave chunks of at most
 // 64 entries (one entry per lane, whole rows only).  The greedy walk runs in
 // parallel over segments of PACK_SEG entries: segment j holds the rows whose
@@ -889,7 +905,26 @@ dm_status presolve_reduce(dm_ctx* ctx, const int8_t* fix) {
         ctx->chunk_desc.p, ctx->chunk_mask.p, ctx->rent_word.p, ctx->rrow_b.p, n_chunks, ctx->chunk_word.p,
         ctx->chunk_b.p);
   DM_LAUNCH_CHECK(ctx);
+  // the smoothed sweep takes short rows in order of length, in segments of
+  // 8, 16 or 32 lanes
+  DArr<uint32_t> len;
+  DArr<int32_t> bound;
+  DM_ALLOC(ctx, ctx->soft_row, size_t(std::max<int64_t>(nshort, 1)));
+  DM_ALLOC(ctx, len, size_t(std::max<int64_t>(nshort, 1)));
+  DM_ALLOC(ctx, bound, 2);
+  DM_HIP(ctx, hipMemsetAsync(bound.p, 0, 2 * sizeof(int32_t), st));
+  if (nshort > 0) {
+    k_row_len<<<grid_for(nshort, 256), 256, 0, st>>>(ctx->rrow_ptr.p, nshort, len.p, ctx->soft_row.p);
+    DM_LAUNCH_CHECK(ctx);
+    DM_TRY(sort_pairs_u32(ctx, len.p, ctx->soft_row.p, size_t(nshort), 7));
+    k_len_bounds<<<grid_for(nshort, 256), 256, 0, st>>>(len.p, nshort, bound.p);
+    DM_LAUNCH_CHECK(ctx);
+  }
+  int32_t bnd[2];
+  DM_HIP(ctx, hipMemcpyAsync(bnd, bound.p, sizeof(bnd), hipMemcpyDeviceToHost, st));
   DM_HIP(ctx, hipStreamSynchronize(st));
+  ctx->soft_c8 = bnd[0];
+  ctx->soft_c16 = bnd[1] - bnd[0];
   return DM_OK;
 }
 
@@ -930,7 +965,10 @@ extern "C" dm_status dm_fix_variables(dm_ctx* ctx, const int8_t* fix, dm_space_i
   if (s != DM_OK) {
     // keep the message, restore the problem without fixings
     const std::string msg = ctx->err;
-    DM_TRY(presolve_reduce(ctx, nullptr));
+    if (presolve_reduce(ctx, nullptr) != DM_OK) {
+      ctx->has_space = false;   // the reduced problem is half rebuilt: unusable
+      return DM_ERR_STATE;
+    }
     if (ctx->has_cost) DM_TRY(cost_offset(ctx));
     ctx->err = msg;
     if (info) fill_info(ctx, info);
