@@ -72,6 +72,37 @@ __device__ inline R smin2(R a, R b, R T) {
   return m - T * r_log1p<R>(r_exp<R>(-d / T));
 }
 
+// Scaled soft-min arithmetic for the short-row recursion.  Values are kept in
+// units u = x / (T ln 2) (FP32) or u = x / T (FP64), so that the soft-min of
+// two values is min - L(1 + E(-|a - b|)) and of many min - L(sum E(u - min))
+// with E = 2^x, L = log2 (FP32: the hardware exp2 / log2 instructions, about
+// one ulp) or E = exp, L = log (FP64).
+template <typename R>
+struct SoftUnits;
+template <>
+struct SoftUnits<float> {
+  static __device__ float unit(float T) { return T * 0.693147180559945309f; }   // x = u * unit
+  static __device__ float E(float x) { return __builtin_amdgcn_exp2f(x); }
+  static __device__ float L(float x) { return __builtin_amdgcn_logf(x); }
+  static __device__ float L1p(float x) { return __builtin_amdgcn_logf(1.0f + x); }
+};
+template <>
+struct SoftUnits<double> {
+  static __device__ double unit(double T) { return T; }
+  static __device__ double E(double x) { return exp(x); }
+  static __device__ double L(double x) { return log(x); }
+  static __device__ double L1p(double x) { return log1p(x); }
+};
+
+// soft-min of two values in scaled units
+template <typename R>
+__device__ inline R smin2u(R a, R b) {
+  if (a == rinf<R>()) return b;
+  if (b == rinf<R>()) return a;
+  const R m = a < b ? a : b, d = a < b ? b - a : a - b;
+  return m - SoftUnits<R>::L1p(SoftUnits<R>::E(-d));
+}
+
 // One DPP lane move (a VALU operation): ctrl 0xB1 swaps neighbours (quad
 // permutation 1,0,3,2), 0x4E swaps pairs (2,3,0,1), 0x141 mirrors each group of
 // eight lanes, 0x140 each row of sixteen; 0x138 shifts the whole wave by one
@@ -80,11 +111,11 @@ __device__ inline R smin2(R a, R b, R T) {
 template <int CTRL, typename R>
 __device__ inline R dpp_move(R v) {
   if constexpr (sizeof(R) == 4) {
-    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, false));
+    return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), CTRL, 0xF, 0xF, true));
   } else {
     const long long bits = __double_as_longlong(v);
-    const int lo = __builtin_amdgcn_update_dpp(0, int(bits & 0xFFFFFFFFll), CTRL, 0xF, 0xF, false);
-    const int hi = __builtin_amdgcn_update_dpp(0, int(bits >> 32), CTRL, 0xF, 0xF, false);
+    const int lo = __builtin_amdgcn_mov_dpp(int(bits & 0xFFFFFFFFll), CTRL, 0xF, 0xF, true);
+    const int hi = __builtin_amdgcn_mov_dpp(int(bits >> 32), CTRL, 0xF, 0xF, true);
     return __longlong_as_double((static_cast<long long>(hi) << 32) | (static_cast<long long>(lo) & 0xFFFFFFFFll));
   }
 }
@@ -92,22 +123,17 @@ __device__ inline R dpp_move(R v) {
 // min / sum over the W lanes (W = 8, 16 or 32) of an aligned segment, the same
 // value in every lane: DPP steps within each sixteen-lane row (every pairing
 // is symmetric, so all lanes form the same sums), one shuffle joins two rows
+// min of two values that are never NaN
+__device__ inline float vmin(float a, float b) { return fminf(a, b); }
+__device__ inline double vmin(double a, double b) { return fmin(a, b); }
+
 template <int W, typename R>
 __device__ inline R seg_min(R v) {
-  R o = dpp_move<0xB1>(v);
-  v = o < v ? o : v;
-  o = dpp_move<0x4E>(v);
-  v = o < v ? o : v;
-  o = dpp_move<0x141>(v);
-  v = o < v ? o : v;
-  if constexpr (W >= 16) {
-    o = dpp_move<0x140>(v);
-    v = o < v ? o : v;
-  }
-  if constexpr (W == 32) {
-    o = __shfl_xor(v, 16, 32);
-    v = o < v ? o : v;
-  }
+  v = vmin(v, dpp_move<0xB1>(v));
+  v = vmin(v, dpp_move<0x4E>(v));
+  v = vmin(v, dpp_move<0x141>(v));
+  if constexpr (W >= 16) v = vmin(v, dpp_move<0x140>(v));
+  if constexpr (W == 32) v = vmin(v, __shfl_xor(v, 16, 32));
   return v;
 }
 
@@ -121,15 +147,15 @@ __device__ inline R seg_sum(R v) {
   return v;
 }
 
-// soft-min over the W lanes of a segment, every lane gets the result: the
-// hard minimum, one exponential per lane, a sum, one logarithm (inf when every
-// lane holds inf)
+// soft-min over the W lanes of a segment in scaled units, every lane gets the
+// result: the hard minimum, one exponential per lane, a sum, one logarithm
+// (inf when every lane holds inf)
 template <int W, typename R>
-__device__ inline R seg_softmin(R x, R T) {
+__device__ inline R seg_softmin(R x) {
   const R m = seg_min<W, R>(x);
   if (m == rinf<R>()) return m;
-  const R e = seg_sum<W, R>(x == rinf<R>() ? R(0) : r_exp<R>(-(x - m) / T));
-  return m - T * r_log<R>(e);
+  const R e = seg_sum<W, R>(x == rinf<R>() ? R(0) : SoftUnits<R>::E(m - x));
+  return m - SoftUnits<R>::L(e);
 }
 
 // multiplier of entry word w from the previous record buffer, with dual
@@ -421,6 +447,7 @@ __device__ void short_rows_soft(const SweepArgs& A, const R* __restrict__ rin, R
   int32_t s = 0, n = 0, b = 0;
   uint32_t w = 0;
   R mylam = R(0);
+  const R unit = SoftUnits<R>::unit(T), inv_unit = R(1) / unit;
   if (act) {
     const int32_t j = A.soft_row[r];
     s = A.rrow_ptr[j];
@@ -429,7 +456,7 @@ __device__ void short_rows_soft(const SweepArgs& A, const R* __restrict__ rin, R
     if (lane < n) {
       w = A.word[s + lane];
       mylam = cur_lambda<R>(rin, w);
-      lamL[lane] = mylam;
+      lamL[lane] = mylam * inv_unit;
       aL[lane] = (w >> 31) ? int8_t(-1) : int8_t(1);
     }
   }
@@ -447,7 +474,7 @@ __device__ void short_rows_soft(const SweepArgs& A, const R* __restrict__ rin, R
       const int a = aL[l];
       R sh = a > 0 ? dpp_move<0x138>(F) : dpp_move<0x130>(F);   // F[lane - a]
       if (lane - a < 0 || lane - a >= W || !valid) sh = rinf<R>();
-      F = smin2<R, true>(F, sh + lamL[l], T);
+      F = smin2u<R>(F, sh + lamL[l]);
       if (!valid) F = rinf<R>();
     }
     R Bv = (valid && sigma == b) ? R(0) : rinf<R>();
@@ -459,22 +486,22 @@ __device__ void short_rows_soft(const SweepArgs& A, const R* __restrict__ rin, R
       if (lane + a < 0 || lane + a >= W || !valid) sh = rinf<R>();
       R x1 = (Fl == rinf<R>() || sh == rinf<R>()) ? rinf<R>() : Fl + lamL[l] + sh;
       R x0 = (Fl == rinf<R>() || Bv == rinf<R>()) ? rinf<R>() : Fl + Bv;
-      x1 = seg_softmin<W, R>(x1, T);
-      x0 = seg_softmin<W, R>(x0, T);
+      x1 = seg_softmin<W, R>(x1);
+      x0 = seg_softmin<W, R>(x0);
       if (lane == l) {
-        myM = x1 - x0;
+        myM = (x1 - x0) * unit;
         my1 = x1;
       }
-      Bv = smin2<R, true>(Bv, sh + lamL[l], T);
+      Bv = smin2u<R>(Bv, sh + lamL[l]);
       if (!valid) Bv = rinf<R>();
     }
     // soft row value B_0(0) sits on lane N
     const R rowv = __shfl(Bv, N, W);
     if (lane < n) {
       if (MODE == MODE_UPDATE) write_out<R>(out, w, mylam - omega * myM);
-      if (MODE == MODE_EVAL) write_out<R>(out, w, r_exp<R>(-(my1 - rowv) / T));
+      if (MODE == MODE_EVAL) write_out<R>(out, w, SoftUnits<R>::E(rowv - my1));
     }
-    if (lane == 0) rowpart = double(rowv);
+    if (lane == 0) rowpart = double(rowv * unit);
   }
   double part = block_sum(rowpart, red);
   store_partial(part, A.partial, item);
