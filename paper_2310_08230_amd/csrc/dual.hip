@@ -81,6 +81,7 @@ template <typename R>
 struct SoftUnits;
 template <>
 struct SoftUnits<float> {
+  static constexpr float big = 3.40282347e+38f;   // largest finite value
   static __device__ float unit(float T) { return T * 0.693147180559945309f; }   // x = u * unit
   static __device__ float E(float x) { return __builtin_amdgcn_exp2f(x); }
   static __device__ float L(float x) { return __builtin_amdgcn_logf(x); }
@@ -88,19 +89,21 @@ struct SoftUnits<float> {
 };
 template <>
 struct SoftUnits<double> {
+  static constexpr double big = 1.7976931348623157e+308;
   static __device__ double unit(double T) { return T; }
   static __device__ double E(double x) { return exp(x); }
   static __device__ double L(double x) { return log(x); }
   static __device__ double L1p(double x) { return log1p(x); }
 };
 
-// soft-min of two values in scaled units
+// soft-min of two values in scaled units, without branches: with the smaller
+// value clamped to the largest finite one, an infinite larger value gives
+// E(-inf) = 0 and the result is the smaller value (inf when both are inf)
 template <typename R>
 __device__ inline R smin2u(R a, R b) {
-  if (a == rinf<R>()) return b;
-  if (b == rinf<R>()) return a;
-  const R m = a < b ? a : b, d = a < b ? b - a : a - b;
-  return m - SoftUnits<R>::L1p(SoftUnits<R>::E(-d));
+  const R m = a < b ? a : b, M = a < b ? b : a;
+  const R mc = m < SoftUnits<R>::big ? m : SoftUnits<R>::big;
+  return m - SoftUnits<R>::L1p(SoftUnits<R>::E(mc - M));
 }
 
 // One DPP lane move (a VALU operation): ctrl 0xB1 swaps neighbours (quad
@@ -148,14 +151,15 @@ __device__ inline R seg_sum(R v) {
 }
 
 // soft-min over the W lanes of a segment in scaled units, every lane gets the
-// result: the hard minimum, one exponential per lane, a sum, one logarithm
-// (inf when every lane holds inf)
+// result: the hard minimum, one exponential per lane, a sum, one logarithm.
+// With the minimum clamped to the largest finite value, lanes holding inf
+// add E(-inf) = 0, and a segment of infs gives L(0) = -inf, so inf.
 template <int W, typename R>
 __device__ inline R seg_softmin(R x) {
   const R m = seg_min<W, R>(x);
-  if (m == rinf<R>()) return m;
-  const R e = seg_sum<W, R>(x == rinf<R>() ? R(0) : SoftUnits<R>::E(m - x));
-  return m - SoftUnits<R>::L(e);
+  const R mc = m < SoftUnits<R>::big ? m : SoftUnits<R>::big;
+  const R e = seg_sum<W, R>(SoftUnits<R>::E(mc - x));
+  return mc - SoftUnits<R>::L(e);
 }
 
 // multiplier of entry word w from the previous record buffer, with dual
@@ -484,8 +488,9 @@ __device__ void short_rows_soft(const SweepArgs& A, const R* __restrict__ rin, R
       const R Fl = Ftab[l * W + lane];
       R sh = a > 0 ? dpp_move<0x130>(Bv) : dpp_move<0x138>(Bv);  // Bv[lane + a]
       if (lane + a < 0 || lane + a >= W || !valid) sh = rinf<R>();
-      R x1 = (Fl == rinf<R>() || sh == rinf<R>()) ? rinf<R>() : Fl + lamL[l] + sh;
-      R x0 = (Fl == rinf<R>() || Bv == rinf<R>()) ? rinf<R>() : Fl + Bv;
+      // inf + finite and inf + inf stay inf
+      R x1 = Fl + lamL[l] + sh;
+      R x0 = Fl + Bv;
       x1 = seg_softmin<W, R>(x1);
       x0 = seg_softmin<W, R>(x0);
       if (lane == l) {

@@ -35,13 +35,17 @@ __global__ void k_gcost(const int8_t* state, const int32_t* var_red, const uint8
   g[p] = float(scale * v);
 }
 
+// one wave per candidate pair: lane-strided partial sums over the pair's
+// corner list, then an xor butterfly (a fixed order)
 __global__ void k_gw(const int32_t* corner_ptr, const int32_t* corner_list, int64_t nC, const float* gcost,
                      float* gw) {
-  int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (i >= nC) return;
+  const int64_t i = int64_t(blockIdx.x) * (blockDim.x >> 6) + (threadIdx.x >> 6);
+  if (i >= nC) return;   // uniform across the wave
+  const int lane = threadIdx.x & 63;
   double a = 0.0;
-  for (int32_t k = corner_ptr[i]; k < corner_ptr[i + 1]; ++k) a += double(gcost[corner_list[k] / 3]);
-  gw[i] = float(a);
+  for (int32_t k = corner_ptr[i] + lane; k < corner_ptr[i + 1]; k += 64) a += double(gcost[corner_list[k] / 3]);
+  for (int off = 32; off > 0; off >>= 1) a += __shfl_xor(a, off);
+  if (lane == 0) gw[i] = float(a);
 }
 
 // one thread per (X vertex, descriptor dimension)
@@ -101,7 +105,8 @@ static dm_status backward_impl(dm_ctx* ctx, const R* lam, R T, double scale, con
   k_gcost<R><<<grid_for(ctx->nP, 256), 256, 0, st>>>(ctx->state.p, ctx->var_red.p, ctx->var_deg.p,
                                                      reinterpret_cast<const R*>(ctx->mrec.p), ctx->nP, scale,
                                                      ctx->gcost_tmp.p);
-  k_gw<<<grid_for(ctx->nC, 256), 256, 0, st>>>(ctx->corner_ptr.p, ctx->corner_list.p, ctx->nC, ctx->gcost_tmp.p,
+  if (ctx->nC > 0)
+    k_gw<<<grid_for(ctx->nC, 4), 256, 0, st>>>(ctx->corner_ptr.p, ctx->corner_list.p, ctx->nC, ctx->gcost_tmp.p,
                                                ctx->gw.p);
   const int32_t nvx = ctx->X.nv, nvy = ctx->Y.nv;
   k_gfx<<<grid_for(int64_t(nvx) * D, 256), 256, 0, st>>>(ctx->cand_xstart.p, ctx->cpair.p, nvx, nvy, ctx->gw.p,
