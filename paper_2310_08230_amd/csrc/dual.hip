@@ -126,17 +126,22 @@ __device__ inline R dpp_move(R v) {
 // min / sum over the W lanes (W = 8, 16 or 32) of an aligned segment, the same
 // value in every lane: DPP steps within each sixteen-lane row (every pairing
 // is symmetric, so all lanes form the same sums), one shuffle joins two rows
-// min of two values that are never NaN
-__device__ inline float vmin(float a, float b) { return fminf(a, b); }
-__device__ inline double vmin(double a, double b) { return fmin(a, b); }
+// min of v and its DPP-moved copy (values are never NaN); adding +0 to the
+// moved value (-0 becomes +0, nothing else changes) gives an arithmetic
+// result, which needs no NaN canonicalisation before the min, and the move
+// folds into that add
+template <int CTRL, typename R>
+__device__ inline R min_dpp(R v) {
+  return fmin(v, dpp_move<CTRL, R>(v) + R(0));
+}
 
 template <int W, typename R>
 __device__ inline R seg_min(R v) {
-  v = vmin(v, dpp_move<0xB1>(v));
-  v = vmin(v, dpp_move<0x4E>(v));
-  v = vmin(v, dpp_move<0x141>(v));
-  if constexpr (W >= 16) v = vmin(v, dpp_move<0x140>(v));
-  if constexpr (W == 32) v = vmin(v, __shfl_xor(v, 16, 32));
+  v = min_dpp<0xB1>(v);
+  v = min_dpp<0x4E>(v);
+  v = min_dpp<0x141>(v);
+  if constexpr (W >= 16) v = min_dpp<0x140>(v);
+  if constexpr (W == 32) v = fmin(v, __shfl_xor(v, 16, 32) + R(0));
   return v;
 }
 
@@ -476,8 +481,9 @@ __device__ void short_rows_soft(const SweepArgs& A, const R* __restrict__ rin, R
     for (int32_t l = 0; l < n; ++l) {
       Ftab[l * W + lane] = F;   // read back below by the same lane only
       const int a = aL[l];
-      R sh = a > 0 ? dpp_move<0x138>(F) : dpp_move<0x130>(F);   // F[lane - a]
-      if (lane - a < 0 || lane - a >= W || !valid) sh = rinf<R>();
+      const R from_lo = dpp_move<0x138>(F), from_hi = dpp_move<0x130>(F);   // F[lane - 1], F[lane + 1]
+      R sh = a > 0 ? from_lo : from_hi;                                       // F[lane - a]
+      if ((unsigned(lane - a) >= unsigned(W)) | !valid) sh = rinf<R>();
       F = smin2u<R>(F, sh + lamL[l]);
       if (!valid) F = rinf<R>();
     }
@@ -486,8 +492,9 @@ __device__ void short_rows_soft(const SweepArgs& A, const R* __restrict__ rin, R
     for (int32_t l = n - 1; l >= 0; --l) {
       const int a = aL[l];
       const R Fl = Ftab[l * W + lane];
-      R sh = a > 0 ? dpp_move<0x130>(Bv) : dpp_move<0x138>(Bv);  // Bv[lane + a]
-      if (lane + a < 0 || lane + a >= W || !valid) sh = rinf<R>();
+      const R from_lo = dpp_move<0x138>(Bv), from_hi = dpp_move<0x130>(Bv);
+      R sh = a > 0 ? from_hi : from_lo;                                       // Bv[lane + a]
+      if ((unsigned(lane + a) >= unsigned(W)) | !valid) sh = rinf<R>();
       // inf + finite and inf + inf stay inf
       R x1 = Fl + lamL[l] + sh;
       R x0 = Fl + Bv;
