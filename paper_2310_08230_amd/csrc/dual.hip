@@ -435,24 +435,37 @@ __device__ void short_wave_hard(const SweepArgs& A, const R* __restrict__ rin, R
 
 // ---------------------------------------------------------------- short rows, soft min
 // One W-lane segment per row (W = 8, 16, 32 for rows of at most 7, 15, 24
-// entries; the rows are taken in order of length from soft_row); lane j holds
+// entries; the rows are taken in order of length from soft_row; a block holds
+// soft_rpb<W>() rows, so the forward table fits SOFT_FTAB values); lane j holds
 // the partial sum sigma = j - N of the recursion
 // F_{l+1}(sigma) = smin(F_l(sigma), F_l(sigma - a_l) + lam_l),
 // B_l(sigma) = smin(B_{l+1}(sigma), B_{l+1}(sigma + a_l) + lam_l).
 // Rows [row0, row1) of soft_row belong to this width; blk counts the blocks of
 // this width, item is the block's index among all blocks.
+template <int W>
+constexpr int soft_rpb() {   // rows per 256-thread block
+  return W == 32 ? 4 : 256 / W;
+}
+template <int W>
+constexpr int soft_nmax() {  // entries per row at most
+  return W == 32 ? SOFT_MAX_ROW : W - 1;
+}
+// forward-table values per block: the largest of the three widths
+constexpr int SOFT_FTAB = 16 * 15 * 16;
+static_assert(soft_rpb<8>() * soft_nmax<8>() * 8 <= SOFT_FTAB && soft_rpb<32>() * soft_nmax<32>() * 32 <= SOFT_FTAB,
+              "forward table too small");
+
 template <typename R, int MODE, int W>
 __device__ void short_rows_soft(const SweepArgs& A, const R* __restrict__ rin, R* __restrict__ out, R omega,
                                 R T, unsigned char* smem, double* red, int32_t item, int32_t blk, int32_t row0,
                                 int32_t row1) {
-  constexpr int RPB = 256 / W;                            // rows per block
-  constexpr int NMAX = W == 32 ? SOFT_MAX_ROW : W - 1;    // entries per row at most
+  constexpr int RPB = soft_rpb<W>(), NMAX = soft_nmax<W>();
   const int seg = threadIdx.x / W, lane = threadIdx.x % W;
   R* Ftab = reinterpret_cast<R*>(smem) + seg * (NMAX * W);
-  R* lamL = reinterpret_cast<R*>(smem) + 256 * SOFT_MAX_ROW + seg * W;
-  int8_t* aL = reinterpret_cast<int8_t*>(reinterpret_cast<R*>(smem) + 256 * SOFT_MAX_ROW + 256) + seg * W;
+  R* lamL = reinterpret_cast<R*>(smem) + SOFT_FTAB + seg * W;
+  int8_t* aL = reinterpret_cast<int8_t*>(reinterpret_cast<R*>(smem) + SOFT_FTAB + 256) + seg * W;
   const int32_t r = row0 + blk * RPB + seg;
-  const bool act = r < row1;
+  const bool act = seg < RPB && r < row1;
   int32_t s = 0, n = 0, b = 0;
   uint32_t w = 0;
   R mylam = R(0);
@@ -684,7 +697,7 @@ __device__ void long_rows(const SweepArgs& A, const R* __restrict__ rin, R* __re
 
 template <typename R, bool SOFT>
 constexpr size_t smem_bytes() {
-  return SOFT ? (256 * SOFT_MAX_ROW + 256) * sizeof(R) + 256 : 16;
+  return SOFT ? (SOFT_FTAB + 256) * sizeof(R) + 256 : 16;
 }
 
 template <typename R, bool SOFT, int MODE>
@@ -717,7 +730,8 @@ __global__ __launch_bounds__(256) void k_sweep(SweepArgs A, const R* __restrict_
   }
   if (item < A.n_short_blocks) {
     if (SOFT) {
-      const int32_t nb8 = (A.soft_c8 + 31) / 32, nb16 = (A.soft_c16 + 15) / 16;
+      const int32_t nb8 = (A.soft_c8 + soft_rpb<8>() - 1) / soft_rpb<8>();
+      const int32_t nb16 = (A.soft_c16 + soft_rpb<16>() - 1) / soft_rpb<16>();
       const int32_t c816 = A.soft_c8 + A.soft_c16;
       if (item < nb8)
         short_rows_soft<R, MODE, 8>(A, rin, out, omega, T, smem, red, item, item, 0, A.soft_c8);
@@ -839,8 +853,10 @@ dm_status dual_sweep(dm_ctx* ctx, int mode, bool soft, const unsigned char* rin,
   A.soft_row = ctx->soft_row.p;
   A.soft_c8 = int32_t(ctx->soft_c8);
   A.soft_c16 = int32_t(ctx->soft_c16);
-  const int64_t soft_blocks =
-      (ctx->soft_c8 + 31) / 32 + (ctx->soft_c16 + 15) / 16 + (ctx->n_short - ctx->soft_c8 - ctx->soft_c16 + 7) / 8;
+  const int64_t c32 = ctx->n_short - ctx->soft_c8 - ctx->soft_c16;
+  const int64_t soft_blocks = (ctx->soft_c8 + soft_rpb<8>() - 1) / soft_rpb<8>() +
+                              (ctx->soft_c16 + soft_rpb<16>() - 1) / soft_rpb<16>() +
+                              (c32 + soft_rpb<32>() - 1) / soft_rpb<32>();
   A.n_short_blocks = soft ? int32_t(soft_blocks) : int32_t((ctx->n_chunks + 3) / 4);
   // projection rows of more than LONG_BLOCK_ROW entries on average get a whole block each
   const int64_t n_long = ctx->n_rows - ctx->n_short;
