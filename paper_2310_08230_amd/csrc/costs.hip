@@ -85,29 +85,6 @@ __global__ void k_elem_cost(const int32_t* pv, const int32_t* cidx, int64_t nP, 
   if (out) out[p] = float(c);
 }
 
-// deterministic single-block sum of the costs of elements fixed to 1
-__global__ __launch_bounds__(1024) void k_fixed1_sum(const double* c, const int8_t* state, int64_t nP,
-                                                     double* out) {
-  __shared__ double red[1024];
-  // eight independent accumulators per thread (fixed order), so the loads of
-  // a thread do not wait on each other
-  double a[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
-  for (int64_t p = threadIdx.x; p < nP; p += 8 * int64_t(blockDim.x)) {
-#pragma unroll
-    for (int u = 0; u < 8; ++u) {
-      const int64_t q = p + int64_t(u) * blockDim.x;
-      if (q < nP && state[q] == 1) a[u] += c[q];
-    }
-  }
-  red[threadIdx.x] = ((((((a[0] + a[1]) + a[2]) + a[3]) + a[4]) + a[5]) + a[6]) + a[7];
-  __syncthreads();
-  for (int w = blockDim.x / 2; w > 0; w >>= 1) {
-    if (int(threadIdx.x) < w) red[threadIdx.x] += red[threadIdx.x + w];
-    __syncthreads();
-  }
-  if (threadIdx.x == 0) *out = red[0];
-}
-
 __global__ void k_corner_keys(const int32_t* pv, const int32_t* cidx, int64_t nP, uint32_t* key,
                               int32_t* val) {
   int64_t s = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
@@ -133,8 +110,7 @@ __global__ void k_corner_ptr(const uint32_t* key, int64_t n, int64_t nC, int32_t
 // constant of the dual objective: the summed costs of the elements fixed to 1
 dm_status cost_offset(dm_ctx* ctx) {
   DM_ALLOC(ctx, ctx->scal, 16);
-  k_fixed1_sum<<<1, 1024, 0, ctx->stream>>>(ctx->cost64.p, ctx->state.p, ctx->nP, ctx->scal.p);
-  DM_LAUNCH_CHECK(ctx);
+  DM_TRY(sum_f64(ctx, ctx->cost64.p, ctx->nP, ctx->state.p, SUM_I8_ONE, ctx->scal.p));   // elements fixed to 1
   DM_HIP(ctx, hipMemcpyAsync(&ctx->offset, ctx->scal.p, sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
   DM_HIP(ctx, hipStreamSynchronize(ctx->stream));
   return DM_OK;

@@ -96,6 +96,50 @@ dm_status sort_pairs_u32(dm_ctx* ctx, uint32_t* keys, int32_t* vals, size_t n, i
   return sort_pairs_impl<uint32_t>(ctx, keys, vals, n, end_bit);
 }
 
+// ---------------------------------------------------------------------------
+// deterministic FP64 sums
+// ---------------------------------------------------------------------------
+constexpr int SUM_MAX_BLOCKS = 1024;
+
+__global__ __launch_bounds__(256) void k_sum_ranges(const double* a, int64_t n, const void* sel, int kind,
+                                                    int64_t per_block, double* partial) {
+  __shared__ double red[4];
+  const int64_t lo = int64_t(blockIdx.x) * per_block;
+  const int64_t hi = lo + per_block < n ? lo + per_block : n;
+  // eight independent accumulators per thread (fixed order)
+  double acc[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+  for (int64_t i = lo + threadIdx.x; i < hi; i += 256 * 8) {
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int64_t q = i + 256 * u;
+      if (q >= hi) continue;
+      const bool take = kind == SUM_ALL ? true
+                        : kind == SUM_I8_ONE ? static_cast<const int8_t*>(sel)[q] == 1
+                                             : static_cast<const uint8_t*>(sel)[q] != 0;
+      if (take) acc[u] += a[q];
+    }
+  }
+  const double v = ((((((acc[0] + acc[1]) + acc[2]) + acc[3]) + acc[4]) + acc[5]) + acc[6]) + acc[7];
+  const double part = block_sum_256(v, red);
+  if (threadIdx.x == 0) partial[blockIdx.x] = part;
+}
+
+__global__ __launch_bounds__(1024) void k_sum_partials(const double* partial, int n, double* out) {
+  __shared__ double red[16];
+  const double r = sum_partials_1024(partial, n, red);
+  if (threadIdx.x == 0) *out = r;
+}
+
+dm_status sum_f64(dm_ctx* ctx, const double* a, int64_t n, const void* sel, int kind, double* out) {
+  const int64_t nb = std::max<int64_t>(1, std::min<int64_t>(SUM_MAX_BLOCKS, (n + 4095) / 4096));
+  const int64_t per_block = (n + nb - 1) / nb;
+  DM_ALLOC(ctx, ctx->sum_part, size_t(SUM_MAX_BLOCKS));
+  k_sum_ranges<<<unsigned(nb), 256, 0, ctx->stream>>>(a, n, sel, kind, per_block, ctx->sum_part.p);
+  k_sum_partials<<<1, 1024, 0, ctx->stream>>>(ctx->sum_part.p, int(nb), out);
+  DM_LAUNCH_CHECK(ctx);
+  return DM_OK;
+}
+
 __global__ void k_scan_tail(const int32_t* in_last, int32_t* out, size_t n, int is_u8,
                             const uint8_t* u8_last) {
   int32_t last = is_u8 ? int32_t(*u8_last) : *in_last;

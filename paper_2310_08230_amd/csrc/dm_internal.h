@@ -240,6 +240,7 @@ struct dm_ctx {
   double pend_offset = 0.0;
   double* pend_out = nullptr;    // bound of the last launch not yet summed
   DArr<double> scal;             // small device scalars
+  DArr<double> sum_part;         // per-block partials of sum_f64
   DArr<int8_t> pref;             // per variable: 1, 0 or -1
   DArr<int64_t> icount;          // integer counters
   DArr<float> gw;                // gradient per pair
@@ -273,6 +274,12 @@ dm_status sort_pairs_u64(dm_ctx* ctx, uint64_t* keys, int32_t* vals, size_t n, i
 dm_status sort_pairs_u32(dm_ctx* ctx, uint32_t* keys, int32_t* vals, size_t n, int end_bit);
 dm_status scan_i32(dm_ctx* ctx, const int32_t* in, int32_t* out, size_t n);  // exclusive, out[n] = total
 dm_status scan_u8(dm_ctx* ctx, const uint8_t* in, int32_t* out, size_t n);   // exclusive, out[n] = total
+// Deterministic FP64 sum of a[0..n) into *out (device), in an order fixed by
+// n: blocks sum contiguous ranges, one block sums their partials.  sel
+// (optional) picks the terms: SUM_I8_ONE takes a[i] where ((int8*)sel)[i] == 1,
+// SUM_U8_NZ where ((uint8*)sel)[i] != 0.
+enum SumSel { SUM_ALL = 0, SUM_I8_ONE = 1, SUM_U8_NZ = 2 };
+dm_status sum_f64(dm_ctx* ctx, const double* a, int64_t n, const void* sel, int kind, double* out);
 dm_status read_i32(dm_ctx* ctx, const int32_t* dev, int32_t* host);
 dm_status check_finite(dm_ctx* ctx, const float* a, int64_t n);
 dm_status dual_flush(dm_ctx* ctx);  // write the bound of the last sweep launch

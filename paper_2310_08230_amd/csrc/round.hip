@@ -52,25 +52,6 @@ __global__ void k_agree(const R* mrec, const uint8_t* deg, int64_t nfree, int8_t
 
 // one-block sums in a fixed order; eight independent accumulators per thread
 // keep its loads from waiting on each other
-__global__ __launch_bounds__(1024) void k_sum_f64(const double* a, int64_t n, double* out) {
-  __shared__ double red[1024];
-  double acc[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
-  for (int64_t i = threadIdx.x; i < n; i += 8 * int64_t(blockDim.x)) {
-#pragma unroll
-    for (int u = 0; u < 8; ++u) {
-      const int64_t q = i + int64_t(u) * blockDim.x;
-      if (q < n) acc[u] += a[q];
-    }
-  }
-  red[threadIdx.x] = ((((((acc[0] + acc[1]) + acc[2]) + acc[3]) + acc[4]) + acc[5]) + acc[6]) + acc[7];
-  __syncthreads();
-  for (int w = blockDim.x / 2; w > 0; w >>= 1) {
-    if (int(threadIdx.x) < w) red[threadIdx.x] += red[threadIdx.x + w];
-    __syncthreads();
-  }
-  if (threadIdx.x == 0) *out = red[0];
-}
-
 __global__ void k_make_x(const int8_t* state, const int32_t* var_red, const int8_t* pref, int64_t nP, uint8_t* x) {
   int64_t p = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (p >= nP) return;
@@ -100,25 +81,6 @@ __global__ __launch_bounds__(256) void k_violations_proj(const int32_t* row_ptr,
   __syncthreads();
   if (threadIdx.x == 0 && sh[0] + sh[1] + sh[2] + sh[3] != 1)
     atomicAdd(reinterpret_cast<unsigned long long*>(count), 1ull);
-}
-
-__global__ __launch_bounds__(1024) void k_primal_obj(const double* c, const uint8_t* x, int64_t nP, double* out) {
-  __shared__ double red[1024];
-  double acc[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
-  for (int64_t p = threadIdx.x; p < nP; p += 8 * int64_t(blockDim.x)) {
-#pragma unroll
-    for (int u = 0; u < 8; ++u) {
-      const int64_t q = p + int64_t(u) * blockDim.x;
-      if (q < nP && x[q]) acc[u] += c[q];
-    }
-  }
-  red[threadIdx.x] = ((((((acc[0] + acc[1]) + acc[2]) + acc[3]) + acc[4]) + acc[5]) + acc[6]) + acc[7];
-  __syncthreads();
-  for (int w = blockDim.x / 2; w > 0; w >>= 1) {
-    if (int(threadIdx.x) < w) red[threadIdx.x] += red[threadIdx.x + w];
-    __syncthreads();
-  }
-  if (threadIdx.x == 0) *out = red[0];
 }
 
 // c~_i += Delta_i in both record buffers; the next projection spreads
@@ -179,8 +141,7 @@ static dm_status round_impl(dm_ctx* ctx, const dm_round_params& P, const R* lam,
     DM_HIP(ctx, hipMemcpyAsync(&undecided, ctx->icount.p, sizeof(int64_t), hipMemcpyDeviceToHost, st));
     DM_HIP(ctx, hipStreamSynchronize(st));
     if (r == 0 && delta <= 0.0) {
-      k_sum_f64<<<1, 1024, 0, st>>>(absm.p, nfree, ctx->scal.p);
-      DM_LAUNCH_CHECK(ctx);
+      DM_TRY(sum_f64(ctx, absm.p, nfree, nullptr, SUM_ALL, ctx->scal.p));
       double s = 0.0;
       DM_HIP(ctx, hipMemcpyAsync(&s, ctx->scal.p, sizeof(double), hipMemcpyDeviceToHost, st));
       DM_HIP(ctx, hipStreamSynchronize(st));
@@ -208,7 +169,7 @@ static dm_status round_impl(dm_ctx* ctx, const dm_round_params& P, const R* lam,
     }
     delta *= P.gamma;
   }
-  k_primal_obj<<<1, 1024, 0, st>>>(ctx->cost64.p, x, ctx->nP, ctx->scal.p + 1);
+  DM_TRY(sum_f64(ctx, ctx->cost64.p, ctx->nP, x, SUM_U8_NZ, ctx->scal.p + 1));
   DM_LAUNCH_CHECK(ctx);
   DM_HIP(ctx, hipMemcpyAsync(pobj, ctx->scal.p + 1, sizeof(double), hipMemcpyDeviceToHost, st));
   DM_HIP(ctx, hipStreamSynchronize(st));
