@@ -107,3 +107,36 @@ def test_smoothed_bound_autograd_config4_shape():
     L.backward()
     assert DX.grad.shape == (len(p.DX), 128) and torch.isfinite(DX.grad).all() and torch.isfinite(DY.grad).all()
     say(f"  L_T={float(L):.6f} |dL/dFX|max={float(DX.grad.abs().max()):.3e}")
+
+
+@pytest.mark.parametrize("prec,tol0,tol_lam,tol_grad", [("fp64", 1e-13, 1e-11, 1e-6), ("fp32", 1e-6, 1e-4, 1e-3)])
+def test_smoothed_all_segment_widths(prec, tol0, tol_lam, tol_grad):
+    """The 500-face pair (K = 16) has closedness rows of 2-7, 8-15 and 16-17
+    entries, so the smoothed sweep runs all three of its segment widths (8,
+    16 and 32 lanes); the smoothed bound, two smoothed updates and the
+    marginal gradient agree with the oracle."""
+    p = make_pair(2, 0)
+    S, ctx = both(p, 16, "fp64" if prec == "fp64" else "fp32")
+    rp = S.get("rrow_ptr")
+    n_short = ctx.info["n_short_rows"]
+    lens = np.diff(rp)[:n_short]
+    widths = ((lens <= 7).sum(), ((lens >= 8) & (lens <= 15)).sum(), (lens >= 16).sum())
+    say(f"  short rows by segment width 8/16/32: {widths}")
+    assert min(widths) > 0
+    T = 0.1
+    lam0 = ctx.init_lambda(prec)
+    r0 = S.lower_bound(S.init_lambda(), T)
+    assert abs(ctx.lower_bound(lam0, T) - r0) <= tol0 * abs(r0)
+    lam, tr = ctx.dual_solve(lam0, 2, 0.5, T)
+    rlam, rtr = S.dual_solve(2, T=T)
+    e_lam = float(np.abs(np_(lam).astype(np.float64) - rlam).max() / np.abs(rlam).max())
+    say(f"  {prec}: bound rel err {rel_err(np_(tr), rtr):.2e}, lambda {e_lam:.2e}")
+    assert rel_err(np_(tr), rtr) <= tol0 * 10
+    assert e_lam <= tol_lam
+    gc, gX, gY, val = ctx.smoothed_backward(lam, T, torch.from_numpy(p.DX), torch.from_numpy(p.DY))
+    rv, rgc, rgX, rgY = S.smoothed_grad(np_(lam).astype(np.float64), T, p.DX, p.DY)
+    ex = float(np.abs(np_(gX) - rgX).max() / np.abs(rgX).max())
+    ec = float(np.abs(np_(gc) - rgc).max())
+    say(f"  {prec}: grad dFX {ex:.2e} dc {ec:.2e} value {val:.10f} vs {rv:.10f}")
+    assert ex <= tol_grad and ec <= tol_grad
+    assert abs(val - rv) <= tol0 * 10 * abs(rv)
