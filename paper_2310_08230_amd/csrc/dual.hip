@@ -264,10 +264,19 @@ __device__ inline R row_lambda(const SweepArgs& A, const R* __restrict__ rin, ui
 //  4. a segmented inclusive scan gives S(k), the sum of the k smallest of a
 //     group, at the lane of the k-th smallest;
 //  5. each lane evaluates its two constrained minima over k.
-__device__ inline int wave_max_i(int v) {
-  for (int o = 32; o > 0; o >>= 1) v = max(v, __shfl_xor(v, o));
-  return v;
-}
+// 16-byte LDS read of four FP32 or two FP64 values
+template <typename R>
+struct LdsVec;
+template <>
+struct LdsVec<float> {
+  using type = float4;
+  static __device__ float get(const float4& v, int u) { return u == 0 ? v.x : u == 1 ? v.y : u == 2 ? v.z : v.w; }
+};
+template <>
+struct LdsVec<double> {
+  using type = double2;
+  static __device__ double get(const double2& v, int u) { return u == 0 ? v.x : v.y; }
+};
 
 template <typename R>
 __device__ inline R permute_to(int dst_lane, R v) {   // push v to lane dst_lane
@@ -283,7 +292,7 @@ __device__ inline R permute_to(int dst_lane, R v) {   // push v to lane dst_lane
 
 template <typename R, int MODE>
 __device__ inline double short_chunk_hard(const SweepArgs& A, const R* __restrict__ rin, R* __restrict__ out,
-                                          R omega, R gam, int32_t wc) {
+                                          R omega, R gam, int32_t wc, R* wave_vals) {
   const int lane = threadIdx.x & 63;
   double rowpart = 0.0;
   if (wc < A.n_chunks) {   // uniform across the wave
@@ -307,22 +316,28 @@ __device__ inline double short_chunk_hard(const SweepArgs& A, const R* __restric
     const unsigned long long rowm = act ? (((n >= 64) ? ~0ull : ((1ull << n) - 1ull)) << s) : 0ull;
     const int32_t P = __popcll(rowm & ~negm);
     const int32_t N = n - P;
-    // rank of this entry in its sign group (ties broken by lane)
-    const int nmax = wave_max_i(act ? n : 0);
-    // (four independent shuffles per step, so their latencies overlap)
+    // rank of this entry in its sign group (ties broken by lane): the wave's
+    // values go to its own 64-entry LDS slice, and each lane reads its row in
+    // aligned 16-byte pieces (lanes of one row read the same addresses: a
+    // broadcast); only this wave touches the slice, so a wave-level fence
+    // orders the writes before the reads
+    wave_vals[lane] = lam;
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    constexpr int V = 16 / int(sizeof(R));   // values per 16-byte read
+    using Vec = typename LdsVec<R>::type;
     int32_t rank = 0;
-    for (int q = 0; q < nmax; q += 4) {
-      R lq[4];
+    if (act) {
+      for (int a = s & ~(V - 1); a < s + n; a += V) {   // a + V <= 64: the slice's end
+        const Vec v = *reinterpret_cast<const Vec*>(wave_vals + a);
 #pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        const int src = s + q + u;
-        lq[u] = __shfl(lam, src < 64 ? src : 63);
-      }
-#pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        const int src = s + q + u;
-        const int gq = int((negm >> (src & 63)) & 1ull);
-        if (act && q + u < n && gq == g) rank += (lq[u] < lam) || (lq[u] == lam && src < lane);
+        for (int u = 0; u < V; ++u) {
+          const int src = a + u;
+          const R lq = LdsVec<R>::get(v, u);
+          const int gq = int((negm >> src) & 1ull);
+          if (src >= s && src < s + n && gq == g) rank += (lq < lam) || (lq == lam && src < lane);
+        }
       }
     }
     // sorted position: positive group first, then negative group
@@ -426,9 +441,10 @@ __device__ inline double short_chunk_hard(const SweepArgs& A, const R* __restric
 // keeps the most waves in flight; batching chunks per wave measured slower)
 template <typename R, int MODE>
 __device__ void short_wave_hard(const SweepArgs& A, const R* __restrict__ rin, R* __restrict__ out, R omega,
-                                R gam, double* red, int32_t item) {
+                                R gam, unsigned char* smem, double* red, int32_t item) {
   const int wave = threadIdx.x >> 6;
-  const double rowpart = short_chunk_hard<R, MODE>(A, rin, out, omega, gam, item * 4 + wave);
+  R* wave_vals = reinterpret_cast<R*>(smem) + wave * 64;
+  const double rowpart = short_chunk_hard<R, MODE>(A, rin, out, omega, gam, item * 4 + wave, wave_vals);
   double part = block_sum(rowpart, red);
   store_partial(part, A.partial, item);
 }
@@ -697,7 +713,7 @@ __device__ void long_rows(const SweepArgs& A, const R* __restrict__ rin, R* __re
 
 template <typename R, bool SOFT>
 constexpr size_t smem_bytes() {
-  return SOFT ? (SOFT_FTAB + 256) * sizeof(R) + 256 : 16;
+  return SOFT ? (SOFT_FTAB + 256) * sizeof(R) + 256 : 256 * sizeof(R);
 }
 
 template <typename R, bool SOFT, int MODE>
@@ -741,7 +757,7 @@ __global__ __launch_bounds__(256) void k_sweep(SweepArgs A, const R* __restrict_
         short_rows_soft<R, MODE, 32>(A, rin, out, omega, T, smem, red, item, item - nb8 - nb16, c816,
                                      A.n_short);
     }
-    else short_wave_hard<R, MODE>(A, rin, out, omega, gam, red, item);
+    else short_wave_hard<R, MODE>(A, rin, out, omega, gam, smem, red, item);
   } else {
     long_rows<R, SOFT, MODE>(A, rin, out, omega, T, gam, red, item);
   }
