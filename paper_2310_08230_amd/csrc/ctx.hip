@@ -84,8 +84,7 @@ static dm_status sort_pairs_impl(dm_ctx* ctx, K* keys, int32_t* vals, size_t n, 
                                         unsigned(end_bit), ctx->stream));
   DM_HIP(ctx, hipMemcpyAsync(keys, k2.p, n * sizeof(K), hipMemcpyDeviceToDevice, ctx->stream));
   DM_HIP(ctx, hipMemcpyAsync(vals, v2.p, n * sizeof(int32_t), hipMemcpyDeviceToDevice, ctx->stream));
-  DM_HIP(ctx, hipStreamSynchronize(ctx->stream));
-  return DM_OK;
+  return DM_OK;   // temporaries are freed in stream order: no wait needed
 }
 
 dm_status sort_pairs_u64(dm_ctx* ctx, uint64_t* keys, int32_t* vals, size_t n, int end_bit) {
@@ -164,7 +163,6 @@ dm_status scan_i32(dm_ctx* ctx, const int32_t* in, int32_t* out, size_t n) {
                                       rocprim::plus<int32_t>(), ctx->stream));
   k_scan_tail<<<1, 1, 0, ctx->stream>>>(in + n - 1, out, n, 0, nullptr);
   DM_LAUNCH_CHECK(ctx);
-  DM_HIP(ctx, hipStreamSynchronize(ctx->stream));
   return DM_OK;
 }
 
@@ -183,7 +181,6 @@ dm_status scan_u8(dm_ctx* ctx, const uint8_t* in, int32_t* out, size_t n) {
                                       rocprim::plus<int32_t>(), ctx->stream));
   k_scan_tail<<<1, 1, 0, ctx->stream>>>(nullptr, out, n, 1, in + n - 1);
   DM_LAUNCH_CHECK(ctx);
-  DM_HIP(ctx, hipStreamSynchronize(ctx->stream));
   return DM_OK;
 }
 

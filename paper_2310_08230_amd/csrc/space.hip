@@ -229,15 +229,26 @@ __global__ void k_xproj(const int32_t* off, Geo g, int64_t base, int64_t nc, int
   }
 }
 
-__global__ void k_ykeys(const int32_t* code, int64_t nP, int32_t nfy, uint32_t* key, int32_t* val,
-                        int32_t* ycount) {
+__global__ void k_ykeys(const int32_t* code, int64_t nP, int32_t nfy, uint32_t* key, int32_t* val) {
   int64_t p = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (p >= nP) return;
   bool yface = (code[4 * p + 2] >> 3) == 0;
   int32_t g = code[4 * p + 3];
   key[p] = yface ? uint32_t(g) : uint32_t(nfy);
   val[p] = int32_t(p);
-  if (yface) atomicAdd(&ycount[g], 1);
+}
+
+// yptr[g] = first position of key >= g in the sorted keys, g = 0..nfy
+__global__ void k_key_starts(const uint32_t* key, int64_t n, int32_t nfy, int32_t* yptr) {
+  const int32_t g = int32_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (g > nfy) return;
+  int64_t lo = 0, hi = n;
+  while (lo < hi) {
+    const int64_t mid = (lo + hi) >> 1;
+    if (key[mid] < uint32_t(g)) lo = mid + 1;
+    else hi = mid;
+  }
+  yptr[g] = int32_t(lo);
 }
 
 __global__ void k_yproj(const int32_t* yptr, const int32_t* val, const int32_t* code, Geo g,
@@ -260,9 +271,22 @@ __global__ void k_yproj(const int32_t* yptr, const int32_t* val, const int32_t* 
 __global__ void k_set_i32(int32_t* a, int64_t i, int32_t v) { a[i] = v; }
 
 // ---------------------------------------------------------------- presolve
+// one atomic OR per wave: the lowest lane with the condition set does it
+__device__ inline void wave_flag(bool cond, int* flag) {
+  const unsigned long long m = __ballot(cond);
+  if (m && int(threadIdx.x & 63) == __ffsll(static_cast<long long>(m)) - 1) atomicOr(flag, 1);
+}
+
+// A presolve round does nothing once the round before it changed nothing or
+// found the system infeasible (prev: that round's flags, or NULL).
+__device__ inline bool presolve_done(const int* prev) {
+  return prev && (prev[0] == 0 || prev[1] != 0);
+}
+
 __global__ void k_presolve_rows(const int32_t* row_ptr, const int32_t* ent_var, const int8_t* ent_coef,
                                 const int32_t* row_b, int64_t nrows, const int8_t* state,
-                                uint32_t* force, int* flags) {
+                                uint32_t* force, int* flags, const int* prev) {
+  if (presolve_done(prev)) return;   // uniform across the grid
   int64_t j = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (j >= nrows) return;
   int32_t s = row_ptr[j], e = row_ptr[j + 1];
@@ -293,20 +317,23 @@ __global__ void k_presolve_rows(const int32_t* row_ptr, const int32_t* ent_var, 
   }
 }
 
-__global__ void k_presolve_vars(int64_t nP, int8_t* state, uint32_t* force, int* flags) {
+__global__ void k_presolve_vars(int64_t nP, int8_t* state, uint32_t* force, int* flags, const int* prev) {
+  if (presolve_done(prev)) return;   // uniform across the grid
   int64_t p = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (p >= nP) return;
-  uint32_t f = force[p];
-  if (!f) return;
-  force[p] = 0;
-  if (f == 3u) {
-    atomicOr(&flags[1], 1);
-    return;
+  const uint32_t f = force[p];
+  bool changed = false, clash = false;
+  if (f) {
+    force[p] = 0;
+    if (f == 3u) {
+      clash = true;
+    } else if (state[p] < 0) {
+      state[p] = (f == 2u) ? 1 : 0;
+      changed = true;
+    }
   }
-  if (state[p] < 0) {
-    state[p] = (f == 2u) ? 1 : 0;
-    atomicOr(&flags[0], 1);
-  }
+  wave_flag(changed, &flags[0]);
+  wave_flag(clash, &flags[1]);
 }
 
 __global__ void k_fix_state(const int8_t* fix, int64_t nP, int8_t* state) {
@@ -403,8 +430,10 @@ __device__ inline int block_excl_flag(bool f, int* sh, int* total) {
 }
 
 __global__ __launch_bounds__(256) void k_presolve_proj(const int32_t* row_ptr, const int32_t* ent_var, int64_t nc,
-                                                       const int8_t* state, uint32_t* force, int* flags) {
+                                                       const int8_t* state, uint32_t* force, int* flags,
+                                                       const int* prev) {
   __shared__ int sh[4];
+  if (presolve_done(prev)) return;   // uniform across the grid
   const int64_t j = nc + blockIdx.x;
   const int32_t s = row_ptr[j], e = row_ptr[j + 1];
   int c1 = 0, cf = 0;
@@ -489,18 +518,29 @@ __global__ void k_var_deg(const int32_t* free_var, const int32_t* code, int64_t 
   deg[i] = uint8_t(3 + (code[4 * p] == 0 ? 1 : 0) + ((code[4 * p + 2] >> 3) == 0 ? 1 : 0));
 }
 
+// flags[2]: longest short row; flags[3] bit 1: a row with < 2 entries, bit 0:
+// a projection row that is not exactly-one (one atomic per wave each)
 __global__ void k_row_stats(const int32_t* rrow_ptr, const int32_t* rrow_b, const int8_t* rent_coef,
                             int64_t n_short, int64_t n_rows, int* flags) {
-  int64_t j = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (j >= n_rows) return;
-  int32_t len = rrow_ptr[j + 1] - rrow_ptr[j];
-  if (len < 2) atomicOr(&flags[3], 2);   // presolve leaves >= 2 free entries per row
-  if (j < n_short) {
-    atomicMax(&flags[2], len);
-  } else {
+  // no early return: every lane of the wave takes part in the reductions
+  const int64_t j = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  const bool in = j < n_rows;
+  const int32_t len = in ? rrow_ptr[j + 1] - rrow_ptr[j] : 2;
+  int32_t short_len = 0;
+  bool bad_proj = false;
+  if (in && j < n_short) {
+    short_len = len;
+  } else if (in) {
     bool ok = rrow_b[j] == 1;
     for (int32_t i = rrow_ptr[j]; i < rrow_ptr[j + 1]; ++i) ok = ok && rent_coef[i] == 1;
-    if (!ok) atomicOr(&flags[3], 1);
+    bad_proj = !ok;
+  }
+  for (int o = 32; o > 0; o >>= 1) short_len = max(short_len, __shfl_xor(short_len, o));
+  if ((threadIdx.x & 63) == 0 && short_len > 0) atomicMax(&flags[2], short_len);
+  const unsigned long long few = __ballot(len < 2), bad = __ballot(bad_proj);
+  if ((threadIdx.x & 63) == 0) {
+    if (few) atomicOr(&flags[3], 2);   // presolve leaves >= 2 free entries per row
+    if (bad) atomicOr(&flags[3], 1);
   }
 }
 
@@ -575,28 +615,35 @@ __global__ void k_chunk_pad(const int4* desc, const unsigned long long* mask, co
   }
 }
 
-__global__ void k_pack(const int32_t* seg_row, const int32_t* rrow_ptr, int32_t n_seg, int32_t* count,
-                       const int32_t* offset, int4* desc, int fill) {
-  int32_t j = int32_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (j >= n_seg) return;
-  int32_t r = seg_row[j], r1 = seg_row[j + 1];
-  int32_t c = 0, o = fill ? offset[j] : 0;
-  while (r < r1) {
-    const int32_t r0 = r, e0 = rrow_ptr[r];
-    // extend the chunk while the next row still fits, reading eight row
-    // pointers per step (independent loads) instead of one
+// One block per segment: the segment's row pointers are staged in LDS (a
+// segment starts at most PACK_SEG / 2 rows, since every presolved row has at
+// least two entries, which the caller checks first), then one thread walks
+// them.
+__global__ __launch_bounds__(256) void k_pack(const int32_t* seg_row, const int32_t* rrow_ptr, int32_t n_seg,
+                                              int32_t* count, const int32_t* offset, int4* desc, int fill) {
+  __shared__ int32_t rp[PACK_SEG / 2 + 1];
+  const int32_t j = blockIdx.x;
+  const int32_t rs = seg_row[j], nr = seg_row[j + 1] - rs;
+  if (nr > PACK_SEG / 2) return;   // excluded by the caller's check
+  for (int32_t i = threadIdx.x; i <= nr; i += blockDim.x) rp[i] = rrow_ptr[rs + i];
+  __syncthreads();
+  if (threadIdx.x != 0) return;
+  int32_t r = 0, c = 0, o = fill ? offset[j] : 0;
+  while (r < nr) {
+    const int32_t q0 = r, e0 = rp[r];
+    // extend the chunk while the next row still fits, eight row pointers per step
     for (;;) {
       int32_t v[8];
 #pragma unroll
-      for (int u = 0; u < 8; ++u) v[u] = r + 1 + u <= r1 ? rrow_ptr[r + 1 + u] : INT32_MAX;
+      for (int u = 0; u < 8; ++u) v[u] = r + 1 + u <= nr ? rp[r + 1 + u] : INT32_MAX;
       int adv = 0;
 #pragma unroll
       for (int u = 0; u < 8; ++u)
-        if (adv == u && r + u < r1 && v[u] - e0 <= 64) adv = u + 1;
+        if (adv == u && r + u < nr && v[u] - e0 <= 64) adv = u + 1;
       r += adv;
       if (adv < 8) break;
     }
-    if (fill) desc[o + c] = make_int4(r0, r - r0, e0, rrow_ptr[r] - e0);
+    if (fill) desc[o + c] = make_int4(rs + q0, r - q0, e0, rp[r] - e0);
     ++c;
   }
   if (!fill) count[j] = c;
@@ -710,16 +757,15 @@ dm_status space_build(dm_ctx* ctx, const int32_t* cand_xy, const int32_t* cand_y
 
   // ---- Y projection rows: stable sort of Y-face elements by face
   DArr<uint32_t> ykey;
-  DArr<int32_t> yval, ycount, yptr;
+  DArr<int32_t> yval, yptr;
   DM_ALLOC(ctx, ykey, size_t(nP));
   DM_ALLOC(ctx, yval, size_t(nP));
-  DM_ALLOC(ctx, ycount, size_t(Y.nf));
   DM_ALLOC(ctx, yptr, size_t(Y.nf) + 1);
-  DM_HIP(ctx, hipMemsetAsync(ycount.p, 0, sizeof(int32_t) * Y.nf, st));
-  k_ykeys<<<grid_for(nP, 256), 256, 0, st>>>(ctx->code.p, nP, Y.nf, ykey.p, yval.p, ycount.p);
+  k_ykeys<<<grid_for(nP, 256), 256, 0, st>>>(ctx->code.p, nP, Y.nf, ykey.p, yval.p);
   DM_LAUNCH_CHECK(ctx);
   DM_TRY(sort_pairs_u32(ctx, ykey.p, yval.p, size_t(nP), bits_for(uint64_t(Y.nf) + 1)));
-  DM_TRY(scan_i32(ctx, ycount.p, yptr.p, size_t(Y.nf)));
+  k_key_starts<<<grid_for(int64_t(Y.nf) + 1, 256), 256, 0, st>>>(ykey.p, nP, Y.nf, yptr.p);
+  DM_LAUNCH_CHECK(ctx);
   int32_t nYf = 0;
   DM_TRY(read_i32(ctx, yptr.p + Y.nf, &nYf));
 
@@ -776,23 +822,37 @@ dm_status presolve_reduce(dm_ctx* ctx, const int8_t* fix) {
   DArr<uint32_t> force;
   DM_ALLOC(ctx, force, size_t(nP));
   DM_HIP(ctx, hipMemsetAsync(force.p, 0, sizeof(uint32_t) * nP, st));
+  // Rounds run in batches of PRESOLVE_BATCH with one host read per batch:
+  // round k writes its (changed, infeasible) flags to rflags[2k..2k+1], and
+  // a round whose predecessor changed nothing (or found infeasibility) does
+  // nothing, so the state after the batch is the state at the fixpoint.
+  constexpr int PRESOLVE_BATCH = 4;
+  DArr<int> rflags;
+  DM_ALLOC(ctx, rflags, 2 * PRESOLVE_BATCH);
   int rounds = 0;
-  for (;;) {
-    DM_HIP(ctx, hipMemsetAsync(err.p, 0, 2 * sizeof(int), st));
-    if (nc > 0)
-      k_presolve_rows<<<grid_for(nc, 128), 128, 0, st>>>(ctx->row_ptr.p, ctx->ent_var.p, ctx->ent_coef.p,
-                                                         ctx->row_b.p, nc, ctx->state.p, force.p, err.p);
-    k_presolve_proj<<<unsigned(nrows - nc), 256, 0, st>>>(ctx->row_ptr.p, ctx->ent_var.p, nc, ctx->state.p,
-                                                          force.p, err.p);
-    k_presolve_vars<<<grid_for(nP, 256), 256, 0, st>>>(nP, ctx->state.p, force.p, err.p);
+  for (bool done = false; !done;) {
+    DM_HIP(ctx, hipMemsetAsync(rflags.p, 0, 2 * PRESOLVE_BATCH * sizeof(int), st));
+    for (int k = 0; k < PRESOLVE_BATCH; ++k) {
+      int* fl = rflags.p + 2 * k;
+      const int* prev = k > 0 ? rflags.p + 2 * (k - 1) : nullptr;
+      if (nc > 0)
+        k_presolve_rows<<<grid_for(nc, 128), 128, 0, st>>>(ctx->row_ptr.p, ctx->ent_var.p, ctx->ent_coef.p,
+                                                           ctx->row_b.p, nc, ctx->state.p, force.p, fl, prev);
+      k_presolve_proj<<<unsigned(nrows - nc), 256, 0, st>>>(ctx->row_ptr.p, ctx->ent_var.p, nc, ctx->state.p,
+                                                            force.p, fl, prev);
+      k_presolve_vars<<<grid_for(nP, 256), 256, 0, st>>>(nP, ctx->state.p, force.p, fl, prev);
+    }
     DM_LAUNCH_CHECK(ctx);
-    int flags[2];
-    DM_HIP(ctx, hipMemcpyAsync(flags, err.p, sizeof(flags), hipMemcpyDeviceToHost, st));
+    int flags[2 * PRESOLVE_BATCH];
+    DM_HIP(ctx, hipMemcpyAsync(flags, rflags.p, sizeof(flags), hipMemcpyDeviceToHost, st));
     DM_HIP(ctx, hipStreamSynchronize(st));
-    ++rounds;
-    if (flags[1]) return dm_fail(ctx, DM_ERR_INFEASIBLE, "presolve proved A x = b infeasible (round %d)", rounds);
-    if (!flags[0]) break;
-    if (rounds > nP + 2) return dm_fail(ctx, DM_ERR_STATE, "presolve did not converge");
+    for (int k = 0; k < PRESOLVE_BATCH && !done; ++k) {
+      ++rounds;
+      if (flags[2 * k + 1])
+        return dm_fail(ctx, DM_ERR_INFEASIBLE, "presolve proved A x = b infeasible (round %d)", rounds);
+      done = !flags[2 * k];
+    }
+    if (!done && rounds > nP + 2) return dm_fail(ctx, DM_ERR_STATE, "presolve did not converge");
   }
   ctx->presolve_rounds = rounds;
 
@@ -884,7 +944,7 @@ dm_status presolve_reduce(dm_ctx* ctx, const int8_t* fix) {
   DM_ALLOC(ctx, seg_off, size_t(n_seg) + 1);
   k_seg_rows<<<grid_for(n_seg + 1, 256), 256, 0, st>>>(ctx->rrow_ptr.p, nshort, n_seg, seg_row.p);
   if (n_seg > 0)
-    k_pack<<<grid_for(n_seg, 64), 64, 0, st>>>(seg_row.p, ctx->rrow_ptr.p, n_seg, seg_cnt.p, nullptr, nullptr, 0);
+    k_pack<<<unsigned(n_seg), 256, 0, st>>>(seg_row.p, ctx->rrow_ptr.p, n_seg, seg_cnt.p, nullptr, nullptr, 0);
   DM_LAUNCH_CHECK(ctx);
   DM_TRY(scan_i32(ctx, seg_cnt.p, seg_off.p, size_t(n_seg)));
   int32_t n_chunks = 0;
@@ -892,8 +952,8 @@ dm_status presolve_reduce(dm_ctx* ctx, const int8_t* fix) {
   ctx->n_chunks = n_chunks;
   DM_ALLOC(ctx, ctx->chunk_desc, size_t(std::max(n_chunks, 1)));
   if (n_seg > 0)
-    k_pack<<<grid_for(n_seg, 64), 64, 0, st>>>(seg_row.p, ctx->rrow_ptr.p, n_seg, nullptr, seg_off.p,
-                                               ctx->chunk_desc.p, 1);
+    k_pack<<<unsigned(n_seg), 256, 0, st>>>(seg_row.p, ctx->rrow_ptr.p, n_seg, nullptr, seg_off.p,
+                                            ctx->chunk_desc.p, 1);
   DM_ALLOC(ctx, ctx->chunk_mask, size_t(std::max(n_chunks, 1)));
   if (n_chunks > 0)
     k_chunk_mask<<<grid_for(n_chunks, 256), 256, 0, st>>>(ctx->chunk_desc.p, ctx->rrow_ptr.p, n_chunks,
