@@ -108,6 +108,27 @@ __global__ void k_corner_ptr(const uint32_t* key, int64_t n, int64_t nC, int32_t
 }  // namespace
 
 // constant of the dual objective: the summed costs of the elements fixed to 1
+// Corners of each candidate pair, ascending (3p+v), for the backward pass;
+// they depend on the product space only, so they are built once per space,
+// on the first backward.
+dm_status corner_lists(dm_ctx* ctx) {
+  if (ctx->corners_ready) return DM_OK;
+  const int64_t nP = ctx->nP, nC = ctx->nC;
+  hipStream_t st = ctx->stream;
+  DArr<uint32_t> key;
+  DM_ALLOC(ctx, key, size_t(std::max<int64_t>(3 * nP, 1)));
+  DM_ALLOC(ctx, ctx->corner_list, size_t(std::max<int64_t>(3 * nP, 1)));
+  DM_ALLOC(ctx, ctx->corner_ptr, size_t(nC) + 1);
+  if (nP > 0)
+    k_corner_keys<<<grid_for(3 * nP, 256), 256, 0, st>>>(ctx->pv.p, ctx->cidx.p, nP, key.p, ctx->corner_list.p);
+  DM_LAUNCH_CHECK(ctx);
+  DM_TRY(sort_pairs_u32(ctx, key.p, ctx->corner_list.p, size_t(3 * nP), bits_for(uint64_t(nC))));
+  k_corner_ptr<<<grid_for(nC + 1, 256), 256, 0, st>>>(key.p, 3 * nP, nC, ctx->corner_ptr.p);
+  DM_LAUNCH_CHECK(ctx);
+  ctx->corners_ready = true;
+  return DM_OK;
+}
+
 dm_status cost_offset(dm_ctx* ctx) {
   DM_ALLOC(ctx, ctx->scal, 16);
   DM_TRY(sum_f64(ctx, ctx->cost64.p, ctx->nP, ctx->state.p, SUM_I8_ONE, ctx->scal.p));   // elements fixed to 1
@@ -165,20 +186,7 @@ extern "C" dm_status dm_build_costs(dm_ctx* ctx, const float* FX, const float* F
   int e = 0;
   DM_TRY(read_i32(ctx, err.p, &e));
   if (e) return dm_fail(ctx, DM_ERR_NONFINITE, "non-finite element cost");
-  DM_TRY(cost_offset(ctx));
-  // corners of each candidate pair, ascending (3p+v), for the backward pass
-  {
-    DArr<uint32_t> key;
-    DM_ALLOC(ctx, key, size_t(3 * nP));
-    DM_ALLOC(ctx, ctx->corner_list, size_t(3 * nP));
-    DM_ALLOC(ctx, ctx->corner_ptr, size_t(nC) + 1);
-    k_corner_keys<<<grid_for(3 * nP, 256), 256, 0, st>>>(ctx->pv.p, ctx->cidx.p, nP, key.p, ctx->corner_list.p);
-    DM_LAUNCH_CHECK(ctx);
-    DM_TRY(sort_pairs_u32(ctx, key.p, ctx->corner_list.p, size_t(3 * nP), bits_for(uint64_t(nC))));
-    k_corner_ptr<<<grid_for(nC + 1, 256), 256, 0, st>>>(key.p, 3 * nP, nC, ctx->corner_ptr.p);
-    DM_LAUNCH_CHECK(ctx);
-  }
-  DM_HIP(ctx, hipStreamSynchronize(st));
+  DM_TRY(cost_offset(ctx));   // waits for the stream
   ctx->cost_prec = prec;
   ctx->has_cost = true;
   ++ctx->cost_generation;

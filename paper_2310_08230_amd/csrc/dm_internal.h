@@ -241,6 +241,7 @@ struct dm_ctx {
   double* pend_out = nullptr;    // bound of the last launch not yet summed
   DArr<double> scal;             // small device scalars
   DArr<double> sum_part;         // per-block partials of sum_f64
+  bool corners_ready = false;    // corner_ptr / corner_list match the product space
   DArr<int8_t> pref;             // per variable: 1, 0 or -1
   DArr<int64_t> icount;          // integer counters
   DArr<float> gw;                // gradient per pair
@@ -283,7 +284,8 @@ dm_status sum_f64(dm_ctx* ctx, const double* a, int64_t n, const void* sel, int 
 dm_status read_i32(dm_ctx* ctx, const int32_t* dev, int32_t* host);
 dm_status check_finite(dm_ctx* ctx, const float* a, int64_t n);
 dm_status dual_flush(dm_ctx* ctx);  // write the bound of the last sweep launch
-dm_status cost_offset(dm_ctx* ctx); // offset = summed costs of elements fixed to 1 (synchronises)
+dm_status cost_offset(dm_ctx* ctx);   // offset = summed costs of elements fixed to 1 (synchronises)
+dm_status corner_lists(dm_ctx* ctx);  // corners per candidate pair (built once per product space)
 dm_status presolve_reduce(dm_ctx* ctx, const int8_t* fix);  // presolve from fixings, reduced problem
 
 // One sweep over all rows of the presolved problem (dual.hip).  Modes: update

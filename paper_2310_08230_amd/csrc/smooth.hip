@@ -101,6 +101,7 @@ static dm_status backward_impl(dm_ctx* ctx, const R* lam, R T, double scale, con
   DM_TRY(dual_sweep<R>(ctx, SWEEP_EVAL, true, bufs[0].p, ctx->mrec.p, R(0), T, ctx->scal.p + 2));
   DM_TRY(dual_flush(ctx));
   DM_ALLOC(ctx, ctx->gcost_tmp, size_t(ctx->nP));
+  DM_TRY(corner_lists(ctx));
   DM_ALLOC(ctx, ctx->gw, size_t(std::max<int64_t>(ctx->nC, 1)));
   k_gcost<R><<<grid_for(ctx->nP, 256), 256, 0, st>>>(ctx->state.p, ctx->var_red.p, ctx->var_deg.p,
                                                      reinterpret_cast<const R*>(ctx->mrec.p), ctx->nP, scale,

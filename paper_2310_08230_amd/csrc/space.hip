@@ -996,6 +996,7 @@ extern "C" dm_status dm_build_product_space(dm_ctx* ctx, const dm_mesh* Xin, con
   if (!ctx) return DM_ERR_INVALID_ARG;
   ctx->err.clear();
   ctx->has_space = false;
+  ctx->corners_ready = false;
   ctx->has_cost = false;
   if (!Xin || !Yin || !cand_xy || !cand_yx || !info)
     return dm_fail(ctx, DM_ERR_INVALID_ARG, "dm_build_product_space: NULL argument");
