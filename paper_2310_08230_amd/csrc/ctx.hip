@@ -36,6 +36,12 @@ extern "C" dm_status dm_create(int32_t device, void* hip_stream, dm_ctx** out) {
   dm_ctx* c = new dm_ctx();
   c->device = device;
   c->stream = static_cast<hipStream_t>(hip_stream);
+  // pinned landing slots for small device-to-host reads
+  if (hipHostMalloc(reinterpret_cast<void**>(&c->host_i32), HOST_SLOTS * sizeof(int32_t), hipHostMallocDefault) !=
+      hipSuccess) {
+    delete c;
+    return DM_ERR_HIP;
+  }
   *out = c;
   return DM_OK;
 }
@@ -44,6 +50,7 @@ extern "C" dm_status dm_destroy(dm_ctx* ctx) {
   if (!ctx) return DM_ERR_INVALID_ARG;
   (void)hipSetDevice(ctx->device);
   (void)hipStreamSynchronize(ctx->stream);
+  if (ctx->host_i32) (void)hipHostFree(ctx->host_i32);
   delete ctx;
   return DM_OK;
 }
@@ -185,8 +192,15 @@ dm_status scan_u8(dm_ctx* ctx, const uint8_t* in, int32_t* out, size_t n) {
 }
 
 dm_status read_i32(dm_ctx* ctx, const int32_t* dev, int32_t* host) {
-  DM_HIP(ctx, hipMemcpyAsync(host, dev, sizeof(int32_t), hipMemcpyDeviceToHost, ctx->stream));
+  return read_i32s(ctx, 1, &dev, host);
+}
+
+dm_status read_i32s(dm_ctx* ctx, int n, const int32_t* const* dev, int32_t* host) {
+  if (n < 0 || n > HOST_SLOTS) return dm_fail(ctx, DM_ERR_STATE, "read_i32s: %d values (at most %d)", n, HOST_SLOTS);
+  for (int i = 0; i < n; ++i)
+    DM_HIP(ctx, hipMemcpyAsync(ctx->host_i32 + i, dev[i], sizeof(int32_t), hipMemcpyDeviceToHost, ctx->stream));
   DM_HIP(ctx, hipStreamSynchronize(ctx->stream));
+  for (int i = 0; i < n; ++i) host[i] = ctx->host_i32[i];
   return DM_OK;
 }
 

@@ -164,6 +164,8 @@ __device__ inline double sum_partials_1024(const double* p, int n, double* red) 
   return r;
 }
 
+constexpr int HOST_SLOTS = 16;
+
 struct dm_ctx {
   int device = 0;
   hipStream_t stream = nullptr;
@@ -242,6 +244,7 @@ struct dm_ctx {
   DArr<double> scal;             // small device scalars
   DArr<double> sum_part;         // per-block partials of sum_f64
   bool corners_ready = false;    // corner_ptr / corner_list match the product space
+  int32_t* host_i32 = nullptr;   // HOST_SLOTS pinned ints: landing slots of read_i32s
   DArr<int8_t> pref;             // per variable: 1, 0 or -1
   DArr<int64_t> icount;          // integer counters
   DArr<float> gw;                // gradient per pair
@@ -282,6 +285,8 @@ dm_status scan_u8(dm_ctx* ctx, const uint8_t* in, int32_t* out, size_t n);   // 
 enum SumSel { SUM_ALL = 0, SUM_I8_ONE = 1, SUM_U8_NZ = 2 };
 dm_status sum_f64(dm_ctx* ctx, const double* a, int64_t n, const void* sel, int kind, double* out);
 dm_status read_i32(dm_ctx* ctx, const int32_t* dev, int32_t* host);
+// n (<= HOST_SLOTS) device ints into host[0..n) with one wait for the stream
+dm_status read_i32s(dm_ctx* ctx, int n, const int32_t* const* dev, int32_t* host);
 dm_status check_finite(dm_ctx* ctx, const float* a, int64_t n);
 dm_status dual_flush(dm_ctx* ctx);  // write the bound of the last sweep launch
 dm_status cost_offset(dm_ctx* ctx);   // offset = summed costs of elements fixed to 1 (synchronises)

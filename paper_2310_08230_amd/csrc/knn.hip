@@ -169,13 +169,11 @@ dm_status knn_distances(dm_ctx* ctx, const float* FX, int32_t nvx, const float* 
     dim3 grid(unsigned(nyp / 64), unsigned(nxp / 64));
     k_gemm_bf16_dist<<<grid, 256, 0, st>>>(A.p, B.p, na.p, nb.p, nvx, nvy, Dp, d2);
     DM_LAUNCH_CHECK(ctx);
-    DM_HIP(ctx, hipStreamSynchronize(st));
     return DM_OK;
   }
   if (prec == DM_PREC_FP32 || prec == DM_PREC_FP64) {
     k_dist_fp32<<<grid_for(int64_t(nvx) * nvy, 256), 256, 0, st>>>(FX, FY, nvx, nvy, D, d2);
     DM_LAUNCH_CHECK(ctx);
-    DM_HIP(ctx, hipStreamSynchronize(st));
     return DM_OK;
   }
   return dm_fail(ctx, DM_ERR_INVALID_ARG, "unknown precision %d", prec);
@@ -198,6 +196,5 @@ extern "C" dm_status dm_knn_candidates(dm_ctx* ctx, const float* FX, int32_t nvx
   k_topk<<<nvx, 256, 0, ctx->stream>>>(d2.p, nvx, nvy, 0, K, cand_xy);
   k_topk<<<nvy, 256, 0, ctx->stream>>>(d2.p, nvx, nvy, 1, K, cand_yx);
   DM_LAUNCH_CHECK(ctx);
-  DM_HIP(ctx, hipStreamSynchronize(ctx->stream));
-  return DM_OK;
+  return DM_OK;   // enqueued only; temporaries are freed in stream order
 }

@@ -147,11 +147,16 @@ dm_status mesh_ingest(dm_ctx* ctx, const dm_mesh* in, MeshDev& m, const char* na
   DM_ALLOC(ctx, eid, size_t(nc) + 1);
   k_edge_check<<<grid_for(nc, 256), 256, 0, ctx->stream>>>(m.dkey.p, nc, nv, lower.p, err.p);
   DM_LAUNCH_CHECK(ctx);
-  DM_TRY(read_i32(ctx, err.p, &e));
-  if (e) return mesh_error(ctx, e, name);
   DM_TRY(scan_u8(ctx, lower.p, eid.p, size_t(nc)));
   int32_t ne = 0;
-  DM_TRY(read_i32(ctx, eid.p + nc, &ne));
+  {
+    const int32_t* src[2] = {err.p, eid.p + nc};
+    int32_t v[2];
+    DM_TRY(read_i32s(ctx, 2, src, v));
+    e = v[0];
+    ne = v[1];
+  }
+  if (e) return mesh_error(ctx, e, name);
   m.ne = ne;
   if (int64_t(ne) * 2 != nc) return dm_fail(ctx, DM_ERR_MESH, "mesh %s: not closed", name);
   DM_ALLOC(ctx, m.edges, size_t(ne) * 2);
@@ -234,8 +239,7 @@ dm_status mesh_areas(dm_ctx* ctx, MeshDev& m) {
   k_vertex_area<<<grid_for(m.nv, 256), 256, 0, ctx->stream>>>(m.dkey.p, m.dval.p, int64_t(m.nf) * 3,
                                                               m.nv, contrib.p, m.area.p);
   DM_LAUNCH_CHECK(ctx);
-  DM_HIP(ctx, hipStreamSynchronize(ctx->stream));
-  return DM_OK;
+  return DM_OK;   // contrib is freed in stream order
 }
 
 extern "C" dm_status dm_mixed_areas(dm_ctx* ctx, const dm_mesh* M, double* out) {

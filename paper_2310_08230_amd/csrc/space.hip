@@ -751,8 +751,13 @@ dm_status space_build(dm_ctx* ctx, const int32_t* cand_xy, const int32_t* cand_y
   DM_LAUNCH_CHECK(ctx);
   DM_TRY(scan_u8(ctx, rflag.p, rexcl.p, size_t(3 * nP)));
   int32_t nc = 0, nXf = 0;
-  DM_TRY(read_i32(ctx, rexcl.p + 3 * nP, &nc));
-  DM_TRY(read_i32(ctx, off.p + g.QA, &nXf));
+  {
+    const int32_t* src[2] = {rexcl.p + 3 * nP, off.p + g.QA};
+    int32_t v[2];
+    DM_TRY(read_i32s(ctx, 2, src, v));
+    nc = v[0];
+    nXf = v[1];
+  }
   ctx->n_closed_full = nc;
 
   // ---- Y projection rows: stable sort of Y-face elements by face
@@ -866,8 +871,13 @@ dm_status presolve_reduce(dm_ctx* ctx, const int8_t* fix) {
   DM_LAUNCH_CHECK(ctx);
   DM_TRY(scan_u8(ctx, fflag.p, fexcl.p, size_t(nP)));
   int32_t nfree = 0, nfix1 = 0;
-  DM_TRY(read_i32(ctx, fexcl.p + nP, &nfree));
-  DM_TRY(read_i32(ctx, err.p + 1, &nfix1));
+  {
+    const int32_t* src[2] = {fexcl.p + nP, err.p + 1};
+    int32_t v[2];
+    DM_TRY(read_i32s(ctx, 2, src, v));
+    nfree = v[0];
+    nfix1 = v[1];
+  }
   ctx->n_free = nfree;
   ctx->n_fixed1 = nfix1;
   DM_ALLOC(ctx, ctx->var_red, size_t(nP));
@@ -893,11 +903,16 @@ dm_status presolve_reduce(dm_ctx* ctx, const int8_t* fix) {
   DM_TRY(scan_u8(ctx, keep.p, new_id.p, size_t(nrows)));
   DM_TRY(scan_i32(ctx, nfr.p, cnt_excl.p, size_t(nrows)));
   int32_t nr = 0, rnnz = 0, nshort = 0, flg1 = 0;
-  DM_TRY(read_i32(ctx, err.p + 1, &flg1));
+  {
+    const int32_t* src[4] = {err.p + 1, new_id.p + nrows, cnt_excl.p + nrows, new_id.p + nc};
+    int32_t v[4];
+    DM_TRY(read_i32s(ctx, 4, src, v));
+    flg1 = v[0];
+    nr = v[1];
+    rnnz = v[2];
+    nshort = v[3];
+  }
   if (flg1) return dm_fail(ctx, DM_ERR_INFEASIBLE, "a fully fixed row is violated");
-  DM_TRY(read_i32(ctx, new_id.p + nrows, &nr));
-  DM_TRY(read_i32(ctx, cnt_excl.p + nrows, &rnnz));
-  DM_TRY(read_i32(ctx, new_id.p + nc, &nshort));
   ctx->n_rows = nr;
   ctx->nnz = rnnz;
   ctx->n_short = nshort;
