@@ -280,6 +280,42 @@ dm_status dm_round_primal(dm_ctx* ctx, const dm_round_params* params, const void
  * number of violated rows in *violations [host].  Synchronises. */
 dm_status dm_check_primal(dm_ctx* ctx, const uint8_t* x, int64_t* violations);
 
+/* Exact search on the residual of confident fixing (Appendix "Coarse-to-fine
+ * solving strategy": the variables left free after fixing are solved
+ * exactly; the paper uses a MILP solver there, this is the library's own
+ * depth-first branch and bound).  The searched problem is the ILP with the
+ * fixings base_fix (NULL: none).  Per node (base fixings plus the branching
+ * decisions on its path): presolve from the node's fixings (an infeasible
+ * node is pruned), dual_iters Jacobi iterations from dm_init_lambda (their
+ * best bound is a valid lower bound of the node; Eq. (D)), rounding with the
+ * given parameters for a primal, and the branching choice: the free
+ * variable whose summed min-marginal differences are closest to zero (ties
+ * to the lower variable), its preferred value (negative sum -> 1) explored
+ * first.  A node is pruned when its bound is within rel_tol * max(1,
+ * |incumbent|) of the incumbent.  On return the problem with base_fix is
+ * in place (as after dm_fix_variables(base_fix); infeasible base fixings
+ * leave the problem without fixings and status DM_SEARCH_INFEASIBLE).
+ *  base_fix [device] int8 [n_prod_tri] (-1 free, else the fixed value) or
+ *  NULL; x [device] uint8 [n_prod_tri] out (the best primal, zeros if none);
+ *  *primal_obj [host] (+inf if none), *bound [host] (the optimum when proved,
+ *  else the root bound), *nodes [host] (nodes visited), *status [host]:
+ *  DM_SEARCH_OPTIMAL (tree exhausted: x is optimal within rel_tol),
+ *  DM_SEARCH_INFEASIBLE (tree exhausted, no feasible x), DM_SEARCH_LIMIT
+ *  (max_nodes reached: x is the best found); *info [host] out (sizes of the
+ *  restored problem) or NULL.  Synchronises. */
+typedef struct {
+  int32_t max_nodes;       /* node limit, >= 1 */
+  int32_t dual_iters;      /* Jacobi iterations per node, >= 1 */
+  double omega;            /* their damping, (0, 1] */
+  double rel_tol;          /* pruning tolerance, >= 0 */
+  dm_round_params round;   /* rounding at each node; round.msg_prec is the
+                              message precision of the whole search */
+} dm_search_params;
+enum { DM_SEARCH_INFEASIBLE = -1, DM_SEARCH_LIMIT = 0, DM_SEARCH_OPTIMAL = 1 };
+dm_status dm_exact_search(dm_ctx* ctx, const dm_search_params* params, const int8_t* base_fix, uint8_t* x,
+                          double* primal_obj, double* bound, int32_t* nodes, int32_t* status,
+                          dm_space_info* info);
+
 /* Gradient of the smoothed bound L_T(lambda) (A11).  With
  * lambda^j_i = c_i/|J_i| + phi^j_i and phi held fixed:
  *   dL/dc_i = mean_j mu^j_i (free), 1 (fixed to 1), 0 (fixed to 0),

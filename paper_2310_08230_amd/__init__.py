@@ -48,6 +48,14 @@ class dm_round_params(C.Structure):
                 ("msg_prec", C.c_int32)]
 
 
+class dm_search_params(C.Structure):
+    _fields_ = [("max_nodes", C.c_int32), ("dual_iters", C.c_int32), ("omega", C.c_double),
+                ("rel_tol", C.c_double), ("round", dm_round_params)]
+
+
+SEARCH_STATUS = {-1: "infeasible", 0: "limit", 1: "optimal"}
+
+
 class dm_lbfgs_params(C.Structure):
     _fields_ = [("history", C.c_int32), ("max_search", C.c_int32), ("omega", C.c_double),
                 ("eps", C.c_double), ("step_up", C.c_double), ("step_down", C.c_double),
@@ -281,6 +289,25 @@ class Context:
         p, feas, r = C.c_double(0), C.c_int32(0), C.c_int32(0)
         self._call("dm_round_primal", C.byref(P), _ptr(lam), _ptr(x), C.byref(p), C.byref(feas), C.byref(r))
         return x, p.value, bool(feas.value), r.value
+
+    def exact_search(self, base_fix=None, max_nodes=1000, dual_iters=100, omega=0.5, rel_tol=1e-9,
+                     msg_prec="fp64", rounds=10, iters_per_round=25, delta0=0.0, gamma=1.5, seed=0):
+        """Depth-first branch and bound on the problem with the fixings
+        base_fix (None: none); returns (x, primal objective, bound, nodes,
+        status) with status "optimal", "infeasible" or "limit".  The
+        problem with base_fix is in place afterwards."""
+        f = None if base_fix is None else _dev(base_fix, torch.int8, self.device)
+        R = dm_round_params(rounds, iters_per_round, delta0, gamma, seed, omega, PREC[msg_prec])
+        P = dm_search_params(max_nodes, dual_iters, omega, rel_tol, R)
+        x = torch.empty(self.info["n_prod_tri"], dtype=torch.uint8, device=self.device)
+        p, b, n, st = C.c_double(0), C.c_double(0), C.c_int32(0), C.c_int32(0)
+        info = dm_space_info()
+        try:
+            self._call("dm_exact_search", C.byref(P), _ptr(f) if f is not None else None, _ptr(x), C.byref(p),
+                       C.byref(b), C.byref(n), C.byref(st), C.byref(info))
+        finally:   # the problem with base_fix is in place afterwards
+            self.info = {k: getattr(info, k) for k, _ in dm_space_info._fields_}
+        return x, p.value, b.value, n.value, SEARCH_STATUS[st.value]
 
     def check_primal(self, x):
         x = _dev(x, torch.uint8, self.device)

@@ -291,6 +291,7 @@ dm_status check_finite(dm_ctx* ctx, const float* a, int64_t n);
 dm_status dual_flush(dm_ctx* ctx);  // write the bound of the last sweep launch
 dm_status cost_offset(dm_ctx* ctx);   // offset = summed costs of elements fixed to 1 (synchronises)
 dm_status corner_lists(dm_ctx* ctx);  // corners per candidate pair (built once per product space)
+void fill_info(dm_ctx* ctx, dm_space_info* info);   // sizes of the current (reduced) problem
 dm_status presolve_reduce(dm_ctx* ctx, const int8_t* fix);  // presolve from fixings, reduced problem
 
 // One sweep over all rows of the presolved problem (dual.hip).  Modes: update

@@ -1,0 +1,269 @@
+// Exact search on the residual of confident fixing (Appendix "Coarse-to-fine
+// solving strategy": the variables left free after fixing are solved exactly;
+// the paper hands them to a commercial MILP solver, here a depth-first branch
+// and bound of the library's own).
+//
+// A node is the problem with the base fixings plus the branching decisions on
+// its path.  Per node, all on the device: presolve from the node's fixings
+// (integer unit propagation; an infeasible node is pruned), Jacobi iterations
+// whose best bound is a valid lower bound of the node's ILP (Eq. (D) is a
+// Lagrangean dual), perturbation rounding for a primal, and one min-marginal
+// sweep for the branching choice: the free variable whose summed min-marginal
+// differences are closest to zero (the least confident one; ties to the lower
+// variable), with the value its min-marginals prefer explored first.  A node is
+// pruned when its bound reaches the incumbent; the search is exact when the
+// tree is exhausted.
+#include <algorithm>
+#include <cmath>
+#include <limits>
+#include <vector>
+
+#include "dm_internal.h"
+
+namespace {
+
+// key of free variable i: (|sum_j M^j_i| as FP32 bits) << 32 | i, so the
+// smallest key is the least confident variable, ties to the lower index
+template <typename R>
+__global__ void k_branch_keys(const R* mrec, const uint8_t* deg, int64_t nfree, unsigned long long* best) {
+  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  unsigned long long key = ~0ull;
+  if (i < nfree) {
+    const R* m = mrec + size_t(i) * REC;
+    double sum = 0.0;
+    for (int k = 0; k < deg[i]; ++k) sum += double(m[k]);
+    const float a = float(fabs(sum));   // >= 0: its bits order like its value
+    key = (static_cast<unsigned long long>(__float_as_uint(a)) << 32) | static_cast<unsigned long long>(i);
+  }
+  for (int o = 32; o > 0; o >>= 1) {
+    const unsigned long long other = __shfl_xor(key, o);
+    key = other < key ? other : key;
+  }
+  if ((threadIdx.x & 63) == 0 && key != ~0ull) atomicMin(best, key);
+}
+
+// preferred value of free variable i: 1 when its summed min-marginal
+// differences are negative
+template <typename R>
+__global__ void k_branch_pref(const R* mrec, const uint8_t* deg, const unsigned long long* best,
+                              const int32_t* free_var, int32_t* out) {
+  const int32_t i = int32_t(*best & 0xFFFFFFFFull);
+  const R* m = mrec + size_t(i) * REC;
+  double sum = 0.0;
+  for (int k = 0; k < deg[i]; ++k) sum += double(m[k]);
+  out[0] = free_var[i];
+  out[1] = sum < 0.0 ? 1 : 0;
+}
+
+__global__ void k_apply_path(const int32_t* path, int32_t n, int8_t* fix) {
+  const int32_t k = int32_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (k < n) fix[path[2 * k]] = int8_t(path[2 * k + 1]);
+}
+
+__global__ void k_state_to_x(const int8_t* state, int64_t nP, uint8_t* x) {
+  const int64_t p = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (p < nP) x[p] = state[p] == 1 ? 1 : 0;
+}
+
+struct Decision {
+  int32_t elem, value;
+};
+
+template <typename R>
+dm_status node_bound_and_branch(dm_ctx* ctx, const dm_search_params& P, DArr<unsigned char>& lam_buf,
+                                double* lb, bool* branch, Decision* choice) {
+  hipStream_t st = ctx->stream;
+  const int64_t nnz = ctx->nnz, nf = ctx->n_free;
+  DM_ALLOC(ctx, lam_buf, size_t(std::max<int64_t>(nnz, 1)) * sizeof(R));
+  R* lam = reinterpret_cast<R*>(lam_buf.p);
+  const int32_t prec = sizeof(R) == 4 ? DM_PREC_FP32 : DM_PREC_FP64;
+  DM_TRY(dm_init_lambda(ctx, prec, lam));
+  DArr<double> trace;
+  const int32_t iters = std::max(P.dual_iters, 1);
+  DM_ALLOC(ctx, trace, size_t(iters));
+  DM_TRY(dm_dual_solve(ctx, iters, P.omega, 0.0, prec, lam, trace.p));
+  std::vector<double> tr(static_cast<size_t>(iters), 0.0);
+  DM_HIP(ctx, hipMemcpyAsync(tr.data(), trace.p, sizeof(double) * iters, hipMemcpyDeviceToHost, st));
+  DM_HIP(ctx, hipStreamSynchronize(st));
+  double best = -std::numeric_limits<double>::infinity();
+  for (double v : tr) best = std::max(best, v);
+  double at_end = 0.0;
+  DM_TRY(dm_lower_bound(ctx, lam, 0.0, prec, &at_end));
+  *lb = std::max(best, at_end);
+  *branch = nf > 0;
+  if (!*branch) return DM_OK;
+  // min-marginal differences at the final multipliers
+  DArr<unsigned char> bufs[2];
+  DM_TRY(dual_flush(ctx));
+  DM_TRY(dual_import<R>(ctx, lam, bufs));
+  const size_t bytes = size_t(nf) * REC * sizeof(R);
+  DM_ALLOC(ctx, ctx->mrec, bytes);
+  DM_HIP(ctx, hipMemsetAsync(ctx->mrec.p, 0, bytes, st));
+  DM_TRY(dual_sweep<R>(ctx, SWEEP_EVAL, false, bufs[0].p, ctx->mrec.p, R(0), R(0), nullptr));
+  DArr<unsigned long long> key;
+  DArr<int32_t> out;
+  DM_ALLOC(ctx, key, 1);
+  DM_ALLOC(ctx, out, 2);
+  DM_HIP(ctx, hipMemsetAsync(key.p, 0xFF, sizeof(unsigned long long), st));
+  k_branch_keys<R><<<grid_for(nf, 256), 256, 0, st>>>(reinterpret_cast<const R*>(ctx->mrec.p), ctx->var_deg.p, nf,
+                                                       key.p);
+  k_branch_pref<R><<<1, 1, 0, st>>>(reinterpret_cast<const R*>(ctx->mrec.p), ctx->var_deg.p, key.p,
+                                    ctx->free_var.p, out.p);
+  DM_LAUNCH_CHECK(ctx);
+  const int32_t* src[2] = {out.p, out.p + 1};
+  int32_t v[2];
+  DM_TRY(read_i32s(ctx, 2, src, v));
+  choice->elem = v[0];
+  choice->value = v[1];
+  return DM_OK;
+}
+
+template <typename R>
+dm_status search_impl(dm_ctx* ctx, const dm_search_params& P, const int8_t* base_fix, uint8_t* x,
+                      double* primal_obj, double* bound, int32_t* nodes_out, int32_t* status) {
+  hipStream_t st = ctx->stream;
+  const int64_t nP = ctx->nP;
+  DArr<int8_t> fix;
+  DArr<uint8_t> xnode;
+  DArr<int32_t> path_dev;
+  DArr<unsigned char> lam_buf;
+  DM_ALLOC(ctx, fix, size_t(std::max<int64_t>(nP, 1)));
+  DM_ALLOC(ctx, xnode, size_t(std::max<int64_t>(nP, 1)));
+  double incumbent = std::numeric_limits<double>::infinity();
+  double root_lb = -std::numeric_limits<double>::infinity();
+  bool root_done = false, limit_hit = false;
+  int32_t nodes = 0;
+  // depth-first: every stack entry is a full path of decisions
+  std::vector<std::vector<Decision>> stack;
+  stack.emplace_back();
+  dm_status result = DM_OK;
+  while (!stack.empty()) {
+    if (nodes >= P.max_nodes) {
+      limit_hit = true;
+      break;
+    }
+    std::vector<Decision> path = std::move(stack.back());
+    stack.pop_back();
+    ++nodes;
+    // node fixings: the base ones plus the path
+    if (base_fix)
+      DM_HIP(ctx, hipMemcpyAsync(fix.p, base_fix, size_t(nP), hipMemcpyDeviceToDevice, st));
+    else
+      DM_HIP(ctx, hipMemsetAsync(fix.p, 0xFF, size_t(nP), st));
+    if (!path.empty()) {
+      std::vector<int32_t> flat;
+      for (const Decision& d : path) {
+        flat.push_back(d.elem);
+        flat.push_back(d.value);
+      }
+      DM_ALLOC(ctx, path_dev, flat.size());
+      DM_HIP(ctx, hipMemcpyAsync(path_dev.p, flat.data(), sizeof(int32_t) * flat.size(), hipMemcpyHostToDevice,
+                                 st));
+      k_apply_path<<<grid_for(int64_t(path.size()), 256), 256, 0, st>>>(path_dev.p, int32_t(path.size()), fix.p);
+      DM_LAUNCH_CHECK(ctx);
+      DM_HIP(ctx, hipStreamSynchronize(st));   // flat is host memory
+    }
+    const dm_status ps = presolve_reduce(ctx, fix.p);
+    if (ps == DM_ERR_INFEASIBLE) {
+      ctx->err.clear();
+      if (!root_done) {
+        root_done = true;
+        root_lb = std::numeric_limits<double>::infinity();
+      }
+      continue;
+    }
+    if (ps != DM_OK) {
+      result = ps;
+      break;
+    }
+    if ((result = cost_offset(ctx)) != DM_OK) break;
+    double lb = 0.0;
+    bool branch = false;
+    Decision choice{0, 0};
+    if ((result = node_bound_and_branch<R>(ctx, P, lam_buf, &lb, &branch, &choice)) != DM_OK) break;
+    if (!root_done) {
+      root_done = true;
+      root_lb = lb;
+    }
+    const double tol = P.rel_tol * std::max(1.0, std::fabs(incumbent));
+    if (lb >= incumbent - tol) continue;   // cannot improve on the incumbent
+    // a primal at this node
+    double pobj = 0.0;
+    int32_t feas = 0, used = 0;
+    if (!branch) {   // presolve fixed everything: the state is the assignment
+      k_state_to_x<<<grid_for(nP, 256), 256, 0, st>>>(ctx->state.p, nP, xnode.p);
+      DM_LAUNCH_CHECK(ctx);
+      int64_t viol = 0;
+      if ((result = dm_check_primal(ctx, xnode.p, &viol)) != DM_OK) break;
+      feas = viol == 0;
+      pobj = ctx->offset;
+    } else {
+      dm_round_params rp = P.round;
+      rp.msg_prec = sizeof(R) == 4 ? DM_PREC_FP32 : DM_PREC_FP64;
+      if ((result = dm_round_primal(ctx, &rp, lam_buf.p, xnode.p, &pobj, &feas, &used)) != DM_OK) break;
+    }
+    if (feas && pobj < incumbent) {
+      incumbent = pobj;
+      DM_HIP(ctx, hipMemcpyAsync(x, xnode.p, size_t(nP), hipMemcpyDeviceToDevice, st));
+    }
+    if (!branch || lb >= incumbent - P.rel_tol * std::max(1.0, std::fabs(incumbent))) continue;
+    // children: the preferred value is explored first (pushed last)
+    std::vector<Decision> other = path, pref = std::move(path);
+    other.push_back({choice.elem, 1 - choice.value});
+    pref.push_back(choice);
+    stack.push_back(std::move(other));
+    stack.push_back(std::move(pref));
+  }
+  // back to the problem with the base fixings only
+  const std::string msg = ctx->err;
+  dm_status rs = presolve_reduce(ctx, base_fix);
+  if (rs == DM_ERR_INFEASIBLE && base_fix) {   // infeasible base fixings: back to no fixings
+    ctx->err.clear();
+    rs = presolve_reduce(ctx, nullptr);
+  }
+  if (rs != DM_OK) {
+    ctx->has_space = false;   // the reduced problem is half rebuilt: unusable
+    return result != DM_OK ? result : rs;
+  }
+  if (ctx->has_cost) DM_TRY(cost_offset(ctx));
+  ++ctx->cost_generation;   // solver state of the node problems is stale
+  ctx->err = msg;
+  if (result != DM_OK) return result;
+  DM_HIP(ctx, hipStreamSynchronize(st));
+  *nodes_out = nodes;
+  *primal_obj = incumbent;
+  if (!limit_hit) {
+    *status = std::isfinite(incumbent) ? DM_SEARCH_OPTIMAL : DM_SEARCH_INFEASIBLE;
+    *bound = incumbent;
+  } else {
+    *status = DM_SEARCH_LIMIT;
+    *bound = std::min(root_lb, incumbent);
+  }
+  if (!std::isfinite(incumbent)) DM_HIP(ctx, hipMemsetAsync(x, 0, size_t(nP), st));
+  DM_HIP(ctx, hipStreamSynchronize(st));
+  return DM_OK;
+}
+
+}  // namespace
+
+extern "C" dm_status dm_exact_search(dm_ctx* ctx, const dm_search_params* params, const int8_t* base_fix,
+                                     uint8_t* x, double* primal_obj, double* bound, int32_t* nodes,
+                                     int32_t* status, dm_space_info* info) {
+  if (!ctx) return DM_ERR_INVALID_ARG;
+  ctx->err.clear();
+  if (!ctx->has_space || !ctx->has_cost) return dm_fail(ctx, DM_ERR_STATE, "dm_exact_search: build space and costs first");
+  if (!params || !x || !primal_obj || !bound || !nodes || !status)
+    return dm_fail(ctx, DM_ERR_INVALID_ARG, "dm_exact_search: NULL argument");
+  const dm_search_params& P = *params;
+  if (P.max_nodes < 1 || P.dual_iters < 1 || !(P.omega > 0.0 && P.omega <= 1.0) || !(P.rel_tol >= 0.0))
+    return dm_fail(ctx, DM_ERR_INVALID_ARG, "dm_exact_search: bad parameters");
+  if (P.round.msg_prec != DM_PREC_FP32 && P.round.msg_prec != DM_PREC_FP64)
+    return dm_fail(ctx, DM_ERR_INVALID_ARG, "dm_exact_search: message precision must be FP32 or FP64");
+  DM_HIP(ctx, hipSetDevice(ctx->device));
+  DM_TRY(dual_flush(ctx));
+  const dm_status s = P.round.msg_prec == DM_PREC_FP32
+                         ? search_impl<float>(ctx, P, base_fix, x, primal_obj, bound, nodes, status)
+                         : search_impl<double>(ctx, P, base_fix, x, primal_obj, bound, nodes, status);
+  if (info && ctx->has_space) fill_info(ctx, info);
+  return s;
+}

@@ -1003,7 +1003,6 @@ dm_status presolve_reduce(dm_ctx* ctx, const int8_t* fix) {
   return DM_OK;
 }
 
-static void fill_info(dm_ctx* ctx, dm_space_info* info);
 
 extern "C" dm_status dm_build_product_space(dm_ctx* ctx, const dm_mesh* Xin, const dm_mesh* Yin,
                                             const int32_t* cand_xy, const int32_t* cand_yx, int32_t K,
@@ -1055,7 +1054,7 @@ extern "C" dm_status dm_fix_variables(dm_ctx* ctx, const int8_t* fix, dm_space_i
   return DM_OK;
 }
 
-static void fill_info(dm_ctx* ctx, dm_space_info* info) {
+void fill_info(dm_ctx* ctx, dm_space_info* info) {
   dm_space_info& I = *info;
   I.n_prod_tri = ctx->nP;
   I.n_rows_full = ctx->n_rows_full;

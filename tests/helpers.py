@@ -152,3 +152,21 @@ def full_candidates(nvx, nvy):
     cxy = np.array([[(m + k) % nvy for k in range(K)] for m in range(nvx)], np.int32)
     cyx = np.array([[(n + k) % nvx for k in range(K)] for n in range(nvy)], np.int32)
     return cxy, cyx, K
+
+
+def milp_optimum(S):
+    """Exact ILP optimum of the oracle space's current (reduced) problem by
+    HiGHS, offset included; None when HiGHS finds it infeasible."""
+    from scipy.optimize import Bounds, LinearConstraint, milp
+    from scipy.sparse import csr_matrix
+    n = S.info["n_free"]
+    if n == 0:
+        return S.offset
+    rows = reduced_rows(S)
+    c = S.get("cost")[S.get("free_var")]
+    r = np.concatenate([[j] * len(vs) for j, (vs, _, _) in enumerate(rows)])
+    A = csr_matrix((np.concatenate([cs for _, cs, _ in rows]).astype(float),
+                    (r, np.concatenate([vs for vs, _, _ in rows]))), shape=(len(rows), n))
+    b = np.array([b for _, _, b in rows], float)
+    res = milp(c, constraints=LinearConstraint(A, b, b), integrality=np.ones(n), bounds=Bounds(0, 1))
+    return res.fun + S.offset if res.status == 0 else None
