@@ -45,6 +45,7 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-gap", action="store_true")
     ap.add_argument("--no-pairs", action="store_true", help="skip the per-pair sweep rooflines")
+    ap.add_argument("--no-search", action="store_true", help="skip the exact-search timing")
     ap.add_argument("--cpu-sample-iters", type=int, default=100)
     ap.add_argument("--gap-seeds", default="0,1,2,3,4", help="seeds of the time-to-1%%-gap runs (median reported)")
     return ap.parse_args()
@@ -88,6 +89,27 @@ class Workload:
             out.update(pobj=pobj, feasible=feas, rounds=rounds,
                        gap=(pobj - dmax) / pobj if pobj else 0.0)
         return out
+
+
+def exact_search_run(seed=0, max_nodes=3000, dual_iters=60):
+    """Branch and bound on a pair whose LP relaxation leaves an integrality
+    gap (the 80-face pair, descriptor noise 1.0, K = 16): wall time to a
+    proved optimum, nodes, and the root bound for the size of the gap."""
+    import torch
+    w = Workload(1, seed, desc_noise=1.0, k=16)
+    c = w.ctx
+    cxy, cyx = c.knn_candidates(w.DX, w.DY, 16, "fp32")
+    info = c.build_product_space(w.VX, w.FX, w.VY, w.FY, cxy, cyx)
+    c.build_costs(w.DX, w.DY, "fp64")
+    root = c.lower_bound(c.dual_solve(c.init_lambda("fp64"), dual_iters, 0.5)[0])
+    c.exact_search(max_nodes=2, dual_iters=dual_iters)   # untimed: loads the kernels
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    x, pobj, bound, nodes, status = c.exact_search(max_nodes=max_nodes, dual_iters=dual_iters)
+    torch.cuda.synchronize()
+    return {"instance": "80-face pair, descriptor noise 1.0, K=16, seed %d" % seed, "free": info["n_free"],
+            "status": status, "optimum": pobj, "root_bound": root, "nodes": nodes,
+            "seconds": round(time.perf_counter() - t0, 4), "violations": c.check_primal(x)}
 
 
 def sweep_roofline(cfg, seed, iters=200, temperature=0.0, **over):
@@ -396,6 +418,10 @@ def main():
                              "seeds_reaching_1pct": sum(1 for v in ok if v["gap"] <= 1e-2),
                              "per_seed": per_seed}
         out["time_to_1pct_gap"] = gaps
+    if not (a.no_search or a.no_gap):   # a time-to-solution figure, like the gap runs
+        log("[bench] exact search, 80-face pair with noisy descriptors (noise 1.0, K = 16)")
+        out["exact_search"] = exact_search_run()
+        log(f"[bench]   {out['exact_search']}")
     if not a.no_cpu_baseline:
         log("[bench] CPU oracle baseline")
         out["cpu_baseline"] = cpu_baseline(a.config, a.seed, a.cpu_sample_iters)
