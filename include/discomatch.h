@@ -103,6 +103,42 @@ dm_status dm_knn_candidates(dm_ctx* ctx, const float* FX, int32_t nvx, const flo
                             int32_t nvy, int32_t D, int32_t K, int32_t prec, int32_t* cand_xy,
                             int32_t* cand_yx);
 
+/* Coarse-to-fine pruning (Sec. 5.2): a vertex matching found at a coarser
+ * resolution restricts the candidate pairs at the next finer one to the
+ * ring neighbourhoods of the matched vertices.  Three steps:
+ *
+ * dm_nearest_vertices: for each of the n points P (a coarse vertex's rest
+ * position) the index of the nearest of the m points Q (fine vertices):
+ * squared distances in FP64 (exact for FP32 coordinates), ties to the lower
+ * index.  P [device] float32 [n*3], Q [device] float32 [m*3], out [device]
+ * int32 [n].  Enqueue only. */
+dm_status dm_nearest_vertices(dm_ctx* ctx, const float* P, int32_t n, const float* Q, int32_t m, int32_t* out);
+
+/* dm_matched_pairs: the vertex pairs (m, n) that the selected elements of a
+ * primal x use (the corners of the product triangles with x = 1), in
+ * ascending order of m * nvY + n, on the context's product space.
+ *  x [device] uint8 [n_prod_tri]; pairs [device] int32 [cap*2] out (m, n);
+ *  *n_pairs [host] out (also when it exceeds cap, which is an error).
+ *  Synchronises. */
+dm_status dm_matched_pairs(dm_ctx* ctx, const uint8_t* x, int32_t* pairs, int32_t cap, int32_t* n_pairs);
+
+/* dm_ring_candidates: for each seed pair (a, b) of fine vertices (a coarse
+ * match placed on the fine meshes), every pair (u, v) with u in the ring
+ * neighbourhood of a on X and v in that of b on Y (rings = 1: the vertex and
+ * its neighbours; 2: also theirs) becomes a candidate; the union over the
+ * seeds is returned as per-vertex lists in ascending order, both ways,
+ * padded to the common length K by repeating the last entry (the layout of
+ * dm_knn_candidates; dm_build_product_space ignores the repeats).
+ *  Xf, Yf: the fine meshes (as for dm_build_product_space); seeds [device]
+ *  int32 [n_seeds*2]; cand_xy [device] int32 [nvX*kcap] out, cand_yx
+ *  [device] int32 [nvY*kcap] out (the first nv*K entries are used); *K
+ *  [host] out.  Errors: a seed out of range, a ring over 512 members, K >
+ *  kcap (DM_ERR_WORKSPACE, *K set), a fine vertex left without candidates
+ *  (DM_ERR_INFEASIBLE).  Synchronises. */
+dm_status dm_ring_candidates(dm_ctx* ctx, const dm_mesh* Xf, const dm_mesh* Yf, const int32_t* seeds,
+                             int32_t n_seeds, int32_t rings, int32_t kcap, int32_t* cand_xy, int32_t* cand_yx,
+                             int32_t* K);
+
 /* Product space, constraints and presolve (A1, A3; Sec. 3.1, Eq. (P)).
  * Validates both meshes, enumerates every product triangle whose three
  * product vertices (m, n) lie in the candidate set C (the union of cand_xy and

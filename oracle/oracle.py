@@ -365,3 +365,71 @@ def unpruned_count(nvx, nex, nfx, nvy, ney, nfy):
     """Closed-form size of the unpruned product space (tri-tri 3 FxFy,
     tri-edge / edge-tri 6 per pair, tri-vertex / vertex-tri 1 per pair)."""
     return 3 * nfx * nfy + 6 * (nfx * ney + nex * nfy) + nfx * nvy + nvx * nfy
+
+
+# ---------------------------------------------------------------- coarse-to-fine pruning (Sec. 5.2)
+# Plain set logic: a coarse vertex match (m, n) admits every fine pair
+# (u, v) with u in the ring neighbourhood of m's location on X and v in that
+# of n's location on Y.
+
+def nearest_vertices(P, Q):
+    """Index of the nearest point of Q for every point of P: squared
+    distances in FP64 (exact for FP32 coordinates), ties to the lower index
+    (argmin returns the first minimum)."""
+    P = np.asarray(P, np.float32).astype(np.float64)
+    Q = np.asarray(Q, np.float32).astype(np.float64)
+    out = np.empty(len(P), np.int32)
+    for i, p in enumerate(P):
+        d = Q - p
+        out[i] = int(np.argmin((d[:, 0] * d[:, 0] + d[:, 1] * d[:, 1]) + d[:, 2] * d[:, 2]))
+    return out
+
+
+def matched_pairs(pv, x, nvy):
+    """Vertex pairs (m, n) used by the elements with x = 1 (their product
+    vertices m * nvy + n), ascending."""
+    ids = np.unique(np.asarray(pv)[np.asarray(x).astype(bool)].ravel())
+    return np.stack([ids // nvy, ids % nvy], axis=1).astype(np.int32)
+
+
+def vertex_rings(F, nv, rings):
+    """Ring neighbourhood of every vertex of a closed mesh: the vertex and its
+    edge neighbours (rings = 1), and theirs (rings = 2), as sets."""
+    nb = [set() for _ in range(nv)]
+    for a, b, c in np.asarray(F):
+        for u, v in ((a, b), (b, c), (c, a)):
+            nb[u].add(int(v))
+            nb[v].add(int(u))
+    out = []
+    for v in range(nv):
+        r = {v} | nb[v]
+        if rings >= 2:
+            for u in list(nb[v]):
+                r |= nb[u]
+        out.append(r)
+    return out
+
+
+def ring_candidates(FX, nvx, FY, nvy, seeds, rings):
+    """Union over seed pairs (a, b) of ring(a) x ring(b); per-vertex lists in
+    ascending order both ways, padded to the common length K by repeating
+    the last entry.  Returns (cand_xy [nvx, K], cand_yx [nvy, K])."""
+    rx, ry = vertex_rings(FX, nvx, rings), vertex_rings(FY, nvy, rings)
+    xs = [set() for _ in range(nvx)]
+    ys = [set() for _ in range(nvy)]
+    for a, b in np.asarray(seeds):
+        for u in rx[int(a)]:
+            xs[u] |= ry[int(b)]
+        for v in ry[int(b)]:
+            ys[v] |= rx[int(a)]
+    K = max(max(len(s) for s in xs), max(len(s) for s in ys))
+
+    def lists(sets):
+        out = np.empty((len(sets), K), np.int32)
+        for i, s in enumerate(sets):
+            srt = sorted(s)
+            if not srt:
+                raise OracleError(E_INFEASIBLE)
+            out[i] = srt + [srt[-1]] * (K - len(srt))
+        return out
+    return lists(xs), lists(ys)

@@ -176,6 +176,45 @@ class Context:
         self.nvx, self.nvy = VX.shape[0], VY.shape[0]
         return self.info
 
+    # -- coarse-to-fine pruning (Sec. 5.2) ------------------------------
+    def nearest_vertices(self, P, Q):
+        """For each point of P the index of the nearest point of Q (FP64
+        squared distances, ties to the lower index)."""
+        P = _dev(P, torch.float32, self.device)
+        Q = _dev(Q, torch.float32, self.device)
+        out = torch.empty(P.shape[0], dtype=torch.int32, device=self.device)
+        self._call("dm_nearest_vertices", _ptr(P), P.shape[0], _ptr(Q), Q.shape[0], _ptr(out))
+        return out
+
+    def matched_pairs(self, x):
+        """Vertex pairs (m, n) used by the selected elements of x, as an
+        int32 [k, 2] tensor in ascending order of m * nvY + n."""
+        x = _dev(x, torch.uint8, self.device)
+        cap = 3 * max(int(x.sum().item()), 1)
+        pairs = torch.empty((cap, 2), dtype=torch.int32, device=self.device)
+        n = C.c_int32(0)
+        self._call("dm_matched_pairs", _ptr(x), _ptr(pairs), cap, C.byref(n))
+        return pairs[:n.value]
+
+    def ring_candidates(self, VX, FX, VY, FY, seeds, rings=2, kcap=512):
+        """Candidate lists of the fine meshes (VX, FX), (VY, FY) from seed
+        vertex pairs: ring(a) x ring(b) for every seed (a, b); returns
+        (cand_xy [nvX, K], cand_yx [nvY, K])."""
+        VX = _dev(VX, torch.float32, self.device)
+        VY = _dev(VY, torch.float32, self.device)
+        FX = _dev(FX, torch.int32, self.device)
+        FY = _dev(FY, torch.int32, self.device)
+        sd = _dev(seeds, torch.int32, self.device)
+        mx = dm_mesh(VX.shape[0], FX.shape[0], VX.data_ptr(), FX.data_ptr())
+        my = dm_mesh(VY.shape[0], FY.shape[0], VY.data_ptr(), FY.data_ptr())
+        cxy = torch.empty(VX.shape[0] * kcap, dtype=torch.int32, device=self.device)
+        cyx = torch.empty(VY.shape[0] * kcap, dtype=torch.int32, device=self.device)
+        K = C.c_int32(0)
+        self._call("dm_ring_candidates", C.byref(mx), C.byref(my), _ptr(sd), sd.shape[0], int(rings), int(kcap),
+                   _ptr(cxy), _ptr(cyx), C.byref(K))
+        k = K.value
+        return cxy[:VX.shape[0] * k].view(VX.shape[0], k), cyx[:VY.shape[0] * k].view(VY.shape[0], k)
+
     def get_space(self, name):
         i = self.info
         shapes = {
