@@ -91,6 +91,49 @@ class Workload:
         return out
 
 
+def c2f_run(seed=0, levels=(500, 1000, 2000, 4000), K0=32, qn_iters=60, rings=2):
+    """Coarse-to-fine pipeline (Sec. 5.2) on the pose of the 1000-face pair
+    at 500 -> 1000 -> 2000 -> 4000 faces: the coarsest level takes K0 nearest
+    candidates, every finer one the ring candidates of the previous level's
+    matching; each level runs qn_iters quasi-Newton iterations and one
+    rounding.  Wall time per level (candidates, build, costs, solve,
+    rounding), sizes and gap."""
+    import numpy as np
+    import torch
+
+    import paper_2310_08230_amd as dm
+    from synth import make_pair
+    ctx = dm.Context(0)
+    out, prev, total = [], None, 0.0
+    for F in levels:
+        p = make_pair(3, seed, faces_x=F, faces_y=F)
+        DX, DY = torch.from_numpy(p.DX).cuda(), torch.from_numpy(p.DY).cuda()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        if prev is None:
+            cxy, cyx = ctx.knn_candidates(DX, DY, K0, "fp32")
+        else:
+            pp, xp = prev
+            pairs = ctx.matched_pairs(xp)
+            mx = ctx.nearest_vertices(pp.RX.astype(np.float32), p.RX.astype(np.float32))
+            my = ctx.nearest_vertices(pp.RY.astype(np.float32), p.RY.astype(np.float32))
+            seeds = torch.stack([mx[pairs[:, 0].long()], my[pairs[:, 1].long()]], 1)
+            cxy, cyx = ctx.ring_candidates(p.VX, p.FX, p.VY, p.FY, seeds, rings=rings)
+        ctx.build_product_space(p.VX, p.FX, p.VY, p.FY, cxy, cyx)
+        ctx.build_costs(DX, DY, "fp32")
+        lam, tr = ctx.lbfgs_solve(ctx.init_lambda("fp32"), qn_iters)[:2]
+        x, pobj, feas, _ = ctx.round_primal(lam)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        total += dt
+        d = float(tr.max())
+        out.append({"faces": F, "K": int(cxy.shape[1]), "n_cand": ctx.info["n_cand"],
+                    "n_prod_tri": ctx.info["n_prod_tri"], "seconds": round(dt, 4), "feasible": feas,
+                    "gap": (pobj - d) / pobj if feas and pobj else None})
+        prev = (p, x)
+    return {"levels": out, "total_seconds": round(total, 4)}
+
+
 def exact_search_run(seed=0, max_nodes=3000, dual_iters=60):
     """Branch and bound on a pair whose LP relaxation leaves an integrality
     gap (the 80-face pair, descriptor noise 1.0, K = 16): wall time to a
@@ -418,6 +461,11 @@ def main():
                              "seeds_reaching_1pct": sum(1 for v in ok if v["gap"] <= 1e-2),
                              "per_seed": per_seed}
         out["time_to_1pct_gap"] = gaps
+    if not a.no_gap:
+        log("[bench] coarse-to-fine 500 -> 1000 -> 2000 -> 4000 faces")
+        c2f_run(a.seed, levels=(500, 1000))   # untimed: loads the kernels
+        out["coarse_to_fine"] = c2f_run(a.seed)
+        log(f"[bench]   {out['coarse_to_fine']}")
     if not (a.no_search or a.no_gap):   # a time-to-solution figure, like the gap runs
         log("[bench] exact search, 80-face pair with noisy descriptors (noise 1.0, K = 16)")
         out["exact_search"] = exact_search_run()
