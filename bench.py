@@ -362,7 +362,7 @@ def main():
     a = parse()
     if a.gpus != 1:
         print(f"bench.py runs on one GPU only; --gpus {a.gpus} is not supported "
-              "(the solver has no multi-GPU path in this build)", file=sys.stderr)
+              "(the solver runs on one GPU and has no multi-GPU path)", file=sys.stderr)
         sys.exit(2)
     import torch
     if not torch.cuda.is_available():
