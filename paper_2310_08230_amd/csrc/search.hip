@@ -246,11 +246,8 @@ dm_status search_impl(dm_ctx* ctx, const dm_search_params& P, const int8_t* base
 
 }  // namespace
 
-extern "C" dm_status dm_exact_search(dm_ctx* ctx, const dm_search_params* params, const int8_t* base_fix,
-                                     uint8_t* x, double* primal_obj, double* bound, int32_t* nodes,
-                                     int32_t* status, dm_space_info* info) {
-  if (!ctx) return DM_ERR_INVALID_ARG;
-  ctx->err.clear();
+static dm_status exact_search(dm_ctx* ctx, const dm_search_params* params, const int8_t* base_fix, uint8_t* x,
+                              double* primal_obj, double* bound, int32_t* nodes, int32_t* status) {
   if (!ctx->has_space || !ctx->has_cost) return dm_fail(ctx, DM_ERR_STATE, "dm_exact_search: build space and costs first");
   if (!params || !x || !primal_obj || !bound || !nodes || !status)
     return dm_fail(ctx, DM_ERR_INVALID_ARG, "dm_exact_search: NULL argument");
@@ -261,9 +258,16 @@ extern "C" dm_status dm_exact_search(dm_ctx* ctx, const dm_search_params* params
     return dm_fail(ctx, DM_ERR_INVALID_ARG, "dm_exact_search: message precision must be FP32 or FP64");
   DM_HIP(ctx, hipSetDevice(ctx->device));
   DM_TRY(dual_flush(ctx));
-  const dm_status s = P.round.msg_prec == DM_PREC_FP32
-                         ? search_impl<float>(ctx, P, base_fix, x, primal_obj, bound, nodes, status)
-                         : search_impl<double>(ctx, P, base_fix, x, primal_obj, bound, nodes, status);
-  if (info && ctx->has_space) fill_info(ctx, info);
+  return P.round.msg_prec == DM_PREC_FP32 ? search_impl<float>(ctx, P, base_fix, x, primal_obj, bound, nodes, status)
+                                          : search_impl<double>(ctx, P, base_fix, x, primal_obj, bound, nodes, status);
+}
+
+extern "C" dm_status dm_exact_search(dm_ctx* ctx, const dm_search_params* params, const int8_t* base_fix,
+                                     uint8_t* x, double* primal_obj, double* bound, int32_t* nodes,
+                                     int32_t* status, dm_space_info* info) {
+  if (!ctx) return DM_ERR_INVALID_ARG;
+  ctx->err.clear();
+  const dm_status s = exact_search(ctx, params, base_fix, x, primal_obj, bound, nodes, status);
+  if (info && ctx->has_space) fill_info(ctx, info);   // also after an error: the sizes in force
   return s;
 }

@@ -65,3 +65,22 @@ def test_c2f_fine_level_solves():
     used = np_(ctx.matched_pairs(xf))
     cand = set(map(tuple, np.stack([np.repeat(np.arange(len(pf.VX)), cxy.shape[1]), np_(cxy).ravel()], 1).tolist()))
     assert all(tuple(u) in cand for u in used.tolist())
+
+
+def test_c2f_errors_are_reported():
+    """Bad inputs come back as errors (checked on the host or by the
+    kernel's own range test), never as out-of-range accesses."""
+    DMError = __import__("paper_2310_08230_amd").DMError
+    pf = make_pair(3, 0, faces_x=500, faces_y=500)
+    ctx = dm().Context(0)
+    seeds = np.array([[0, 0], [5, 7]], np.int32)
+    with pytest.raises(DMError) as e:   # a capacity below the needed K
+        ctx.ring_candidates(pf.VX, pf.FX, pf.VY, pf.FY, np.stack([np.arange(252)] * 2, 1), rings=2, kcap=4)
+    assert e.value.code == -6
+    with pytest.raises(DMError):        # a seed outside the fine mesh
+        ctx.ring_candidates(pf.VX, pf.FX, pf.VY, pf.FY, np.array([[0, 10 ** 6]], np.int32), rings=1)
+    with pytest.raises(DMError) as e:   # a fine vertex left without candidates
+        ctx.ring_candidates(pf.VX, pf.FX, pf.VY, pf.FY, seeds, rings=1, kcap=64)
+    assert e.value.code == -4
+    with pytest.raises(DMError):
+        ctx.nearest_vertices(pf.RX.astype(np.float32), np.zeros((0, 3), np.float32))

@@ -84,3 +84,14 @@ def test_search_with_infeasible_fixings():
     x, pobj, bound, nodes, status = ctx.exact_search(base_fix=fix, max_nodes=50, dual_iters=20)
     assert status == "infeasible" and pobj == np.inf and not np_(x).any()
     assert ctx.info["n_free"] == free   # the problem without fixings is back
+
+
+def test_search_rejects_bad_parameters():
+    DMError = __import__("paper_2310_08230_amd").DMError
+    p = tiny_pair("tetra", "tetra", desc_noise=0.3)
+    S, ctx = both(p, 2, "fp64")
+    for kw in (dict(max_nodes=0), dict(dual_iters=0), dict(omega=0.0), dict(rel_tol=-1.0), dict(msg_prec="bf16")):
+        with pytest.raises((DMError, KeyError)):
+            ctx.exact_search(**kw)
+    x, pobj, _, _, status = ctx.exact_search(max_nodes=10, dual_iters=20)   # still usable
+    assert status == "optimal" and ctx.check_primal(x) == 0
