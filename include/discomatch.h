@@ -103,6 +103,32 @@ dm_status dm_knn_candidates(dm_ctx* ctx, const float* FX, int32_t nvx, const flo
                             int32_t nvy, int32_t D, int32_t K, int32_t prec, int32_t* cand_xy,
                             int32_t* cand_yx);
 
+/* Generic 0-1 ILPs (Appendix "Other ILPs": the solver is not specific to
+ * matching): min c^T x subject to A x = b, x in {0,1}^n, every coefficient
+ * +1 or -1, every variable in 1 to 5 rows, no variable twice with the same
+ * sign in one row.  Rows with all coefficients +1 and b = 1 are exactly-one
+ * rows of any length; the others have at most 64 entries.  A variable in
+ * d < 4 rows gets padding rows x_i - x_i = 0 (always satisfied; one for
+ * d = 2, 3, two for d = 1) so that it has 4 or 5 rows; the full row order is
+ * [other input rows | padding rows by variable | exactly-one input rows].
+ * Presolve and the reduced problem follow as for the matching ILP, and every
+ * solver entry point applies (multipliers, dual and quasi-Newton solves,
+ * bounds, rounding, fixing, exact search); the ones that need meshes,
+ * candidates or descriptor costs return DM_ERR_STATE.  Costs come from
+ * dm_set_costs.
+ *  row_ptr [device] int32 [n_rows + 1]; cols [device] int32 [nnz]; coefs
+ *  [device] int8 [nnz]; b [device] int32 [n_rows]; *info [host] out.
+ *  Synchronises. */
+dm_status dm_build_ilp(dm_ctx* ctx, int32_t n_vars, int32_t n_rows, const int32_t* row_ptr, const int32_t* cols,
+                       const int8_t* coefs, const int32_t* b, dm_space_info* info);
+
+/* Costs c [device] float64 [n_prod_tri] of the current problem (generic or
+ * matching), replacing any built ones; the offset of the variables fixed to
+ * 1 follows.  After it, dm_smoothed_backward (which differentiates the
+ * descriptor costs) is refused until dm_build_costs runs again.
+ * Errors: a non-finite cost.  Synchronises. */
+dm_status dm_set_costs(dm_ctx* ctx, const double* cost);
+
 /* Coarse-to-fine pruning (Sec. 5.2): a vertex matching found at a coarser
  * resolution restricts the candidate pairs at the next finer one to the
  * ring neighbourhoods of the matched vertices.  Three steps:

@@ -33,6 +33,8 @@ def lib():
         L.or_space_build.argtypes = [C.c_int, C.c_int, P, P, C.c_int, C.c_int, P, P, P, P,
                                      C.c_int, P]
         L.or_space_build.restype = C.c_void_p
+        L.or_ilp_build.argtypes = [C.c_int, C.c_int, P, P, P, P, P]
+        L.or_ilp_build.restype = C.c_void_p
         L.or_space_free.argtypes = [P]
         L.or_space_info.argtypes = [P, P]
         L.or_space_get.argtypes = [P, C.c_int, P]
@@ -181,6 +183,21 @@ class Space:
         self.info = self._read_info()
         self.nvx, self.nvy = len(VX), len(VY)
         self.nfx, self.nfy = len(FX), len(FY)
+
+    @classmethod
+    def from_ilp(cls, n_vars, row_ptr, cols, coefs, b):
+        """Generic 0-1 ILP with +-1 rows (CSR), padded and presolved as the
+        library does (see or_ilp_build)."""
+        S = cls.__new__(cls)
+        S._keep = [_c(row_ptr, np.int32), _c(cols, np.int32), _c(coefs, np.int32), _c(b, np.int32)]
+        rp, cl, cf, bb = S._keep
+        st = C.c_int(0)
+        S.h = lib().or_ilp_build(int(n_vars), len(rp) - 1, _p(rp), _p(cl), _p(cf), _p(bb), C.byref(st))
+        if not S.h:
+            raise OracleError(st.value)
+        S.info = S._read_info()
+        S.nvx = S.nvy = S.nfx = S.nfy = 0
+        return S
 
     def _read_info(self):
         info = np.zeros(8, np.int64)

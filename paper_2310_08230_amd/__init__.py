@@ -215,6 +215,26 @@ class Context:
         k = K.value
         return cxy[:VX.shape[0] * k].view(VX.shape[0], k), cyx[:VY.shape[0] * k].view(VY.shape[0], k)
 
+    # -- generic 0-1 ILPs ------------------------------------------------
+    def build_ilp(self, n_vars, row_ptr, cols, coefs, b):
+        """min c^T x, A x = b, x in {0,1}^n with +-1 rows given as CSR
+        (row_ptr [n_rows + 1], cols, coefs [nnz], b [n_rows])."""
+        rp = _dev(row_ptr, torch.int32, self.device)
+        cl = _dev(cols, torch.int32, self.device)
+        cf = _dev(coefs, torch.int8, self.device)
+        bb = _dev(b, torch.int32, self.device)
+        info = dm_space_info()
+        self._call("dm_build_ilp", int(n_vars), rp.shape[0] - 1, _ptr(rp), _ptr(cl) if cl.numel() else None,
+                   _ptr(cf) if cf.numel() else None, _ptr(bb) if bb.numel() else None, C.byref(info))
+        self.info = {n: getattr(info, n) for n, _ in dm_space_info._fields_}
+        self.nvx = self.nvy = 0
+        return self.info
+
+    def set_costs(self, cost):
+        """Costs of the current problem's variables (float64)."""
+        c = _dev(cost, torch.float64, self.device)
+        self._call("dm_set_costs", _ptr(c))
+
     def get_space(self, name):
         i = self.info
         shapes = {

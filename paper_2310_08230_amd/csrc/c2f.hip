@@ -177,7 +177,8 @@ extern "C" dm_status dm_matched_pairs(dm_ctx* ctx, const uint8_t* x, int32_t* pa
                                       int32_t* n_pairs) {
   if (!ctx) return DM_ERR_INVALID_ARG;
   ctx->err.clear();
-  if (!ctx->has_space) return dm_fail(ctx, DM_ERR_STATE, "dm_matched_pairs: no product space built");
+  if (!ctx->has_space || ctx->generic)
+    return dm_fail(ctx, DM_ERR_STATE, "dm_matched_pairs: needs a product space built from meshes");
   if (!x || !n_pairs || cap < 0 || (cap > 0 && !pairs))
     return dm_fail(ctx, DM_ERR_INVALID_ARG, "dm_matched_pairs: bad arguments");
   DM_HIP(ctx, hipSetDevice(ctx->device));

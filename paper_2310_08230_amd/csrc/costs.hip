@@ -142,6 +142,8 @@ extern "C" dm_status dm_build_costs(dm_ctx* ctx, const float* FX, const float* F
   if (!ctx) return DM_ERR_INVALID_ARG;
   ctx->err.clear();
   if (!ctx->has_space) return dm_fail(ctx, DM_ERR_STATE, "dm_build_costs: no product space");
+  if (ctx->generic)
+    return dm_fail(ctx, DM_ERR_STATE, "dm_build_costs: descriptor costs need a product space built from meshes");
   if (!FX || !FY || D < 1) return dm_fail(ctx, DM_ERR_INVALID_ARG, "dm_build_costs: bad descriptors");
   if (prec != DM_PREC_FP64 && prec != DM_PREC_FP32 && prec != DM_PREC_BF16)
     return dm_fail(ctx, DM_ERR_INVALID_ARG, "dm_build_costs: unknown precision %d", prec);
@@ -188,6 +190,7 @@ extern "C" dm_status dm_build_costs(dm_ctx* ctx, const float* FX, const float* F
   if (e) return dm_fail(ctx, DM_ERR_NONFINITE, "non-finite element cost");
   DM_TRY(cost_offset(ctx));   // waits for the stream
   ctx->cost_prec = prec;
+  ctx->desc_costs = true;
   ctx->has_cost = true;
   ++ctx->cost_generation;
   return DM_OK;

@@ -244,6 +244,8 @@ struct dm_ctx {
   DArr<double> scal;             // small device scalars
   DArr<double> sum_part;         // per-block partials of sum_f64
   bool corners_ready = false;    // corner_ptr / corner_list match the product space
+  bool generic = false;          // the problem came from dm_build_ilp (no meshes, no candidates)
+  bool desc_costs = false;       // the costs came from descriptors (dm_build_costs)
   int32_t* host_i32 = nullptr;   // HOST_SLOTS pinned ints: landing slots of read_i32s
   DArr<int8_t> pref;             // per variable: 1, 0 or -1
   DArr<int64_t> icount;          // integer counters

@@ -131,6 +131,8 @@ extern "C" dm_status dm_smoothed_backward(dm_ctx* ctx, const void* lambda, doubl
   if (!ctx) return DM_ERR_INVALID_ARG;
   ctx->err.clear();
   if (!ctx->has_space || !ctx->has_cost) return dm_fail(ctx, DM_ERR_STATE, "dm_smoothed_backward: build space and costs first");
+  if (ctx->generic || !ctx->desc_costs)
+    return dm_fail(ctx, DM_ERR_STATE, "dm_smoothed_backward: needs costs from descriptors (dm_build_costs)");
   if ((!lambda && ctx->nnz > 0) || !FX || !FY || !gFX || !gFY || D < 1)
     return dm_fail(ctx, DM_ERR_INVALID_ARG, "dm_smoothed_backward: bad arguments");
   if (!(temperature > 0.0)) return dm_fail(ctx, DM_ERR_INVALID_ARG, "dm_smoothed_backward: temperature must be > 0");

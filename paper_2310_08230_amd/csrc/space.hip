@@ -843,7 +843,8 @@ dm_status presolve_reduce(dm_ctx* ctx, const int8_t* fix) {
       if (nc > 0)
         k_presolve_rows<<<grid_for(nc, 128), 128, 0, st>>>(ctx->row_ptr.p, ctx->ent_var.p, ctx->ent_coef.p,
                                                            ctx->row_b.p, nc, ctx->state.p, force.p, fl, prev);
-      k_presolve_proj<<<unsigned(nrows - nc), 256, 0, st>>>(ctx->row_ptr.p, ctx->ent_var.p, nc, ctx->state.p,
+      if (nrows > nc)
+        k_presolve_proj<<<unsigned(nrows - nc), 256, 0, st>>>(ctx->row_ptr.p, ctx->ent_var.p, nc, ctx->state.p,
                                                             force.p, fl, prev);
       k_presolve_vars<<<grid_for(nP, 256), 256, 0, st>>>(nP, ctx->state.p, force.p, fl, prev);
     }
@@ -897,7 +898,8 @@ dm_status presolve_reduce(dm_ctx* ctx, const int8_t* fix) {
     k_row_residual<<<grid_for(nc, 128), 128, 0, st>>>(ctx->row_ptr.p, ctx->ent_var.p, ctx->ent_coef.p,
                                                       ctx->row_b.p, nc, ctx->state.p, nfr.p, resid.p, keep.p,
                                                       err.p);
-  k_row_residual_proj<<<unsigned(nrows - nc), 256, 0, st>>>(ctx->row_ptr.p, ctx->ent_var.p, nc, ctx->state.p,
+  if (nrows > nc)
+    k_row_residual_proj<<<unsigned(nrows - nc), 256, 0, st>>>(ctx->row_ptr.p, ctx->ent_var.p, nc, ctx->state.p,
                                                             nfr.p, resid.p, keep.p, err.p);
   DM_LAUNCH_CHECK(ctx);
   DM_TRY(scan_u8(ctx, keep.p, new_id.p, size_t(nrows)));
@@ -927,7 +929,8 @@ dm_status presolve_reduce(dm_ctx* ctx, const int8_t* fix) {
         ctx->row_ptr.p, ctx->ent_var.p, ctx->ent_coef.p, ctx->ent_slot.p, nc, ctx->state.p, ctx->var_red.p,
         ctx->code.p, ctx->free_var.p, keep.p, new_id.p, cnt_excl.p, resid.p, ctx->rrow_orig.p, ctx->rrow_ptr.p,
         ctx->rrow_b.p, ctx->rent_var.p, ctx->rent_coef.p, ctx->rent_word.p);
-  k_reduced_fill_proj<<<unsigned(nrows - nc), 256, 0, st>>>(
+  if (nrows > nc)
+    k_reduced_fill_proj<<<unsigned(nrows - nc), 256, 0, st>>>(
       ctx->row_ptr.p, ctx->ent_var.p, ctx->ent_slot.p, nc, ctx->state.p, ctx->var_red.p, ctx->code.p, keep.p,
       new_id.p, cnt_excl.p, resid.p, ctx->rrow_orig.p, ctx->rrow_ptr.p, ctx->rrow_b.p, ctx->rent_var.p,
       ctx->rent_coef.p, ctx->rent_word.p);
@@ -1012,6 +1015,7 @@ extern "C" dm_status dm_build_product_space(dm_ctx* ctx, const dm_mesh* Xin, con
   ctx->has_space = false;
   ctx->corners_ready = false;
   ctx->has_cost = false;
+  ctx->generic = false;
   if (!Xin || !Yin || !cand_xy || !cand_yx || !info)
     return dm_fail(ctx, DM_ERR_INVALID_ARG, "dm_build_product_space: NULL argument");
   DM_HIP(ctx, hipSetDevice(ctx->device));
