@@ -134,6 +134,43 @@ def c2f_run(seed=0, levels=(500, 1000, 2000, 4000), K0=32, qn_iters=60, rings=2)
     return {"levels": out, "total_seconds": round(total, 4)}
 
 
+def generic_ilp_run(n=200, n_side=4000, seed=0, iters=500, search_n=20, search_side=60):
+    """Generic 0-1 ILP path: an n x n assignment with n_side random +-1 side
+    rows (planted feasible), FP32 Jacobi iterations per second and the bound
+    reached; then the exact search to a proved optimum on a 20 x 20 instance
+    with 60 side rows."""
+    import torch
+
+    import paper_2310_08230_amd as dm
+    from synth import generic_ilp
+    ctx = dm.Context(0)
+    nv, rp, cols, coefs, b, c = generic_ilp(n, n_side, seed)
+    info = ctx.build_ilp(nv, rp, cols, coefs, b)
+    ctx.set_costs(torch.from_numpy(c))
+    lam = ctx.init_lambda("fp32")
+    ctx.dual_solve(lam, 20, 0.5, trace=False)   # untimed: loads the kernels
+    lam = ctx.init_lambda("fp32")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    lam, tr = ctx.dual_solve(lam, iters, 0.5)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    out = {"instance": f"{n}x{n} assignment + {n_side} +-1 side rows, seed {seed}", "n_vars": nv,
+           "rows": info["n_rows"], "nnz": info["nnz"], "jacobi_iters_per_s": round(iters / dt, 1),
+           "bound": float(tr.max())}
+    nv, rp, cols, coefs, b, c = generic_ilp(search_n, search_side, seed + 1)
+    ctx.build_ilp(nv, rp, cols, coefs, b)
+    ctx.set_costs(torch.from_numpy(c))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    x, pobj, bound, nodes, status = ctx.exact_search(max_nodes=3000, dual_iters=60)
+    torch.cuda.synchronize()
+    out["exact_search"] = {"instance": f"{search_n}x{search_n} assignment + {search_side} side rows",
+                           "status": status, "optimum": pobj, "nodes": nodes,
+                           "seconds": round(time.perf_counter() - t0, 4)}
+    return out
+
+
 def exact_search_run(seed=0, max_nodes=3000, dual_iters=60):
     """Branch and bound on a pair whose LP relaxation leaves an integrality
     gap (the 80-face pair, descriptor noise 1.0, K = 16): wall time to a
@@ -466,6 +503,10 @@ def main():
         c2f_run(a.seed, levels=(500, 1000))   # untimed: loads the kernels
         out["coarse_to_fine"] = c2f_run(a.seed)
         log(f"[bench]   {out['coarse_to_fine']}")
+    if not a.no_gap:
+        log("[bench] generic 0-1 ILP (assignment + side rows)")
+        out["generic_ilp"] = generic_ilp_run(seed=a.seed)
+        log(f"[bench]   {out['generic_ilp']}")
     if not (a.no_search or a.no_gap):   # a time-to-solution figure, like the gap runs
         log("[bench] exact search, 80-face pair with noisy descriptors (noise 1.0, K = 16)")
         out["exact_search"] = exact_search_run()

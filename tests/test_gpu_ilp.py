@@ -7,7 +7,8 @@ import pytest
 import torch
 
 from gpu_common import dm, np_, rel_err, say
-from helpers import generic_ilp, milp_optimum
+from helpers import milp_optimum
+from synth import generic_ilp
 from oracle import oracle as O
 
 pytestmark = pytest.mark.gpu

@@ -4,7 +4,8 @@ independent assignment solver."""
 import numpy as np
 import pytest
 
-from helpers import enumerate_ilp, generic_ilp, milp_optimum, reduced_rows
+from helpers import enumerate_ilp, milp_optimum, reduced_rows
+from synth import generic_ilp
 from oracle import oracle as O
 
 
