@@ -75,3 +75,17 @@ def test_ilp_errors_and_refused_calls():
         with pytest.raises(DMError):
             call()
     assert ctx.check_primal(x) > 0   # still usable afterwards
+
+
+def test_ilp_smoothed_dual_parity():
+    """The smoothed dual on a generic ILP (padding rows run in the 8-lane
+    soft segments, side rows up to 16 lanes, assignment rows on the
+    exactly-one path)."""
+    S, ctx, _ = _both(20, 60, 1)
+    T = 0.1
+    r0 = S.lower_bound(S.init_lambda(), T)
+    assert abs(ctx.lower_bound(ctx.init_lambda("fp64"), T) - r0) <= 1e-13 * max(1.0, abs(r0))
+    lam, tr = ctx.dual_solve(ctx.init_lambda("fp64"), 20, 0.5, T)
+    rlam, rtr = S.dual_solve(20, T=T)
+    say(f"  smoothed: bound rel err {rel_err(np_(tr), rtr):.2e}")
+    assert rel_err(np_(tr), rtr) <= 1e-10
