@@ -129,3 +129,49 @@ def test_knn_candidates(cfg, prec):
             near_ties += 1
     say(f"  {prec} candidate sets differing at near ties: {near_ties}")
     assert near_ties <= (2 if prec == "fp32" else 0.2 * (len(p.DX) + len(p.DY)))
+
+
+def _bf16_rne(a):
+    """Round float32 values to bfloat16 (round to nearest, ties to even),
+    returned as float32: the inputs the BF16 distance products see."""
+    u = np.ascontiguousarray(a, np.float32).view(np.uint32).astype(np.uint64)
+    u = (u + (((u >> 16) & 1) + 0x7FFF)) & 0xFFFF0000
+    return u.astype(np.uint32).view(np.float32)
+
+
+@pytest.mark.parametrize("case", ["cfg2", "cfg3", "d16", "d72", "d200"])
+def test_knn_bf16_matches_rounded_inputs(case):
+    """BF16 candidates against the oracle run on the same BF16-rounded
+    descriptors: products of BF16 values are exact in FP32, so the candidate
+    sets may differ only where the K-th and (K+1)-th squared distances lie
+    within the FP32 accumulation error (D terms, norms included).  The custom
+    widths cover the distance kernel's K loop with a remainder only (16), one
+    64-wide group plus a remainder (72) and three groups plus a remainder
+    (200), on side lengths that leave ragged 64-row tiles."""
+    if case.startswith("cfg"):
+        p = make_pair(int(case[3:]), 0)
+        DX, DY, K = p.DX, p.DY, p.spec.k
+    else:
+        rng = np.random.default_rng(17)
+        D = int(case[1:])
+        DX = rng.standard_normal((300, D)).astype(np.float32)
+        DY = rng.standard_normal((261, D)).astype(np.float32)
+        K = 8
+    ctx = dm().Context(0)
+    cxy, cyx = ctx.knn_candidates(torch.from_numpy(DX), torch.from_numpy(DY), K, "bf16")
+    BX, BY = _bf16_rne(DX), _bf16_rne(DY)
+    rxy, ryx = O.knn(BX, BY, K)
+    bx, by = BX.astype(np.float64), BY.astype(np.float64)
+    D2 = (bx ** 2).sum(1)[:, None] + (by ** 2).sum(1)[None] - 2.0 * bx @ by.T
+    nx, ny = (bx ** 2).sum(1), (by ** 2).sum(1)
+    eps = 4.0 * bx.shape[1] * 2.0 ** -24
+    differ = 0
+    for G, R, Dm, nq, nc in [(np_(cxy), rxy, D2, nx, ny), (np_(cyx), ryx, D2.T, ny, nx)]:
+        for q in range(len(G)):
+            if set(G[q]) == set(R[q]):
+                continue
+            srt = np.sort(Dm[q])
+            assert srt[K] - srt[K - 1] <= eps * (nq[q] + nc.max()), (case, q, srt[K - 1], srt[K])
+            differ += 1
+    say(f"  {case}: candidate sets differing at FP32 near ties: {differ} of {len(DX) + len(DY)}")
+    assert differ <= 0.02 * (len(DX) + len(DY))
