@@ -116,9 +116,14 @@ dm_status dm_knn_candidates(dm_ctx* ctx, const float* FX, int32_t nvx, const flo
  * bounds, rounding, fixing, exact search); the ones that need meshes,
  * candidates or descriptor costs return DM_ERR_STATE.  Costs come from
  * dm_set_costs.
- *  row_ptr [device] int32 [n_rows + 1]; cols [device] int32 [nnz]; coefs
- *  [device] int8 [nnz]; b [device] int32 [n_rows]; *info [host] out.
- *  Synchronises. */
+ *  row_ptr [device] int32 [n_rows + 1], starting at 0 and never decreasing,
+ *  nnz = row_ptr[n_rows]; cols [device] int32 [nnz]; coefs [device] int8
+ *  [nnz]; b [device] int32 [n_rows]; *info [host] out.
+ *  Errors: DM_ERR_INVALID_ARG for malformed row pointers, a column out of
+ *  range, a coefficient other than +-1, a variable in no row or in more
+ *  than 5, or a variable twice in one row; DM_ERR_WORKSPACE for a row that
+ *  is not exactly-one with more than 64 entries; DM_ERR_INFEASIBLE when
+ *  presolve proves A x = b has no 0-1 solution.  Synchronises. */
 dm_status dm_build_ilp(dm_ctx* ctx, int32_t n_vars, int32_t n_rows, const int32_t* row_ptr, const int32_t* cols,
                        const int8_t* coefs, const int32_t* b, dm_space_info* info);
 

@@ -21,14 +21,25 @@
 
 namespace {
 
-constexpr int ERR_COEF = 1, ERR_COL = 2, ERR_LONG = 4, ERR_DEG = 8, ERR_DUP = 16, ERR_NONFINITE = 32;
+constexpr int ERR_COEF = 1, ERR_COL = 2, ERR_LONG = 4, ERR_DEG = 8, ERR_DUP = 16, ERR_NONFINITE = 32,
+              ERR_PTR = 64;
 
+// Every thread checks its own row's pointers (0 <= start <= end <= total, the
+// first start 0) before it reads an entry, so malformed row pointers are
+// reported and never index outside the total entries.
 __global__ void k_ilp_rows(const int32_t* row_ptr, const int32_t* cols, const int8_t* coefs, const int32_t* b,
-                           int32_t n_rows, int32_t n_vars, uint8_t* is_long, uint8_t* is_short, int32_t* len,
-                           int32_t* deg, int* err) {
+                           int32_t n_rows, int32_t n_vars, int32_t total, uint8_t* is_long, uint8_t* is_short,
+                           int32_t* len, int32_t* deg, int* err) {
   const int32_t j = int32_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (j >= n_rows) return;
   const int32_t s = row_ptr[j], e = row_ptr[j + 1];
+  if (s < 0 || e < s || e > total || (j == 0 && s != 0)) {
+    atomicOr(err, ERR_PTR);
+    is_long[j] = 0;
+    is_short[j] = 0;
+    len[j] = 0;
+    return;
+  }
   bool all_pos = true;
   int bad = 0;
   for (int32_t i = s; i < e; ++i) {
@@ -154,8 +165,8 @@ __global__ void k_set_cost(const double* c, int64_t n, double* c64, float* c32, 
   c32[p] = float(v);
 }
 
-dm_status build_ilp(dm_ctx* ctx, int32_t n_vars, int32_t n_rows, const int32_t* row_ptr, const int32_t* cols,
-                    const int8_t* coefs, const int32_t* b) {
+dm_status build_ilp(dm_ctx* ctx, int32_t n_vars, int32_t n_rows, int32_t total, const int32_t* row_ptr,
+                    const int32_t* cols, const int8_t* coefs, const int32_t* b) {
   hipStream_t st = ctx->stream;
   DArr<uint8_t> is_long, is_short;
   DArr<int32_t> len, deg, pad, pos_short, pos_long, pos_pad, new_row;
@@ -173,8 +184,8 @@ dm_status build_ilp(dm_ctx* ctx, int32_t n_vars, int32_t n_rows, const int32_t* 
   DM_HIP(ctx, hipMemsetAsync(deg.p, 0, sizeof(int32_t) * n_vars, st));
   DM_HIP(ctx, hipMemsetAsync(err.p, 0, sizeof(int), st));
   if (n_rows > 0)
-    k_ilp_rows<<<grid_for(n_rows, 256), 256, 0, st>>>(row_ptr, cols, coefs, b, n_rows, n_vars, is_long.p,
-                                                       is_short.p, len.p, deg.p, err.p);
+    k_ilp_rows<<<grid_for(n_rows, 256), 256, 0, st>>>(row_ptr, cols, coefs, b, n_rows, n_vars, total,
+                                                       is_long.p, is_short.p, len.p, deg.p, err.p);
   k_ilp_pad<<<grid_for(n_vars, 256), 256, 0, st>>>(deg.p, n_vars, pad.p, err.p);
   DM_LAUNCH_CHECK(ctx);
   DM_TRY(scan_u8(ctx, is_short.p, pos_short.p, size_t(n_rows)));
@@ -185,6 +196,9 @@ dm_status build_ilp(dm_ctx* ctx, int32_t n_vars, int32_t n_rows, const int32_t* 
     const int32_t* src[3] = {err.p, pos_short.p + n_rows, pos_pad.p + n_vars};
     DM_TRY(read_i32s(ctx, 3, src, v));
   }
+  if (v[0] & ERR_PTR)
+    return dm_fail(ctx, DM_ERR_INVALID_ARG,
+                   "dm_build_ilp: row pointers must start at 0, never decrease and end at the entry count");
   if (v[0] & ERR_COEF) return dm_fail(ctx, DM_ERR_INVALID_ARG, "dm_build_ilp: a coefficient is not +1 or -1");
   if (v[0] & ERR_COL) return dm_fail(ctx, DM_ERR_INVALID_ARG, "dm_build_ilp: a column is out of range");
   if (v[0] & ERR_LONG)
@@ -270,7 +284,7 @@ extern "C" dm_status dm_build_ilp(dm_ctx* ctx, int32_t n_vars, int32_t n_rows, c
   DM_TRY(read_i32(ctx, row_ptr + n_rows, &total));
   if (total < 0 || (total > 0 && (!cols || !coefs)))
     return dm_fail(ctx, DM_ERR_INVALID_ARG, "dm_build_ilp: bad row pointers or entries");
-  DM_TRY(build_ilp(ctx, n_vars, n_rows, row_ptr, cols, coefs, b));
+  DM_TRY(build_ilp(ctx, n_vars, n_rows, total, row_ptr, cols, coefs, b));
   ctx->has_space = true;
   fill_info(ctx, info);
   return DM_OK;

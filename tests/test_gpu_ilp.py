@@ -68,6 +68,15 @@ def test_ilp_errors_and_refused_calls():
         ctx.build_ilp(2, rp, np.array([0, 0]), np.array([1, 1]), np.array([1]))
     with pytest.raises(DMError):   # variable 1 in no row
         ctx.build_ilp(2, np.array([0, 1], np.int32), np.array([0]), np.array([1]), np.array([1]))
+    # malformed row pointers (chosen so that every entry a row names is
+    # still inside the arrays passed): not starting at 0, decreasing, and a
+    # row ending past the entry count row_ptr[n_rows]
+    for bad_rp, n_ent in (([1, 2], 2), ([0, 2, 1], 2), ([0, 3, 2], 3)):
+        with pytest.raises(DMError, match="row pointers"):
+            ctx.build_ilp(2, np.array(bad_rp, np.int32), np.arange(n_ent) % 2, np.ones(n_ent),
+                          np.ones(len(bad_rp) - 1))
+    ctx.build_ilp(2, rp, np.array([0, 1]), np.array([1, 1]), np.array([1]))   # usable afterwards
+    assert ctx.info["n_prod_tri"] == 2
     S, ctx, _ = _both(8, 10, 0)
     x = torch.zeros(ctx.info["n_prod_tri"], dtype=torch.uint8, device="cuda")
     for call in (lambda: ctx.matched_pairs(x), lambda: ctx.get_space("pv"),
