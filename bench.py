@@ -315,7 +315,23 @@ def cpu_baseline(cfg, seed, iters):
     dt = time.perf_counter() - t0
     return {"value": iters / dt, "unit": "dual iterations/s", "cores": 1, "kind": "oracle",
             "sample": f"FP64 oracle, same pair (config {cfg}, seed {seed}): candidates, product space, "
-                      f"presolve, costs and {iters} Jacobi iterations in {dt:.1f} s"}
+                      f"presolve, costs and {iters} Jacobi iterations in {dt:.1f} s",
+            "host": host_cpu()}
+
+
+def host_cpu():
+    """CPU model of this host and the cores this process may run on (the
+    oracle itself is single-threaded, built -O2 -ffp-contract=off)."""
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"cpu_model": model, "cores_available": len(os.sched_getaffinity(0))}
 
 
 def copy_calibration(nbytes, reps=5):

@@ -106,7 +106,7 @@ def test_smoothed_bound_autograd_config4_shape():
     L = dm().SmoothedBound.apply(DX, DY, ctx, 20, 0.1, 0.5, "bf16")
     L.backward()
     assert DX.grad.shape == (len(p.DX), 128) and torch.isfinite(DX.grad).all() and torch.isfinite(DY.grad).all()
-    say(f"  L_T={float(L):.6f} |dL/dFX|max={float(DX.grad.abs().max()):.3e}")
+    say(f"  L_T={float(L.detach()):.6f} |dL/dFX|max={float(DX.grad.abs().max()):.3e}")
 
 
 @pytest.mark.parametrize("prec,tol0,tol_lam,tol_grad", [("fp64", 1e-13, 1e-11, 1e-6), ("fp32", 1e-6, 1e-4, 1e-3)])
