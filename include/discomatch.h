@@ -81,7 +81,11 @@ typedef struct {
  * (a hipStream_t, may be NULL for the default stream).  The context's device
  * memory is allocated and freed stream-ordered on that stream (the device's
  * default memory pool, set to keep freed memory for reuse), so the stream
- * must stay valid until dm_destroy. */
+ * must stay valid until dm_destroy.  The release threshold is a property of
+ * that pool for the whole process: memory freed to it stays reserved for
+ * later stream-ordered allocations (of this library or any other user of
+ * the default pool) until the process ends or the pool is trimmed
+ * (hipMemPoolTrimTo); PyTorch's caching allocator does not draw from it. */
 dm_status dm_create(int32_t device, void* hip_stream, dm_ctx** out);
 dm_status dm_destroy(dm_ctx* ctx);
 /* Message of the last error on ctx (empty string if none); owned by ctx. */
