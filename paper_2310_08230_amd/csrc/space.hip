@@ -519,29 +519,48 @@ __global__ void k_var_deg(const int32_t* free_var, const int32_t* code, int64_t 
 }
 
 // flags[2]: longest short row; flags[3] bit 1: a row with < 2 entries, bit 0:
-// a projection row that is not exactly-one (one atomic per wave each)
-__global__ void k_row_stats(const int32_t* rrow_ptr, const int32_t* rrow_b, const int8_t* rent_coef,
-                            int64_t n_short, int64_t n_rows, int* flags) {
+// a projection row that is not exactly-one.  One update per block at most:
+// the block's maximum goes to flags[2] only while it exceeds what is stored
+// there (a maximum only grows, so a block that reads a value at least as
+// large has nothing to add), since one atomic per wave on that one word
+// serialised the kernel on large problems
+__global__ void k_row_stats(const int32_t* rrow_ptr, const int32_t* rrow_b, int64_t n_short, int64_t n_rows,
+                            int* flags) {
   // no early return: every lane of the wave takes part in the reductions
   const int64_t j = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   const bool in = j < n_rows;
   const int32_t len = in ? rrow_ptr[j + 1] - rrow_ptr[j] : 2;
   int32_t short_len = 0;
   bool bad_proj = false;
-  if (in && j < n_short) {
-    short_len = len;
-  } else if (in) {
-    bool ok = rrow_b[j] == 1;
-    for (int32_t i = rrow_ptr[j]; i < rrow_ptr[j + 1]; ++i) ok = ok && rent_coef[i] == 1;
-    bad_proj = !ok;
-  }
+  if (in && j < n_short) short_len = len;
+  else if (in) bad_proj = rrow_b[j] != 1;   // coefficients: k_long_coefs
+  __shared__ int wmax[4], wbits[4];
   for (int o = 32; o > 0; o >>= 1) short_len = max(short_len, __shfl_xor(short_len, o));
-  if ((threadIdx.x & 63) == 0 && short_len > 0) atomicMax(&flags[2], short_len);
   const unsigned long long few = __ballot(len < 2), bad = __ballot(bad_proj);
+  const int wave = threadIdx.x >> 6;
   if ((threadIdx.x & 63) == 0) {
-    if (few) atomicOr(&flags[3], 2);   // presolve leaves >= 2 free entries per row
-    if (bad) atomicOr(&flags[3], 1);
+    wmax[wave] = short_len;
+    wbits[wave] = (few ? 2 : 0) | (bad ? 1 : 0);   // presolve leaves >= 2 free entries per row
   }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const int m = max(max(wmax[0], wmax[1]), max(wmax[2], wmax[3]));
+    const int bits = wbits[0] | wbits[1] | wbits[2] | wbits[3];
+    if (m > 0 && m > __hip_atomic_load(&flags[2], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
+      atomicMax(&flags[2], m);
+    if (bits) atomicOr(&flags[3], bits);
+  }
+}
+
+// every coefficient of a projection (exactly-one) row must be +1; those rows
+// hold the entries from rrow_ptr[n_short] on, checked one entry per thread
+__global__ void k_long_coefs(const int32_t* rrow_ptr, int64_t n_short, int64_t nnz, const int8_t* coef,
+                             int* flags) {
+  // no early return: every lane of the wave takes part in the ballot
+  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  const int64_t start = rrow_ptr[n_short];
+  const bool bad = i >= start && i < nnz && coef[i] != 1;
+  if (__ballot(bad) && (threadIdx.x & 63) == 0) atomicOr(&flags[3], 1);
 }
 
 __global__ void k_row_len(const int32_t* rrow_ptr, int64_t n_short, uint32_t* len, int32_t* row) {
@@ -941,8 +960,9 @@ dm_status presolve_reduce(dm_ctx* ctx, const int8_t* fix) {
     k_var_deg<<<grid_for(nfree, 256), 256, 0, st>>>(ctx->free_var.p, ctx->code.p, nfree, ctx->var_deg.p);
   DM_HIP(ctx, hipMemsetAsync(err.p, 0, 4 * sizeof(int), st));
   if (nr > 0)
-    k_row_stats<<<grid_for(nr, 256), 256, 0, st>>>(ctx->rrow_ptr.p, ctx->rrow_b.p, ctx->rent_coef.p, nshort,
-                                                   nr, err.p);
+    k_row_stats<<<grid_for(nr, 256), 256, 0, st>>>(ctx->rrow_ptr.p, ctx->rrow_b.p, nshort, nr, err.p);
+  if (rnnz > 0)
+    k_long_coefs<<<grid_for(rnnz, 256), 256, 0, st>>>(ctx->rrow_ptr.p, nshort, rnnz, ctx->rent_coef.p, err.p);
   DM_LAUNCH_CHECK(ctx);
   int stats[4];
   DM_HIP(ctx, hipMemcpyAsync(stats, err.p, sizeof(stats), hipMemcpyDeviceToHost, st));
