@@ -441,12 +441,16 @@ def main():
     c = w.ctx
     lam = c.init_lambda(w.msg)
     c.dual_solve(lam, 20, w.spec.omega, w.spec.temperature, trace=False)
-    c.timing(True)
+    # the solve alone (bound trace on, no per-launch events): iterations/s
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     c.dual_solve(lam, w.iters, w.spec.omega, w.spec.temperature)
     torch.cuda.synchronize()
     solve_s = time.perf_counter() - t1
+    # the same solve with start/stop events around every sweep launch
+    c.timing(True)
+    c.dual_solve(lam, w.iters, w.spec.omega, w.spec.temperature)
+    torch.cuda.synchronize()
     c.timing(False)
     n_launch, tot_ms = c.timing_read()
     avg_s = tot_ms / 1e3 / max(n_launch, 1)
