@@ -167,8 +167,7 @@ extern "C" dm_status dm_build_costs(dm_ctx* ctx, const float* FX, const float* F
                                                         ctx->X.area.p, ctx->Y.area.p, w.p, ctx->pair_d.p,
                                                         ctx->pair_a.p);
   } else {
-    DM_TRY(check_finite(ctx, FX, int64_t(nvx) * D));
-    DM_TRY(check_finite(ctx, FY, int64_t(nvy) * D));
+    DM_TRY(check_finite(ctx, FX, int64_t(nvx) * D, FY, int64_t(nvy) * D));
     if (prec == DM_PREC_FP64)
       k_pair_w64<<<grid_for(nC, 256), 256, 0, st>>>(ctx->cpair.p, nC, nvy, FX, FY, D, ctx->X.area.p,
                                                     ctx->Y.area.p, w.p, ctx->pair_d.p, ctx->pair_a.p);

@@ -289,7 +289,7 @@ dm_status sum_f64(dm_ctx* ctx, const double* a, int64_t n, const void* sel, int 
 dm_status read_i32(dm_ctx* ctx, const int32_t* dev, int32_t* host);
 // n (<= HOST_SLOTS) device ints into host[0..n) with one wait for the stream
 dm_status read_i32s(dm_ctx* ctx, int n, const int32_t* const* dev, int32_t* host);
-dm_status check_finite(dm_ctx* ctx, const float* a, int64_t n);
+dm_status check_finite(dm_ctx* ctx, const float* a, int64_t na, const float* b, int64_t nb);
 dm_status dual_flush(dm_ctx* ctx);  // write the bound of the last sweep launch
 dm_status cost_offset(dm_ctx* ctx);   // offset = summed costs of elements fixed to 1 (synchronises)
 dm_status corner_lists(dm_ctx* ctx);  // corners per candidate pair (built once per product space)

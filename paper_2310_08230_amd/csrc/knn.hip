@@ -138,11 +138,13 @@ __global__ __launch_bounds__(256) void k_topk(const float* d2, int32_t nvx, int3
 
 }  // namespace
 
-dm_status check_finite(dm_ctx* ctx, const float* a, int64_t n) {
+// both descriptor arrays flag one word, read back once
+dm_status check_finite(dm_ctx* ctx, const float* a, int64_t na, const float* b, int64_t nb) {
   DArr<int> err;
   DM_ALLOC(ctx, err, 1);
   DM_HIP(ctx, hipMemsetAsync(err.p, 0, sizeof(int), ctx->stream));
-  if (n > 0) k_nonfinite<<<grid_for(n, 256), 256, 0, ctx->stream>>>(a, n, err.p);
+  if (na > 0) k_nonfinite<<<grid_for(na, 256), 256, 0, ctx->stream>>>(a, na, err.p);
+  if (nb > 0) k_nonfinite<<<grid_for(nb, 256), 256, 0, ctx->stream>>>(b, nb, err.p);
   DM_LAUNCH_CHECK(ctx);
   int e = 0;
   DM_TRY(read_i32(ctx, err.p, &e));
@@ -153,8 +155,7 @@ dm_status check_finite(dm_ctx* ctx, const float* a, int64_t n) {
 dm_status knn_distances(dm_ctx* ctx, const float* FX, int32_t nvx, const float* FY, int32_t nvy,
                         int32_t D, int32_t prec, float* d2) {
   hipStream_t st = ctx->stream;
-  DM_TRY(check_finite(ctx, FX, int64_t(nvx) * D));
-  DM_TRY(check_finite(ctx, FY, int64_t(nvy) * D));
+  DM_TRY(check_finite(ctx, FX, int64_t(nvx) * D, FY, int64_t(nvy) * D));
   if (prec == DM_PREC_BF16) {
     const int32_t Dp = (D + 7) / 8 * 8;
     const int32_t nxp = (nvx + 63) / 64 * 64, nyp = (nvy + 63) / 64 * 64;

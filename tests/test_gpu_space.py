@@ -107,6 +107,31 @@ def test_errors():
     assert e.value.code == -1
 
 
+def test_nonfinite_descriptors_are_rejected():
+    """A NaN or an infinity in either shape's descriptors is reported as
+    DM_ERR_NONFINITE by the candidate and cost builders in every precision,
+    and the context stays usable."""
+    p = make_pair(1, 0)
+    DX, DY = torch.from_numpy(p.DX), torch.from_numpy(p.DY)
+    ctx = dm().Context(0)
+    cxy, cyx = O.knn(p.DX, p.DY, 6)
+    ctx.build_product_space(p.VX, p.FX, p.VY, p.FY, cxy, cyx)
+    for side, val in (("X", float("nan")), ("Y", float("inf")), ("Y", float("nan"))):
+        bx, by = DX.clone(), DY.clone()
+        (bx if side == "X" else by)[len(bx if side == "X" else by) - 1, 3] = val
+        for prec in ("fp32", "bf16"):
+            with pytest.raises(dm().DMError) as e:
+                ctx.knn_candidates(bx, by, 6, prec)
+            assert e.value.code == -5, (side, prec)
+        for prec in ("fp64", "fp32", "bf16"):
+            with pytest.raises(dm().DMError) as e:
+                ctx.build_costs(bx, by, prec)
+            assert e.value.code == -5, (side, prec)
+    gx, gy = ctx.knn_candidates(DX, DY, 6, "fp32")
+    assert np.array_equal(np_(gx), cxy) and np.array_equal(np_(gy), cyx)
+    ctx.build_costs(DX, DY, "fp64")
+
+
 @pytest.mark.parametrize("cfg,prec", [(1, "fp32"), (2, "fp32"), (2, "bf16"), (3, "bf16")])
 def test_knn_candidates(cfg, prec):
     p = make_pair(cfg, 0)
