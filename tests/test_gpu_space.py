@@ -107,6 +107,35 @@ def test_errors():
     assert e.value.code == -1
 
 
+def test_mesh_errors_name_the_first_fault():
+    """Malformed meshes are rejected with the fault named, in a fixed order
+    (non-finite vertex, index out of range, repeated vertex, orientation),
+    also where one mesh has several faults; the context stays usable."""
+    V, F = meshes.icosahedron()
+    cxy, cyx, _ = full_candidates(12, 12)
+    ctx = dm().Context(0)
+    out_of_range = F.copy()
+    out_of_range[3, 1] = 12
+    repeated = F.copy()
+    repeated[5, 2] = repeated[5, 0]
+    both_faults = out_of_range.copy()
+    both_faults[7] = both_faults[7][[0, 2, 1]]   # also flipped
+    nan_v = V.copy()
+    nan_v[4, 1] = np.nan
+    cases = [(V, out_of_range, -2, "out of range"), (V, repeated, -2, "repeats a vertex"),
+             (V, both_faults, -2, "out of range"), (nan_v, F, -5, "non-finite vertex"),
+             (nan_v, both_faults, -5, "non-finite vertex")]
+    for Vb, Fb, code, msg in cases:
+        with pytest.raises(dm().DMError, match=msg) as e:
+            ctx.build_product_space(Vb, Fb, V, F, cxy, cyx)
+        assert e.value.code == code, msg
+        with pytest.raises(dm().DMError, match=msg):
+            ctx.build_product_space(V, F, Vb, Fb, cxy, cyx)
+    S = O.Space(V, F, V, F, cxy, cyx)
+    ctx.build_product_space(V, F, V, F, cxy, cyx)
+    assert ctx.info["n_prod_tri"] == S.info["nP"]
+
+
 def test_nonfinite_descriptors_are_rejected():
     """A NaN or an infinity in either shape's descriptors is reported as
     DM_ERR_NONFINITE by the candidate and cost builders in every precision,
