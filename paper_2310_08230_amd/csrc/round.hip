@@ -98,16 +98,23 @@ __global__ void k_perturb(const int8_t* pref, int64_t nfree, double delta, uint6
 
 }  // namespace
 
-dm_status count_violations(dm_ctx* ctx, const uint8_t* x, int64_t* out) {
+// violated rows of x into icount[1] (enqueued only)
+static dm_status enqueue_violations(dm_ctx* ctx, const uint8_t* x) {
   DM_ALLOC(ctx, ctx->icount, 4);
   DM_HIP(ctx, hipMemsetAsync(ctx->icount.p + 1, 0, sizeof(int64_t), ctx->stream));
   const int64_t nc = ctx->n_closed_full;
   if (nc > 0)
     k_violations<<<grid_for(nc, 256), 256, 0, ctx->stream>>>(ctx->row_ptr.p, ctx->ent_var.p, ctx->ent_coef.p,
                                                              ctx->row_b.p, nc, x, ctx->icount.p + 1);
-  k_violations_proj<<<unsigned(ctx->n_rows_full - nc), 256, 0, ctx->stream>>>(ctx->row_ptr.p, ctx->ent_var.p, nc,
-                                                                               x, ctx->icount.p + 1);
+  if (ctx->n_rows_full > nc)
+    k_violations_proj<<<unsigned(ctx->n_rows_full - nc), 256, 0, ctx->stream>>>(ctx->row_ptr.p, ctx->ent_var.p,
+                                                                                 nc, x, ctx->icount.p + 1);
   DM_LAUNCH_CHECK(ctx);
+  return DM_OK;
+}
+
+dm_status count_violations(dm_ctx* ctx, const uint8_t* x, int64_t* out) {
+  DM_TRY(enqueue_violations(ctx, x));
   DM_HIP(ctx, hipMemcpyAsync(out, ctx->icount.p + 1, sizeof(int64_t), hipMemcpyDeviceToHost, ctx->stream));
   DM_HIP(ctx, hipStreamSynchronize(ctx->stream));
   return DM_OK;
@@ -137,25 +144,31 @@ static dm_status round_impl(dm_ctx* ctx, const dm_round_params& P, const R* lam,
       k_agree<R><<<grid_for(nfree, 256), 256, 0, st>>>(reinterpret_cast<const R*>(ctx->mrec.p), ctx->var_deg.p,
                                                       nfree, ctx->pref.p, ctx->icount.p, absm.p);
     DM_LAUNCH_CHECK(ctx);
+    // the undecided count and, on the first round, the automatic perturbation
+    // scale (from the summed |M|) come back with one wait
+    const bool auto_delta = r == 0 && delta <= 0.0;
+    if (auto_delta) DM_TRY(sum_f64(ctx, absm.p, nfree, nullptr, SUM_ALL, ctx->scal.p));
     int64_t undecided = 0;
+    double sum_absm = 0.0;
     DM_HIP(ctx, hipMemcpyAsync(&undecided, ctx->icount.p, sizeof(int64_t), hipMemcpyDeviceToHost, st));
+    if (auto_delta)
+      DM_HIP(ctx, hipMemcpyAsync(&sum_absm, ctx->scal.p, sizeof(double), hipMemcpyDeviceToHost, st));
     DM_HIP(ctx, hipStreamSynchronize(st));
-    if (r == 0 && delta <= 0.0) {
-      DM_TRY(sum_f64(ctx, absm.p, nfree, nullptr, SUM_ALL, ctx->scal.p));
-      double s = 0.0;
-      DM_HIP(ctx, hipMemcpyAsync(&s, ctx->scal.p, sizeof(double), hipMemcpyDeviceToHost, st));
-      DM_HIP(ctx, hipStreamSynchronize(st));
-      delta = ctx->nnz ? 0.1 * s / double(ctx->nnz) : 0.0;
-    }
+    if (auto_delta) delta = ctx->nnz ? 0.1 * sum_absm / double(ctx->nnz) : 0.0;
     k_make_x<<<grid_for(ctx->nP, 256), 256, 0, st>>>(ctx->state.p, ctx->var_red.p, ctx->pref.p, ctx->nP, x);
     DM_LAUNCH_CHECK(ctx);
     *rounds_used = r;
     if (undecided == 0) {
+      // violations and the objective of x with one wait
+      DM_TRY(enqueue_violations(ctx, x));
+      DM_TRY(sum_f64(ctx, ctx->cost64.p, ctx->nP, x, SUM_U8_NZ, ctx->scal.p + 1));
       int64_t viol = 0;
-      DM_TRY(count_violations(ctx, x, &viol));
+      DM_HIP(ctx, hipMemcpyAsync(&viol, ctx->icount.p + 1, sizeof(int64_t), hipMemcpyDeviceToHost, st));
+      DM_HIP(ctx, hipMemcpyAsync(pobj, ctx->scal.p + 1, sizeof(double), hipMemcpyDeviceToHost, st));
+      DM_HIP(ctx, hipStreamSynchronize(st));
       if (viol == 0) {
         *feasible = 1;
-        break;
+        return DM_OK;
       }
     }
     if (r == P.rounds) break;
