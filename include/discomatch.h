@@ -200,7 +200,9 @@ dm_status dm_build_product_space(dm_ctx* ctx, const dm_mesh* X, const dm_mesh* Y
  *  DM_ARR_RROW_ORIG int64 [n_rows], DM_ARR_RROW_PTR int64 [n_rows+1],
  *  DM_ARR_RENT_VAR int64 [nnz], DM_ARR_RENT_COEF int32 [nnz], DM_ARR_RROW_B int32 [n_rows]
  *  DM_ARR_EDGES_X / _Y int32 [n_edges*2] sorted (min, max) vertex pairs
- *  DM_ARR_CAND    uint8 [nvx*nvy]        1 where (m, n) is in C */
+ *  DM_ARR_CAND    uint8 [nvx*nvy]        1 where (m, n) is in C
+ * dst [device] receives the array (enqueued only); it may be NULL when the
+ * array is empty (e.g. the reduced rows of a problem presolve decided). */
 enum {
   DM_ARR_PV = 0, DM_ARR_CODE, DM_ARR_STATE, DM_ARR_ROW_KEY, DM_ARR_ROW_PTR, DM_ARR_ENT_VAR,
   DM_ARR_ENT_COEF, DM_ARR_ROW_B, DM_ARR_FREE_VAR, DM_ARR_RROW_ORIG, DM_ARR_RROW_PTR,

@@ -220,7 +220,8 @@ __global__ void k_export_code(const int32_t* code, int32_t* out, int64_t n) {
 
 template <typename S, typename D>
 static dm_status widen(dm_ctx* ctx, const S* in, void* out, int64_t n) {
-  if (n <= 0) return DM_OK;
+  if (n <= 0) return DM_OK;   // an empty array: dst may be NULL
+  if (!out) return dm_fail(ctx, DM_ERR_INVALID_ARG, "dm_get_space: dst is NULL");
   k_widen<S, D><<<grid_for(n, 256), 256, 0, ctx->stream>>>(in, static_cast<D*>(out), n);
   DM_LAUNCH_CHECK(ctx);
   return DM_OK;
@@ -229,7 +230,6 @@ static dm_status widen(dm_ctx* ctx, const S* in, void* out, int64_t n) {
 extern "C" dm_status dm_get_space(dm_ctx* ctx, int32_t which, void* dst) {
   if (!ctx) return DM_ERR_INVALID_ARG;
   if (!ctx->has_space) return dm_fail(ctx, DM_ERR_STATE, "dm_get_space: no product space built");
-  if (!dst) return dm_fail(ctx, DM_ERR_INVALID_ARG, "dm_get_space: dst is NULL");
   DM_HIP(ctx, hipSetDevice(ctx->device));
   if (ctx->generic && (which == DM_ARR_PV || which == DM_ARR_EDGES_X || which == DM_ARR_EDGES_Y || which == DM_ARR_CAND))
     return dm_fail(ctx, DM_ERR_STATE, "dm_get_space: a problem from dm_build_ilp has no meshes or candidates");

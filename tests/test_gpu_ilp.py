@@ -98,3 +98,59 @@ def test_ilp_smoothed_dual_parity():
     rlam, rtr = S.dual_solve(20, T=T)
     say(f"  smoothed: bound rel err {rel_err(np_(tr), rtr):.2e}")
     assert rel_err(np_(tr), rtr) <= 1e-10
+
+
+@pytest.mark.parametrize("seed", [4, 0])
+def test_ilp_without_exactly_one_rows(seed):
+    """A generic ILP whose rows are all short +-1 rows (half +1, half -1, so
+    none is an exactly-one row), costs of both signs: the problem has no
+    projection rows, and the sweeps, rounding, the primal check and the
+    exact search run without them.  Seed 4 keeps 10 free variables and an
+    integrality gap; seed 0 is decided entirely by presolve.  Bounds against
+    the oracle, the optimum against HiGHS."""
+    rng = np.random.default_rng(seed)
+    n = 16
+    planted = rng.integers(0, 2, n)
+    rows, deg = [], np.zeros(n, int)
+    while len(rows) < 12:
+        k = int(rng.choice([2, 4, 6]))
+        vs = rng.choice(n, k, replace=False)
+        if np.any(deg[vs] >= 5):
+            continue
+        a = np.array([1] * (k // 2) + [-1] * (k // 2))
+        rng.shuffle(a)
+        rows.append((vs, a))
+        deg[vs] += 1
+    for v in range(n):   # every variable in some row
+        if deg[v] == 0:
+            u = next(u for u in range(n) if u != v and deg[u] < 5)
+            rows.append((np.array([v, u]), np.array([1, -1])))
+            deg[[v, u]] += 1
+    rp = np.cumsum([0] + [len(vs) for vs, _ in rows]).astype(np.int32)
+    cols = np.concatenate([vs for vs, _ in rows]).astype(np.int32)
+    coefs = np.concatenate([a for _, a in rows]).astype(np.int8)
+    b = np.array([int(a @ planted[vs]) for vs, a in rows], np.int32)
+    c = rng.uniform(0.5, 2.0, n) * rng.choice([-1, 1], n)
+    S = O.Space.from_ilp(n, rp, cols, coefs, b)
+    S.set_costs(c)
+    ctx = dm().Context(0)
+    ctx.build_ilp(n, rp, cols, coefs, b)
+    ctx.set_costs(torch.from_numpy(c))
+    assert (ctx.info["n_rows"], ctx.info["nnz"], ctx.info["n_free"]) == (S.info["n_rows"], S.info["nnz"],
+                                                                         S.info["n_free"])
+    for name in REDUCED:
+        assert np.array_equal(np_(ctx.get_space(name)).astype(np.int64),
+                              np.asarray(S.get(name)).astype(np.int64)), name
+    lam, tr = ctx.dual_solve(ctx.init_lambda("fp64"), 30, 0.5)
+    _, rtr = S.dual_solve(30)
+    assert rel_err(np_(tr), rtr) <= 1e-10
+    opt = milp_optimum(S)
+    assert float(np_(tr).max()) <= opt + 1e-9 * max(1.0, abs(opt))
+    x, pobj, feas, _ = ctx.round_primal(lam, seed=0)
+    if feas:
+        assert ctx.check_primal(x) == 0 and pobj >= opt - 1e-9 * max(1.0, abs(opt))
+    xs, p2, bound, nodes, status = ctx.exact_search()
+    say(f"  seed {seed}: free {ctx.info['n_free']}, rows {ctx.info['n_rows']}: HiGHS {opt:.10f}, "
+        f"rounding feasible {feas}, search {p2:.10f} in {nodes} nodes, {status}")
+    assert status == "optimal" and abs(p2 - opt) <= 1e-9 * max(1.0, abs(opt))
+    assert ctx.check_primal(xs) == 0 and S.check_primal(np_(xs)) == 0
