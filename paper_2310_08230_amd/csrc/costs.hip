@@ -184,10 +184,17 @@ extern "C" dm_status dm_build_costs(dm_ctx* ctx, const float* FX, const float* F
   k_elem_cost<<<grid_for(nP, 256), 256, 0, st>>>(ctx->pv.p, ctx->cidx.p, nP, w.p, ctx->cost64.p,
                                                  ctx->cost32.p, cost, err.p);
   DM_LAUNCH_CHECK(ctx);
+  // the non-finite flag and the offset of the elements fixed to 1 (FP64,
+  // fixed order) come back with one wait
+  DM_ALLOC(ctx, ctx->scal, 16);
+  DM_TRY(sum_f64(ctx, ctx->cost64.p, ctx->nP, ctx->state.p, SUM_I8_ONE, ctx->scal.p));
   int e = 0;
-  DM_TRY(read_i32(ctx, err.p, &e));
+  double offset = 0.0;
+  DM_HIP(ctx, hipMemcpyAsync(&e, err.p, sizeof(int), hipMemcpyDeviceToHost, st));
+  DM_HIP(ctx, hipMemcpyAsync(&offset, ctx->scal.p, sizeof(double), hipMemcpyDeviceToHost, st));
+  DM_HIP(ctx, hipStreamSynchronize(st));
   if (e) return dm_fail(ctx, DM_ERR_NONFINITE, "non-finite element cost");
-  DM_TRY(cost_offset(ctx));   // waits for the stream
+  ctx->offset = offset;
   ctx->cost_prec = prec;
   ctx->desc_costs = true;
   ctx->has_cost = true;
