@@ -1,0 +1,63 @@
+"""The measurement helpers of bench.py (CPU only): the copy-calibrated HBM
+traffic summary behind the roofline's `traffic` field, its guard against a
+changed sweep source, and the host description of the CPU baseline."""
+import csv
+import json
+import os
+import shutil
+
+import bench
+
+FIELDS = ["Dispatch_Id", "Kernel_Name", "Counter_Name", "Counter_Value"]
+SWEEP = "void (anonymous namespace)::k_sweep<float, false, 0>((anonymous namespace)::SweepArgs, float const*)"
+OTHER = "void (anonymous namespace)::k_sweep<float, false, 1>((anonymous namespace)::SweepArgs, float const*)"
+
+
+def _csv(path, counter, rows):
+    with open(path, "w", newline="") as f:
+        w = csv.DictWriter(f, fieldnames=FIELDS)
+        w.writeheader()
+        for i, (name, v) in enumerate(rows):
+            w.writerow({"Dispatch_Id": i, "Kernel_Name": name, "Counter_Name": counter, "Counter_Value": v})
+
+
+def test_traffic_summary_scales_by_the_copy_calibration(tmp_path):
+    copy_bytes = 1 << 28
+    # the copy reads half its bytes under FETCH_SIZE (factor 2) and all of
+    # them under WRITE_SIZE (factor 1); the sweep's medians are 800 and 1100
+    # KiB, the evaluation-mode sweep and the outlier must not enter them
+    _csv(tmp_path / "cf.csv", "FETCH_SIZE", [("__amd_rocclr_copyBuffer", 131072.0)] * 3)
+    _csv(tmp_path / "cw.csv", "WRITE_SIZE", [("__amd_rocclr_copyBuffer", 262144.0)] * 3)
+    _csv(tmp_path / "f.csv", "FETCH_SIZE", [(SWEEP, 790.0), (SWEEP, 800.0), (SWEEP, 5000.0), (OTHER, 1e9)])
+    _csv(tmp_path / "w.csv", "WRITE_SIZE", [(SWEEP, 1100.0), (SWEEP, 1090.0), (SWEEP, 1200.0), (OTHER, 1e9)])
+    out = tmp_path / "t.json"
+    bench.summarize_counters(str(tmp_path / "f.csv"), str(tmp_path / "w.csv"), str(tmp_path / "cf.csv"),
+                             str(tmp_path / "cw.csv"), str(out), copy_bytes, "cmd", "w")
+    rec = json.load(open(out))
+    assert rec["copy_calibration"]["fetch_factor"] == 2.0 and rec["copy_calibration"]["write_factor"] == 1.0
+    assert rec["dispatches"] == [3, 3]
+    assert rec["fetch_bytes"] == 800 * 2 * 1024 and rec["write_bytes"] == 1100 * 1024
+    assert rec["bytes_per_launch"] == rec["fetch_bytes"] + rec["write_bytes"]
+    assert len(rec["dual_hip_sha256"]) == 64
+
+
+def test_traffic_field_follows_the_profiled_source(tmp_path, monkeypatch):
+    committed = json.load(open(os.path.join(bench.ROOT, "profiles", "sweep_plain_fp32_500_hbm_traffic.json")))
+    # a copy of the tree's two inputs: the same source gives the stored figure
+    (tmp_path / "profiles").mkdir()
+    src_dir = tmp_path / "paper_2310_08230_amd" / "csrc"
+    src_dir.mkdir(parents=True)
+    shutil.copy(os.path.join(bench.ROOT, "profiles", "sweep_plain_fp32_500_hbm_traffic.json"), tmp_path / "profiles")
+    shutil.copy(os.path.join(bench.ROOT, "paper_2310_08230_amd", "csrc", "dual.hip"), src_dir)
+    monkeypatch.setattr(bench, "ROOT", str(tmp_path))
+    assert bench._traffic() == committed["bytes_per_launch"]
+    # a changed sweep source: the counters no longer describe it
+    with open(src_dir / "dual.hip", "a") as f:
+        f.write("\n// changed\n")
+    assert bench._traffic() is None
+
+
+def test_host_cpu_names_model_and_cores():
+    h = bench.host_cpu()
+    assert isinstance(h["cpu_model"], str) and h["cpu_model"]
+    assert h["cores_available"] >= 1
