@@ -741,11 +741,14 @@ void* or_space_build(int nvx, int nfx, const float* VX, const int* FX, int nvy, 
   return S;
 }
 
-// Generic 0-1 ILP with +-1 rows (Appendix "Other ILPs").  Exactly-one rows
-// (all +1, b = 1) keep any length, the others at most 64 entries; a variable
-// in d < 4 rows gets padding rows x_i - x_i = 0 (one for d = 2 or 3, two for
-// d = 1) so that it lies in 4 or 5 rows.  Row order: the other input rows,
-// then the padding rows by variable, then the exactly-one input rows.
+// Generic 0-1 ILP with +-1 rows (Appendix "Other ILPs": the solver is not
+// specific to matching).  The decomposition of Eq. (D) as stated: one
+// subproblem per input row, over the distinct variables of that row, and a
+// variable's multipliers sum to its cost over the rows it lies in (1 to 5).
+// Exactly-one rows (all +1, b = 1) keep any length, the others at most 64
+// entries.  Row order: the other input rows, then the exactly-one input rows
+// (each group in input order); a variable named twice in one row is
+// rejected.
 void* or_ilp_build(int n_vars, int n_rows, const int* row_ptr, const int* cols, const int* coefs, const int* b,
                    int* status) {
   *status = E_ARG;
@@ -754,17 +757,17 @@ void* or_ilp_build(int n_vars, int n_rows, const int* row_ptr, const int* cols, 
   std::vector<bool> exactly_one(size_t(n_rows), false);
   for (int j = 0; j < n_rows; ++j) {
     bool all_pos = true;
-    std::vector<std::pair<int, int>> seen;
+    std::vector<int> seen;
     for (int e = row_ptr[j]; e < row_ptr[j + 1]; ++e) {
       if (coefs[e] != 1 && coefs[e] != -1) return nullptr;
       if (cols[e] < 0 || cols[e] >= n_vars) return nullptr;
       all_pos = all_pos && coefs[e] == 1;
-      seen.push_back({cols[e], coefs[e]});
+      seen.push_back(cols[e]);
       ++deg[size_t(cols[e])];
     }
     std::sort(seen.begin(), seen.end());
     for (size_t i = 1; i < seen.size(); ++i)
-      if (seen[i] == seen[i - 1]) return nullptr;   // a variable twice with one sign
+      if (seen[i] == seen[i - 1]) return nullptr;   // a variable twice in one row
     const int len = row_ptr[j + 1] - row_ptr[j];
     exactly_one[size_t(j)] = all_pos && b[j] == 1 && len > 0;
     if (!exactly_one[size_t(j)] && len > 64) return nullptr;
@@ -773,40 +776,20 @@ void* or_ilp_build(int n_vars, int n_rows, const int* row_ptr, const int* cols, 
     if (deg[size_t(v)] < 1 || deg[size_t(v)] > 5) return nullptr;
   Space* S = new Space();
   S->nP = n_vars;
-  auto add_row = [&](int64_t key, int rhs) {
-    S->row_key.push_back(key);
-    S->row_b.push_back(rhs);
+  auto add_input_row = [&](int j) {
+    S->row_key.push_back(j);
+    S->row_b.push_back(b[j]);
     S->row_ptr.push_back(int64_t(S->ent_var.size()));
+    for (int e = row_ptr[j]; e < row_ptr[j + 1]; ++e) {
+      S->ent_var.push_back(cols[e]);
+      S->ent_coef.push_back(coefs[e]);
+    }
   };
   for (int j = 0; j < n_rows; ++j)
-    if (!exactly_one[size_t(j)]) {
-      add_row(j, b[j]);
-      for (int e = row_ptr[j]; e < row_ptr[j + 1]; ++e) {
-        S->ent_var.push_back(cols[e]);
-        S->ent_coef.push_back(coefs[e]);
-      }
-    }
-  int64_t pad_key = n_rows;
-  for (int v = 0; v < n_vars; ++v) {
-    const int d = deg[size_t(v)];
-    const int pads = d == 1 ? 2 : (d <= 3 ? 1 : 0);
-    for (int k = 0; k < pads; ++k) {
-      add_row(pad_key++, 0);
-      S->ent_var.push_back(v);
-      S->ent_coef.push_back(1);
-      S->ent_var.push_back(v);
-      S->ent_coef.push_back(-1);
-    }
-  }
+    if (!exactly_one[size_t(j)]) add_input_row(j);
   S->n_closed = int64_t(S->row_b.size());
   for (int j = 0; j < n_rows; ++j)
-    if (exactly_one[size_t(j)]) {
-      add_row(j, b[j]);
-      for (int e = row_ptr[j]; e < row_ptr[j + 1]; ++e) {
-        S->ent_var.push_back(cols[e]);
-        S->ent_coef.push_back(coefs[e]);
-      }
-    }
+    if (exactly_one[size_t(j)]) add_input_row(j);
   S->n_rows = int64_t(S->row_b.size());
   S->row_ptr.push_back(int64_t(S->ent_var.size()));
   const int st = presolve(*S);

@@ -186,8 +186,9 @@ class Space:
 
     @classmethod
     def from_ilp(cls, n_vars, row_ptr, cols, coefs, b):
-        """Generic 0-1 ILP with +-1 rows (CSR), padded and presolved as the
-        library does (see or_ilp_build)."""
+        """Generic 0-1 ILP with +-1 rows (CSR): one subproblem per input
+        row, rows reordered [other rows | exactly-one rows], presolved (see
+        or_ilp_build)."""
         S = cls.__new__(cls)
         S._keep = [_c(row_ptr, np.int32), _c(cols, np.int32), _c(coefs, np.int32), _c(b, np.int32)]
         rp, cl, cf, bb = S._keep

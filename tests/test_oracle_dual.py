@@ -519,3 +519,56 @@ def test_infeasible_fixings_are_reported():
     fix, _, _ = S.confident_fix(lam, 0.9)
     with pytest.raises(O.OracleError):
         S.fix_variables(fix)
+
+
+def test_costs_equal_eq_cost_restated():
+    """The oracle's element costs equal Eq. (cost) written out here from the
+    element list: c_p = sum over its three product vertices (m, n) of
+    (A_X(m) + A_Y(n)) ||F_X(m) - F_Y(n)||, with the oracle's mixed areas
+    (pinned above) and FP64 descriptors."""
+    for cfg, seed in ((1, 0), (1, 2)):
+        p = make_pair(cfg, seed)
+        S = _space(p, 6)
+        want = _costs64(S, p, p.DX.astype(np.float64), p.DY.astype(np.float64))
+        got = S.get("cost")
+        assert got.shape == want.shape and np.max(np.abs(got - want) / np.maximum(np.abs(want), 1e-300)) <= 1e-12
+
+
+def test_identity_elements_cost_nothing():
+    """Matching a shape onto itself with identical descriptors: every
+    triangle-triangle element (f, f) with the faces aligned (rotation 0) has
+    cost 0, and only those (and degenerate elements of zero-distance pairs)
+    do."""
+    p = make_pair(1, 0)
+    cxy, cyx = O.knn(p.DX, p.DX, 6)
+    S = O.Space(p.VX, p.FX, p.VX, p.FX, cxy, cyx)
+    S.costs(p.DX, p.DX)
+    code, cost = S.get("code"), S.get("cost")
+    tt0 = (code[:, 0] == 0) & (code[:, 2] == 0) & (code[:, 1] == code[:, 3])
+    assert tt0.sum() == len(p.FX) and np.all(cost[tt0] == 0.0)
+    pv = S.get("pv")
+    nv = len(p.VX)
+    diag = np.all(pv // nv == pv % nv, axis=1)   # every product vertex (m, m)
+    assert np.all(cost[~diag] > 0.0) and np.all(cost[diag] == 0.0)
+
+
+def test_confident_fixing_ranks_largest_score_first():
+    """Hand-worked min-marginals: two exactly-one rows over x0, x1, x2 with
+    multipliers (0, 1, 5) and (0, 2, 9), so c = (0, 3, 14).  In an
+    exactly-one row M_i = lambda_i - min_{k != i} lambda_k, giving
+    (-1, 1, 5) and (-2, 2, 9): sums -3, 3, 14, all three agreeing (x0 -> 1,
+    x1, x2 -> 0).  Largest |sum| first with ties to the lower variable:
+    x2, x0, x1.  Fixing floor(0.9 * 3) = 2 takes x2 = 0 and x0 = 1;
+    floor(0.34 * 3) = 1 takes x2 = 0 only.  (Smallest first would take x0
+    and x1.)"""
+    rp = np.array([0, 3, 6], np.int32)
+    S = O.Space.from_ilp(3, rp, np.array([0, 1, 2, 0, 1, 2]), np.ones(6, int), np.array([1, 1]))
+    S.set_costs(np.array([0.0, 3.0, 14.0]))
+    assert S.info["n_free"] == 3
+    lam = np.array([0.0, 1.0, 5.0, 0.0, 2.0, 9.0])
+    M, _, _ = S.min_marginals(lam)
+    assert np.allclose(M, [-1, 1, 5, -2, 2, 9], atol=0)
+    fix, na, nf = S.confident_fix(lam, 0.9)
+    assert (na, nf) == (3, 2) and fix.tolist() == [1, -1, 0]
+    fix, na, nf = S.confident_fix(lam, 0.34)
+    assert (na, nf) == (3, 1) and fix.tolist() == [-1, -1, 0]
