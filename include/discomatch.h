@@ -107,6 +107,24 @@ dm_status dm_knn_candidates(dm_ctx* ctx, const float* FX, int32_t nvx, const flo
                             int32_t nvy, int32_t D, int32_t K, int32_t prec, int32_t* cand_xy,
                             int32_t* cand_yx);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * computation and results as dm_knn_candidates, with the temporaries (an
+ * error word, the squared distances and the BF16 operand copies) in a fixed
+ * scratch array of 16 MiB that every GPU the library runs on holds until the
+ * process ends.  No call allocates or frees memory.  Arguments, layouts and
+ * errors as dm_knn_candidates; in addition DM_ERR_WORKSPACE when the
+ * temporaries exceed 16 MiB: 4*nvx*nvy bytes of distances, plus
+ * 2*D8*(nvx64 + nvy64) + 4*(nvx64 + nvy64) in BF16, with D8 = D rounded up
+ * to 8 and nvx64, nvy64 rounded up to 64, each piece rounded up to 256 bytes
+ * (about 2000 x 2000 vertices at D = 128).  Every call on one GPU shares
+ * that GPU's array and leaves its last contents there; calls that overlap on
+ * one GPU (other threads, other streams, other contexts) race and must be
+ * serialised by the caller.  Synchronises (the finiteness check). */
+dm_status dm_knn_candidates_noalloc(dm_ctx* ctx, const float* FX, int32_t nvx, const float* FY,
+                                    int32_t nvy, int32_t D, int32_t K, int32_t prec, int32_t* cand_xy,
+                                    int32_t* cand_yx);
+
 /* Generic 0-1 ILPs (Appendix "Other ILPs": the solver is not specific to
  * matching): min c^T x subject to A x = b, x in {0,1}^n, every coefficient
  * +1 or -1, every variable in 1 to 5 rows, no variable twice with the same

@@ -75,6 +75,7 @@ def lib():
             "dm_destroy": [P],
             "dm_set_stream": [P, P],
             "dm_knn_candidates": [P, P, I32, P, I32, I32, I32, I32, P, P],
+            "dm_knn_candidates_noalloc": [P, P, I32, P, I32, I32, I32, I32, P, P],
             "dm_build_product_space": [P, P, P, P, P, I32, P],
             "dm_get_space": [P, I32, P],
             "dm_build_costs": [P, P, P, I32, I32, P],
@@ -156,6 +157,20 @@ class Context:
         cxy = torch.empty((DX.shape[0], K), dtype=torch.int32, device=self.device)
         cyx = torch.empty((DY.shape[0], K), dtype=torch.int32, device=self.device)
         self._call("dm_knn_candidates", _ptr(DX), DX.shape[0], _ptr(DY), DY.shape[0], DX.shape[1], K,
+                   PREC[prec], _ptr(cxy), _ptr(cyx))
+        return cxy, cyx
+
+    def knn_candidates_noalloc(self, DX, DY, K, prec="fp32", out=None):
+        """As knn_candidates, through the entry point that allocates nothing
+        (its temporaries live in the library's fixed per-GPU scratch array);
+        out = (cand_xy, cand_yx) int32 tensors to write, else new ones."""
+        DX = _dev(DX, torch.float32, self.device)
+        DY = _dev(DY, torch.float32, self.device)
+        if out is None:
+            out = (torch.empty((DX.shape[0], K), dtype=torch.int32, device=self.device),
+                   torch.empty((DY.shape[0], K), dtype=torch.int32, device=self.device))
+        cxy, cyx = out
+        self._call("dm_knn_candidates_noalloc", _ptr(DX), DX.shape[0], _ptr(DY), DY.shape[0], DX.shape[1], K,
                    PREC[prec], _ptr(cxy), _ptr(cyx))
         return cxy, cyx
 

@@ -42,6 +42,12 @@ extern "C" dm_status dm_create(int32_t device, void* hip_stream, dm_ctx** out) {
     delete c;
     return DM_ERR_HIP;
   }
+  // device address of the allocation-free entry point's scratch array
+  if (knn_scratch_init(c) != DM_OK) {
+    (void)hipHostFree(c->host_i32);
+    delete c;
+    return DM_ERR_HIP;
+  }
   *out = c;
   return DM_OK;
 }

@@ -290,6 +290,8 @@ dm_status read_i32(dm_ctx* ctx, const int32_t* dev, int32_t* host);
 // n (<= HOST_SLOTS) device ints into host[0..n) with one wait for the stream
 dm_status read_i32s(dm_ctx* ctx, int n, const int32_t* const* dev, int32_t* host);
 dm_status check_finite(dm_ctx* ctx, const float* a, int64_t na, const float* b, int64_t nb);
+// takes this device's address of the scratch array of dm_knn_candidates_noalloc (once per device)
+dm_status knn_scratch_init(dm_ctx* ctx);
 dm_status dual_flush(dm_ctx* ctx);  // write the bound of the last sweep launch
 dm_status cost_offset(dm_ctx* ctx);   // offset = summed costs of elements fixed to 1 (synchronises)
 dm_status corner_lists(dm_ctx* ctx);  // corners per candidate pair (built once per product space)

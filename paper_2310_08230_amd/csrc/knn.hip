@@ -10,6 +10,7 @@
 // The candidates of a vertex are its K nearest vertices of the other shape,
 // ordered by (squared distance, index).
 #include <cmath>
+#include <mutex>
 
 #include "dm_internal.h"
 
@@ -136,39 +137,80 @@ __global__ __launch_bounds__(256) void k_topk(const float* d2, int32_t nvx, int3
   for (int32_t k = threadIdx.x; k < K; k += blockDim.x) out[int64_t(q) * K + k] = int32_t(keys[k] & 0xFFFFFFFFu);
 }
 
-}  // namespace
 
-// both descriptor arrays flag one word, read back once
-dm_status check_finite(dm_ctx* ctx, const float* a, int64_t na, const float* b, int64_t nb) {
-  DArr<int> err;
-  DM_ALLOC(ctx, err, 1);
-  DM_HIP(ctx, hipMemsetAsync(err.p, 0, sizeof(int), ctx->stream));
-  if (na > 0) k_nonfinite<<<grid_for(na, 256), 256, 0, ctx->stream>>>(a, na, err.p);
-  if (nb > 0) k_nonfinite<<<grid_for(nb, 256), 256, 0, ctx->stream>>>(b, nb, err.p);
+__global__ void k_zero_i32(int* p) { *p = 0; }
+
+// Temporaries of one candidate computation, carved from one block of device
+// memory: an error word, the squared distances d2 [nvx*nvy] and, in the BF16
+// form, the rounded descriptors padded to 64 rows and 8 columns with their
+// norms.  Every piece starts on a 256-byte boundary.
+struct KnnBufs {
+  int* err = nullptr;
+  float* d2 = nullptr;
+  uint16_t* A = nullptr;
+  uint16_t* B = nullptr;
+  float* na = nullptr;
+  float* nb = nullptr;
+};
+
+inline size_t align256(size_t n) { return (n + 255) / 256 * 256; }
+
+// bytes the temporaries need; with base set, the pieces' addresses in it
+size_t knn_layout(int32_t nvx, int32_t nvy, int32_t D, int32_t prec, bool with_d2, unsigned char* base,
+                  KnnBufs* out) {
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    const size_t at = off;
+    off += align256(bytes);
+    return base ? base + at : nullptr;
+  };
+  KnnBufs b;
+  b.err = reinterpret_cast<int*>(take(sizeof(int)));
+  if (with_d2) b.d2 = reinterpret_cast<float*>(take(sizeof(float) * size_t(nvx) * size_t(nvy)));
+  if (prec == DM_PREC_BF16) {
+    const size_t Dp = size_t(D + 7) / 8 * 8;
+    const size_t nxp = size_t(nvx + 63) / 64 * 64, nyp = size_t(nvy + 63) / 64 * 64;
+    b.A = reinterpret_cast<uint16_t*>(take(sizeof(uint16_t) * nxp * Dp));
+    b.B = reinterpret_cast<uint16_t*>(take(sizeof(uint16_t) * nyp * Dp));
+    b.na = reinterpret_cast<float*>(take(sizeof(float) * nxp));
+    b.nb = reinterpret_cast<float*>(take(sizeof(float) * nyp));
+  }
+  if (out) *out = b;
+  return off;
+}
+
+// Scratch of the allocation-free entry point: one array per GPU, alive until
+// the process ends.  Host code never passes the array's name to a kernel; it
+// uses the device address taken once per device by knn_scratch_init.
+constexpr size_t KNN_SCRATCH_BYTES = size_t(16) << 20;
+static __device__ __align__(256) unsigned char scratch[KNN_SCRATCH_BYTES];
+
+constexpr int KNN_MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[KNN_MAX_DEVICES] = {};
+
+dm_status check_finite_into(dm_ctx* ctx, const float* a, int64_t na, const float* b, int64_t nb, int* err) {
+  k_zero_i32<<<1, 1, 0, ctx->stream>>>(err);
+  if (na > 0) k_nonfinite<<<grid_for(na, 256), 256, 0, ctx->stream>>>(a, na, err);
+  if (nb > 0) k_nonfinite<<<grid_for(nb, 256), 256, 0, ctx->stream>>>(b, nb, err);
   DM_LAUNCH_CHECK(ctx);
   int e = 0;
-  DM_TRY(read_i32(ctx, err.p, &e));
+  DM_TRY(read_i32(ctx, err, &e));
   if (e) return dm_fail(ctx, DM_ERR_NONFINITE, "non-finite descriptor");
   return DM_OK;
 }
 
-dm_status knn_distances(dm_ctx* ctx, const float* FX, int32_t nvx, const float* FY, int32_t nvy,
-                        int32_t D, int32_t prec, float* d2) {
+dm_status distances_into(dm_ctx* ctx, const float* FX, int32_t nvx, const float* FY, int32_t nvy, int32_t D,
+                         int32_t prec, const KnnBufs& w, float* d2) {
   hipStream_t st = ctx->stream;
-  DM_TRY(check_finite(ctx, FX, int64_t(nvx) * D, FY, int64_t(nvy) * D));
+  DM_TRY(check_finite_into(ctx, FX, int64_t(nvx) * D, FY, int64_t(nvy) * D, w.err));
   if (prec == DM_PREC_BF16) {
     const int32_t Dp = (D + 7) / 8 * 8;
     const int32_t nxp = (nvx + 63) / 64 * 64, nyp = (nvy + 63) / 64 * 64;
-    DArr<uint16_t> A, B;
-    DArr<float> na, nb;
-    DM_ALLOC(ctx, A, size_t(nxp) * Dp);
-    DM_ALLOC(ctx, B, size_t(nyp) * Dp);
-    DM_ALLOC(ctx, na, size_t(nxp));
-    DM_ALLOC(ctx, nb, size_t(nyp));
-    k_to_bf16<<<grid_for(nxp, 128), 128, 0, st>>>(FX, nvx, D, nxp, Dp, A.p, na.p);
-    k_to_bf16<<<grid_for(nyp, 128), 128, 0, st>>>(FY, nvy, D, nyp, Dp, B.p, nb.p);
+    k_to_bf16<<<grid_for(nxp, 128), 128, 0, st>>>(FX, nvx, D, nxp, Dp, w.A, w.na);
+    k_to_bf16<<<grid_for(nyp, 128), 128, 0, st>>>(FY, nvy, D, nyp, Dp, w.B, w.nb);
     dim3 grid(unsigned(nyp / 64), unsigned(nxp / 64));
-    k_gemm_bf16_dist<<<grid, 256, 0, st>>>(A.p, B.p, na.p, nb.p, nvx, nvy, Dp, d2);
+    k_gemm_bf16_dist<<<grid, 256, 0, st>>>(w.A, w.B, w.na, w.nb, nvx, nvy, Dp, d2);
     DM_LAUNCH_CHECK(ctx);
     return DM_OK;
   }
@@ -180,22 +222,96 @@ dm_status knn_distances(dm_ctx* ctx, const float* FX, int32_t nvx, const float* 
   return dm_fail(ctx, DM_ERR_INVALID_ARG, "unknown precision %d", prec);
 }
 
+dm_status knn_check_args(dm_ctx* ctx, const char* name, const float* FX, int32_t nvx, const float* FY,
+                         int32_t nvy, int32_t D, int32_t K, int32_t prec, const int32_t* cand_xy,
+                         const int32_t* cand_yx) {
+  if (!FX || !FY || !cand_xy || !cand_yx) return dm_fail(ctx, DM_ERR_INVALID_ARG, "%s: NULL argument", name);
+  if (nvx < 1 || nvy < 1 || nvx > TOPK_MAX || nvy > TOPK_MAX || D < 1 || K < 1 || K > nvx || K > nvy)
+    return dm_fail(ctx, DM_ERR_INVALID_ARG, "%s: nvx=%d nvy=%d D=%d K=%d out of range", name, nvx, nvy, D, K);
+  if (prec != DM_PREC_BF16 && prec != DM_PREC_FP32 && prec != DM_PREC_FP64)
+    return dm_fail(ctx, DM_ERR_INVALID_ARG, "%s: unknown precision %d", name, prec);
+  return DM_OK;
+}
+
+// distances into w.d2, then the K nearest both ways
+dm_status knn_run(dm_ctx* ctx, const float* FX, int32_t nvx, const float* FY, int32_t nvy, int32_t D, int32_t K,
+                  int32_t prec, int32_t* cand_xy, int32_t* cand_yx, const KnnBufs& w) {
+  DM_TRY(distances_into(ctx, FX, nvx, FY, nvy, D, prec, w, w.d2));
+  k_topk<<<nvx, 256, 0, ctx->stream>>>(w.d2, nvx, nvy, 0, K, cand_xy);
+  k_topk<<<nvy, 256, 0, ctx->stream>>>(w.d2, nvx, nvy, 1, K, cand_yx);
+  DM_LAUNCH_CHECK(ctx);
+  return DM_OK;
+}
+
+}  // namespace
+
+// device address of this GPU's scratch array, taken once per device with the
+// device current (each GPU holds its own copy at its own address)
+dm_status knn_scratch_init(dm_ctx* ctx) {
+  const int dev = ctx->device;
+  if (dev < 0 || dev >= KNN_MAX_DEVICES) return DM_OK;   // the allocation-free entry point refuses such devices
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (g_scratch_ptr[dev]) return DM_OK;
+  void* ptr = nullptr;
+  DM_HIP(ctx, hipSetDevice(dev));
+  DM_HIP(ctx, hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+  if (!ptr) return dm_fail(ctx, DM_ERR_HIP, "no device address for the candidate scratch array");
+  g_scratch_ptr[dev] = ptr;
+  return DM_OK;
+}
+
+// both descriptor arrays flag one word, read back once
+dm_status check_finite(dm_ctx* ctx, const float* a, int64_t na, const float* b, int64_t nb) {
+  DArr<int> err;
+  DM_ALLOC(ctx, err, 1);
+  return check_finite_into(ctx, a, na, b, nb, err.p);
+}
+
+dm_status knn_distances(dm_ctx* ctx, const float* FX, int32_t nvx, const float* FY, int32_t nvy,
+                        int32_t D, int32_t prec, float* d2) {
+  // the distances go to the caller's d2: the layout without its d2 piece
+  DArr<unsigned char> ws;
+  KnnBufs w;
+  DM_ALLOC(ctx, ws, knn_layout(nvx, nvy, D, prec, false, nullptr, nullptr));
+  knn_layout(nvx, nvy, D, prec, false, ws.p, &w);
+  return distances_into(ctx, FX, nvx, FY, nvy, D, prec, w, d2);
+}
+
 extern "C" dm_status dm_knn_candidates(dm_ctx* ctx, const float* FX, int32_t nvx, const float* FY,
                                        int32_t nvy, int32_t D, int32_t K, int32_t prec, int32_t* cand_xy,
                                        int32_t* cand_yx) {
   if (!ctx) return DM_ERR_INVALID_ARG;
   ctx->err.clear();
-  if (!FX || !FY || !cand_xy || !cand_yx)
-    return dm_fail(ctx, DM_ERR_INVALID_ARG, "dm_knn_candidates: NULL argument");
-  if (nvx < 1 || nvy < 1 || nvx > TOPK_MAX || nvy > TOPK_MAX || D < 1 || K < 1 || K > nvx || K > nvy)
-    return dm_fail(ctx, DM_ERR_INVALID_ARG, "dm_knn_candidates: nvx=%d nvy=%d D=%d K=%d out of range", nvx,
-                   nvy, D, K);
+  DM_TRY(knn_check_args(ctx, "dm_knn_candidates", FX, nvx, FY, nvy, D, K, prec, cand_xy, cand_yx));
   DM_HIP(ctx, hipSetDevice(ctx->device));
-  DArr<float> d2;
-  DM_ALLOC(ctx, d2, size_t(nvx) * nvy);
-  DM_TRY(knn_distances(ctx, FX, nvx, FY, nvy, D, prec, d2.p));
-  k_topk<<<nvx, 256, 0, ctx->stream>>>(d2.p, nvx, nvy, 0, K, cand_xy);
-  k_topk<<<nvy, 256, 0, ctx->stream>>>(d2.p, nvx, nvy, 1, K, cand_yx);
-  DM_LAUNCH_CHECK(ctx);
-  return DM_OK;   // enqueued only; temporaries are freed in stream order
+  DArr<unsigned char> ws;
+  KnnBufs w;
+  DM_ALLOC(ctx, ws, knn_layout(nvx, nvy, D, prec, true, nullptr, nullptr));
+  knn_layout(nvx, nvy, D, prec, true, ws.p, &w);
+  DM_TRY(knn_run(ctx, FX, nvx, FY, nvy, D, K, prec, cand_xy, cand_yx, w));
+  return DM_OK;   // the temporaries are freed in stream order
+}
+
+extern "C" dm_status dm_knn_candidates_noalloc(dm_ctx* ctx, const float* FX, int32_t nvx, const float* FY,
+                                               int32_t nvy, int32_t D, int32_t K, int32_t prec,
+                                               int32_t* cand_xy, int32_t* cand_yx) {
+  if (!ctx) return DM_ERR_INVALID_ARG;
+  ctx->err.clear();
+  DM_TRY(knn_check_args(ctx, "dm_knn_candidates_noalloc", FX, nvx, FY, nvy, D, K, prec, cand_xy, cand_yx));
+  const size_t need = knn_layout(nvx, nvy, D, prec, true, nullptr, nullptr);
+  if (need > KNN_SCRATCH_BYTES)
+    return dm_fail(ctx, DM_ERR_WORKSPACE,
+                   "dm_knn_candidates_noalloc: needs %zu bytes of scratch, the limit is %zu (nvx=%d nvy=%d D=%d)",
+                   need, KNN_SCRATCH_BYTES, nvx, nvy, D);
+  void* base = nullptr;
+  {
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (ctx->device >= 0 && ctx->device < KNN_MAX_DEVICES) base = g_scratch_ptr[ctx->device];
+  }
+  if (!base) return dm_fail(ctx, DM_ERR_STATE, "dm_knn_candidates_noalloc: no scratch address for device %d",
+                            ctx->device);
+  DM_HIP(ctx, hipSetDevice(ctx->device));
+  KnnBufs w;
+  knn_layout(nvx, nvy, D, prec, true, static_cast<unsigned char*>(base), &w);
+  return knn_run(ctx, FX, nvx, FY, nvy, D, K, prec, cand_xy, cand_yx, w);
 }
