@@ -127,12 +127,12 @@ dm_status dm_knn_candidates_noalloc(dm_ctx* ctx, const float* FX, int32_t nvx, c
 
 /* Generic 0-1 ILPs (Appendix "Other ILPs": the solver is not specific to
  * matching): min c^T x subject to A x = b, x in {0,1}^n, every coefficient
- * +1 or -1, every variable in 1 to 5 rows, no variable twice with the same
- * sign in one row.  Rows with all coefficients +1 and b = 1 are exactly-one
- * rows of any length; the others have at most 64 entries.  A variable in
- * d < 4 rows gets padding rows x_i - x_i = 0 (always satisfied; one for
- * d = 2, 3, two for d = 1) so that it has 4 or 5 rows; the full row order is
- * [other input rows | padding rows by variable | exactly-one input rows].
+ * +1 or -1, every variable in 1 to 5 rows, no variable twice in one row.
+ * Rows with all coefficients +1 and b = 1 are exactly-one rows of any
+ * length; the others have at most 64 entries.  The decomposition is that of
+ * Eq. (D): one subproblem per input row and nothing else, so a variable in d
+ * rows has d multipliers summing to its cost.  The full row order is
+ * [other input rows | exactly-one input rows], each group in input order.
  * Presolve and the reduced problem follow as for the matching ILP, and every
  * solver entry point applies (multipliers, dual and quasi-Newton solves,
  * bounds, rounding, fixing, exact search); the ones that need meshes,

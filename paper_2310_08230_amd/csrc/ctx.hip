@@ -237,7 +237,7 @@ extern "C" dm_status dm_get_space(dm_ctx* ctx, int32_t which, void* dst) {
   if (!ctx) return DM_ERR_INVALID_ARG;
   if (!ctx->has_space) return dm_fail(ctx, DM_ERR_STATE, "dm_get_space: no product space built");
   DM_HIP(ctx, hipSetDevice(ctx->device));
-  if (ctx->generic && (which == DM_ARR_PV || which == DM_ARR_EDGES_X || which == DM_ARR_EDGES_Y || which == DM_ARR_CAND))
+  if (ctx->generic && (which == DM_ARR_PV || which == DM_ARR_CODE || which == DM_ARR_EDGES_X || which == DM_ARR_EDGES_Y || which == DM_ARR_CAND))
     return dm_fail(ctx, DM_ERR_STATE, "dm_get_space: a problem from dm_build_ilp has no meshes or candidates");
   switch (which) {
     case DM_ARR_PV: return widen<int32_t, int32_t>(ctx, ctx->pv.p, dst, ctx->nP * 3);

@@ -76,46 +76,48 @@ struct MeshDev {
   DArr<double> area;       // nv mixed areas (filled by costs)
 };
 
-// Reduced-problem entry word: [31] coefficient is -1, [30] variable has five
-// rows, [29:27] slot of the entry in its variable's record, [26:0] variable.
+// Reduced-problem entry word: [31] coefficient is -1, [30] unused, [29:27]
+// slot of the entry in its variable's record, [26:0] variable.
 constexpr uint32_t W_NEG = 1u << 31;
-constexpr uint32_t W_DEG5 = 1u << 30;
 constexpr int W_SLOT_SHIFT = 27;
 constexpr uint32_t W_VAR_MASK = (1u << 27) - 1u;
-constexpr int REC = 8;          // record stride: 5 multiplier slots, cost, 2 spare
+constexpr int REC = 8;          // record stride: 5 multiplier slots, cost, degree, 1 spare
 constexpr int REC_COST = 5;
+constexpr int REC_DEG = 6;
 constexpr int MAX_SHORT_ROW = 64;
 constexpr int SOFT_MAX_ROW = 24;
 constexpr uint32_t CHUNK_PAD = 0xFFFFFFFFu;   // entry word of an unused chunk slot
 
 // Multipliers of free variable i from its record (slots 0-4 hold s_k, slot 5
-// the cost c_i), with dual feasibility restored: lambda_k = s_k + (c_i -
-// sum_k s_k) / |J_i|.  Slot 4 is used only when the variable has five rows.
-// Every reader of a record (the row sweeps and the per-variable passes) goes
-// through this one function, so they all see bit-identical multipliers.
+// the cost c_i, slot 6 the number |J_i| of rows the variable lies in, 1 to
+// 5), with dual feasibility restored: lambda_k = s_k + (c_i - sum_k s_k) /
+// |J_i|.  Slots at or above |J_i| hold zero and are never written, so the sum
+// runs over all five.  Every reader of a record (the row sweeps and the
+// per-variable passes) goes through this one function, so they all see
+// bit-identical multipliers.
 template <typename R>
-__device__ inline void rec_lambdas(const R* __restrict__ rec, size_t i, bool d5, R lam[5]) {
+__device__ inline void rec_lambdas(const R* __restrict__ rec, size_t i, R lam[5]) {
   const R* r = rec + i * REC;
-  R s0, s1, s2, s3, s4, c;
+  R s0, s1, s2, s3, s4, c, d;
   if constexpr (sizeof(R) == 4) {
-    // records are 32-byte aligned: one 16-byte and one 8-byte load
+    // records are 32-byte aligned: two 16-byte loads of one 32-byte sector
     const float4 lo = *reinterpret_cast<const float4*>(r);
-    const float2 hi = *reinterpret_cast<const float2*>(r + 4);
-    s0 = lo.x, s1 = lo.y, s2 = lo.z, s3 = lo.w, s4 = hi.x, c = hi.y;
+    const float4 hi = *reinterpret_cast<const float4*>(r + 4);
+    s0 = lo.x, s1 = lo.y, s2 = lo.z, s3 = lo.w, s4 = hi.x, c = hi.y, d = hi.z;
   } else {
     const double2 a = *reinterpret_cast<const double2*>(r);
     const double2 b = *reinterpret_cast<const double2*>(r + 2);
-    const double2 d = *reinterpret_cast<const double2*>(r + 4);
-    s0 = a.x, s1 = a.y, s2 = b.x, s3 = b.y, s4 = d.x, c = d.y;
+    const double2 e = *reinterpret_cast<const double2*>(r + 4);
+    const double2 f = *reinterpret_cast<const double2*>(r + 6);
+    s0 = a.x, s1 = a.y, s2 = b.x, s3 = b.y, s4 = e.x, c = e.y, d = f.x;
   }
-  R sum = ((s0 + s1) + s2) + s3;
-  if (d5) sum += s4;
-  const R corr = (c - sum) / (d5 ? R(5) : R(4));
+  const R sum = (((s0 + s1) + s2) + s3) + s4;
+  const R corr = (c - sum) / d;
   lam[0] = s0 + corr;
   lam[1] = s1 + corr;
   lam[2] = s2 + corr;
   lam[3] = s3 + corr;
-  lam[4] = d5 ? s4 + corr : R(0);
+  lam[4] = s4 + corr;
 }
 
 // FP64 sum of a 256-thread block in a fixed order: an xor butterfly inside
@@ -188,6 +190,7 @@ struct dm_ctx {
   int64_t nP = 0;
   DArr<int32_t> pv;        // nP*3
   DArr<int32_t> code;      // nP*4 (x class, x id, y class*8+pattern, y id)
+  DArr<uint8_t> elem_deg;  // nP: rows each element lies in (1 to 5)
 
   // full incidence A (rows: closedness | X projection | Y projection)
   int64_t n_rows_full = 0, n_closed_full = 0, nnz_full = 0;
@@ -211,7 +214,7 @@ struct dm_ctx {
   DArr<int32_t> rent_var;
   DArr<int8_t> rent_coef;
   DArr<uint32_t> rent_word;
-  DArr<uint8_t> var_deg;   // n_free
+  DArr<uint8_t> var_deg;   // n_free: rows of each free variable (1 to 5)
   int32_t n_chunks = 0;
   DArr<int4> chunk_desc;   // n_chunks wave chunks: (first row, rows, first entry, entries)
   DArr<unsigned long long> chunk_mask;  // per chunk: bit e set when entry e starts a row

@@ -5,7 +5,9 @@
 // record of REC reals: slots 0-2 for its three closedness rows (edges k = 0,
 // 1, 2 of the element), slot 3 for its first projection row, slot 4 for its
 // Y projection row when the element is triangle-triangle, slot 5 for the cost
-// c_i.  Two record buffers alternate between iterations.
+// c_i, slot 6 for its number of rows (a generic problem's variable takes slots
+// 0 to |J_i| - 1 in row order).  Two record buffers alternate between
+// iterations.
 //
 // One iteration is one kernel launch over every row of the presolved problem:
 //   1. each entry reads its variable's record from the previous iteration and
@@ -172,7 +174,7 @@ __device__ inline R seg_softmin(R x) {
 template <typename R>
 __device__ inline R cur_lambda(const R* __restrict__ rec, uint32_t w) {
   R lam[5];
-  rec_lambdas<R>(rec, size_t(w & W_VAR_MASK), (w & W_DEG5) != 0, lam);
+  rec_lambdas<R>(rec, size_t(w & W_VAR_MASK), lam);
   const int k = int((w >> W_SLOT_SHIFT) & 7u);
   return k == 0 ? lam[0] : k == 1 ? lam[1] : k == 2 ? lam[2] : k == 3 ? lam[3] : lam[4];
 }
@@ -771,12 +773,17 @@ __global__ void k_import(const R* lam, const uint32_t* word, int64_t nnz, R* rec
 }
 
 template <typename R>
-__global__ void k_set_cost(const int32_t* free_var, const double* c64, int64_t nfree, R* rec0, R* rec1) {
+__global__ void k_set_cost(const int32_t* free_var, const double* c64, const uint8_t* deg, int64_t nfree, R* rec0,
+                           R* rec1) {
   int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (i >= nfree) return;
-  R c = R(c64[free_var[i]]);
+  const R c = R(c64[free_var[i]]), d = R(deg[i]);
   rec0[size_t(i) * REC + REC_COST] = c;
-  if (rec1) rec1[size_t(i) * REC + REC_COST] = c;
+  rec0[size_t(i) * REC + REC_DEG] = d;
+  if (rec1) {
+    rec1[size_t(i) * REC + REC_COST] = c;
+    rec1[size_t(i) * REC + REC_DEG] = d;
+  }
 }
 
 template <typename R>
@@ -786,13 +793,13 @@ __global__ void k_export(const R* rec, const uint32_t* word, int64_t nnz, R* lam
 }
 
 template <typename R>
-__global__ void k_init_lambda(const uint32_t* word, const int32_t* free_var, const double* c64, int64_t nnz,
-                              R* lam) {
+__global__ void k_init_lambda(const uint32_t* word, const int32_t* free_var, const double* c64, const uint8_t* deg,
+                              int64_t nnz, R* lam) {
   int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (e >= nnz) return;
-  uint32_t w = word[e];
-  R c = R(c64[free_var[w & W_VAR_MASK]]);
-  lam[e] = c / ((w & W_DEG5) ? R(5) : R(4));
+  const uint32_t i = word[e] & W_VAR_MASK;
+  const R c = R(c64[free_var[i]]);
+  lam[e] = c / R(deg[i]);
 }
 
 __global__ void k_write_offset(double* out, double v) { *out = v; }
@@ -831,7 +838,7 @@ dm_status dual_import(dm_ctx* ctx, const R* lam, DArr<unsigned char>* bufs) {
   R* r1 = reinterpret_cast<R*>(bufs[1].p);
   if (ctx->n_free > 0)
     k_set_cost<R><<<grid_for(ctx->n_free, 256), 256, 0, ctx->stream>>>(ctx->free_var.p, ctx->cost64.p,
-                                                                       ctx->n_free, r0, r1);
+                                                                       ctx->var_deg.p, ctx->n_free, r0, r1);
   if (ctx->nnz > 0)
     k_import<R><<<grid_for(ctx->nnz, 256), 256, 0, ctx->stream>>>(lam, ctx->rent_word.p, ctx->nnz, r0);
   DM_LAUNCH_CHECK(ctx);
@@ -1025,10 +1032,10 @@ extern "C" dm_status dm_init_lambda(dm_ctx* ctx, int32_t msg_prec, void* lambda)
   if (ctx->nnz == 0) return DM_OK;
   if (msg_prec == DM_PREC_FP32)
     k_init_lambda<float><<<grid_for(ctx->nnz, 256), 256, 0, ctx->stream>>>(
-        ctx->rent_word.p, ctx->free_var.p, ctx->cost64.p, ctx->nnz, static_cast<float*>(lambda));
+        ctx->rent_word.p, ctx->free_var.p, ctx->cost64.p, ctx->var_deg.p, ctx->nnz, static_cast<float*>(lambda));
   else
     k_init_lambda<double><<<grid_for(ctx->nnz, 256), 256, 0, ctx->stream>>>(
-        ctx->rent_word.p, ctx->free_var.p, ctx->cost64.p, ctx->nnz, static_cast<double*>(lambda));
+        ctx->rent_word.p, ctx->free_var.p, ctx->cost64.p, ctx->var_deg.p, ctx->nnz, static_cast<double*>(lambda));
   DM_LAUNCH_CHECK(ctx);
   return DM_OK;
 }

@@ -2,19 +2,13 @@
 // other 0-1 problems, Appendix "Other ILPs"): min c^T x subject to A x = b,
 // x in {0,1}^n, every coefficient +1 or -1.  The rows are split as in the
 // matching problem: exactly-one rows (all +1, b = 1, any length) and short
-// rows (everything else, at most 64 entries).
+// rows (everything else, at most 64 entries).  The Lagrangean decomposition
+// is that of Eq. (D): one subproblem per input row, and a variable in d rows
+// (1 to 5) has d multipliers that sum to its cost.
 //
-// The solver's records hold four or five multipliers per variable, so a
-// variable in d < 4 rows gets rows x_i - x_i = 0 (its two entries are two
-// copies of x_i; the row is always satisfied): one for d = 2 or 3, two for
-// d = 1, which brings every degree to 4 or 5.  Each such row is one more
-// subproblem of the Lagrangean decomposition (Eq. (D)) over copies of the
-// variable, so every bound stays valid.
-//
-// Full row order: the short input rows in input order, then the padding rows
-// by variable, then the exactly-one input rows in input order.  A variable's
-// record slots follow its entries in that order (+1 before -1 within a
-// padding row).
+// Full row order: the short input rows in input order, then the exactly-one
+// input rows in input order.  A variable's record slots 0 to d - 1 follow its
+// entries in that row order.
 #include <algorithm>
 
 #include "dm_internal.h"
@@ -58,15 +52,6 @@ __global__ void k_ilp_rows(const int32_t* row_ptr, const int32_t* cols, const in
   len[j] = e - s;
 }
 
-// padding rows per variable: d = 1 -> 2, d = 2, 3 -> 1, d = 4, 5 -> 0
-__global__ void k_ilp_pad(const int32_t* deg, int32_t n_vars, int32_t* pad, int* err) {
-  const int32_t v = int32_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (v >= n_vars) return;
-  const int32_t d = deg[v];
-  if (d < 1 || d > 5) atomicOr(err, ERR_DEG);
-  pad[v] = d == 1 ? 2 : (d <= 3 ? 1 : 0);
-}
-
 // new position of every input row and the lengths of the full rows
 __global__ void k_ilp_place(const uint8_t* is_long, const int32_t* pos_short, const int32_t* pos_long,
                             const int32_t* len, int32_t n_rows, int32_t base_long, int32_t* new_row,
@@ -76,13 +61,6 @@ __global__ void k_ilp_place(const uint8_t* is_long, const int32_t* pos_short, co
   const int32_t r = is_long[j] ? base_long + pos_long[j] : pos_short[j];
   new_row[j] = r;
   new_len[r] = len[j];
-}
-
-__global__ void k_ilp_pad_len(const int32_t* pad, const int32_t* pos_pad, int32_t n_vars, int32_t base_pad,
-                              int32_t* new_len) {
-  const int32_t v = int32_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (v >= n_vars) return;
-  for (int k = 0; k < pad[v]; ++k) new_len[base_pad + pos_pad[v] + k] = 2;
 }
 
 __global__ void k_ilp_fill(const int32_t* row_ptr, const int32_t* cols, const int8_t* coefs, const int32_t* b,
@@ -99,40 +77,24 @@ __global__ void k_ilp_fill(const int32_t* row_ptr, const int32_t* cols, const in
   row_key[r] = j;
 }
 
-__global__ void k_ilp_fill_pad(const int32_t* pad, const int32_t* pos_pad, int32_t n_vars, int32_t base_pad,
-                               int32_t n_rows_in, const int32_t* full_ptr, int32_t* ent_var, int8_t* ent_coef,
-                               int32_t* row_b, int64_t* row_key) {
-  const int32_t v = int32_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (v >= n_vars) return;
-  for (int k = 0; k < pad[v]; ++k) {
-    const int32_t r = base_pad + pos_pad[v] + k, o = full_ptr[r];
-    ent_var[o] = v;
-    ent_coef[o] = 1;
-    ent_var[o + 1] = v;
-    ent_coef[o + 1] = -1;
-    row_b[r] = 0;
-    row_key[r] = int64_t(n_rows_in) + pos_pad[v] + k;
-  }
-}
-
-// sort key of entry e: (variable, row, -1 after +1); value e
-__global__ void k_ilp_slot_keys(const int32_t* full_ptr, const int32_t* ent_var, const int8_t* ent_coef,
-                                int32_t n_full_rows, uint64_t* key, int32_t* val) {
+// sort key of entry e: (variable, row); value e
+__global__ void k_ilp_slot_keys(const int32_t* full_ptr, const int32_t* ent_var, int32_t n_full_rows, uint64_t* key,
+                                int32_t* val) {
   const int32_t r = int32_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (r >= n_full_rows) return;
   for (int32_t e = full_ptr[r]; e < full_ptr[r + 1]; ++e) {
-    key[e] = (uint64_t(ent_var[e]) * uint64_t(n_full_rows) + uint64_t(r)) * 2u + (ent_coef[e] < 0 ? 1u : 0u);
+    key[e] = uint64_t(ent_var[e]) * uint64_t(n_full_rows) + uint64_t(r);
     val[e] = e;
   }
 }
 
 // slot of every entry: its rank among its variable's entries (sorted keys);
-// a repeated (variable, row, sign) is an input row that names a variable twice
+// a repeated (variable, row) is an input row that names a variable twice
 __global__ void k_ilp_slots(const uint64_t* key, const int32_t* val, int64_t nnz, int32_t n_full_rows,
                             uint8_t* slot, int* err) {
   const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (i >= nnz) return;
-  const uint64_t per_var = uint64_t(n_full_rows) * 2u;
+  const uint64_t per_var = uint64_t(n_full_rows);
   const uint64_t v = key[i] / per_var;
   int64_t lo = 0, hi = i;
   while (lo < hi) {
@@ -141,19 +103,16 @@ __global__ void k_ilp_slots(const uint64_t* key, const int32_t* val, int64_t nnz
     else hi = mid;
   }
   slot[val[i]] = uint8_t(i - lo);
-  if (i > 0 && key[i] == key[i - 1]) atomicOr(err, ERR_DUP);   // same variable, row and sign
+  if (i > 0 && key[i] == key[i - 1]) atomicOr(err, ERR_DUP);   // same variable and row
 }
 
-// the degree codes the reduction reads (a variable with five rows has code
-// words 0 and 0 at offsets 0 and 2; one with four rows has 1 and 0)
-__global__ void k_ilp_codes(const int32_t* deg, const int32_t* pad, int32_t n_vars, int32_t* code) {
+// rows of every variable (checked to be 1 to 5) as the element degree
+__global__ void k_ilp_deg(const int32_t* deg, int32_t n_vars, uint8_t* elem_deg, int* err) {
   const int32_t v = int32_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (v >= n_vars) return;
-  const int32_t d = deg[v] + 2 * pad[v];
-  code[4 * int64_t(v)] = d == 5 ? 0 : 1;
-  code[4 * int64_t(v) + 1] = 0;
-  code[4 * int64_t(v) + 2] = 0;
-  code[4 * int64_t(v) + 3] = 0;
+  const int32_t d = deg[v];
+  if (d < 1 || d > 5) atomicOr(err, ERR_DEG);
+  elem_deg[v] = uint8_t(d < 1 ? 1 : (d > 5 ? 5 : d));
 }
 
 __global__ void k_set_cost(const double* c, int64_t n, double* c64, float* c32, int* err) {
@@ -169,32 +128,30 @@ dm_status build_ilp(dm_ctx* ctx, int32_t n_vars, int32_t n_rows, int32_t total, 
                     const int32_t* cols, const int8_t* coefs, const int32_t* b) {
   hipStream_t st = ctx->stream;
   DArr<uint8_t> is_long, is_short;
-  DArr<int32_t> len, deg, pad, pos_short, pos_long, pos_pad, new_row;
+  DArr<int32_t> len, deg, pos_short, pos_long, new_row;
   DArr<int> err;
   DM_ALLOC(ctx, is_long, size_t(std::max(n_rows, 1)));
   DM_ALLOC(ctx, is_short, size_t(std::max(n_rows, 1)));
   DM_ALLOC(ctx, len, size_t(std::max(n_rows, 1)));
   DM_ALLOC(ctx, new_row, size_t(std::max(n_rows, 1)));
   DM_ALLOC(ctx, deg, size_t(n_vars));
-  DM_ALLOC(ctx, pad, size_t(n_vars));
   DM_ALLOC(ctx, pos_short, size_t(n_rows) + 1);
   DM_ALLOC(ctx, pos_long, size_t(n_rows) + 1);
-  DM_ALLOC(ctx, pos_pad, size_t(n_vars) + 1);
   DM_ALLOC(ctx, err, 1);
+  DM_ALLOC(ctx, ctx->elem_deg, size_t(n_vars));
   DM_HIP(ctx, hipMemsetAsync(deg.p, 0, sizeof(int32_t) * n_vars, st));
   DM_HIP(ctx, hipMemsetAsync(err.p, 0, sizeof(int), st));
   if (n_rows > 0)
     k_ilp_rows<<<grid_for(n_rows, 256), 256, 0, st>>>(row_ptr, cols, coefs, b, n_rows, n_vars, total,
                                                        is_long.p, is_short.p, len.p, deg.p, err.p);
-  k_ilp_pad<<<grid_for(n_vars, 256), 256, 0, st>>>(deg.p, n_vars, pad.p, err.p);
+  k_ilp_deg<<<grid_for(n_vars, 256), 256, 0, st>>>(deg.p, n_vars, ctx->elem_deg.p, err.p);
   DM_LAUNCH_CHECK(ctx);
   DM_TRY(scan_u8(ctx, is_short.p, pos_short.p, size_t(n_rows)));
   DM_TRY(scan_u8(ctx, is_long.p, pos_long.p, size_t(n_rows)));
-  DM_TRY(scan_i32(ctx, pad.p, pos_pad.p, size_t(n_vars)));
-  int32_t v[3];
+  int32_t v[2];
   {
-    const int32_t* src[3] = {err.p, pos_short.p + n_rows, pos_pad.p + n_vars};
-    DM_TRY(read_i32s(ctx, 3, src, v));
+    const int32_t* src[2] = {err.p, pos_short.p + n_rows};
+    DM_TRY(read_i32s(ctx, 2, src, v));
   }
   if (v[0] & ERR_PTR)
     return dm_fail(ctx, DM_ERR_INVALID_ARG,
@@ -205,23 +162,21 @@ dm_status build_ilp(dm_ctx* ctx, int32_t n_vars, int32_t n_rows, int32_t total, 
     return dm_fail(ctx, DM_ERR_WORKSPACE, "dm_build_ilp: a row that is not exactly-one has more than %d entries",
                    MAX_SHORT_ROW);
   if (v[0] & ERR_DEG) return dm_fail(ctx, DM_ERR_INVALID_ARG, "dm_build_ilp: a variable is in no row or in more than 5");
-  const int32_t n_short_in = v[1], n_pad = v[2];
-  const int32_t base_pad = n_short_in, base_long = n_short_in + n_pad;
-  const int64_t n_full = int64_t(n_rows) + n_pad;
+  const int32_t n_short_in = v[1];
+  const int64_t n_full = n_rows;
   // full row lengths and pointers
   DArr<int32_t> new_len;
   DM_ALLOC(ctx, new_len, size_t(std::max<int64_t>(n_full, 1)));
   DM_ALLOC(ctx, ctx->row_ptr, size_t(n_full) + 1);
   if (n_rows > 0)
     k_ilp_place<<<grid_for(n_rows, 256), 256, 0, st>>>(is_long.p, pos_short.p, pos_long.p, len.p, n_rows,
-                                                        base_long, new_row.p, new_len.p);
-  k_ilp_pad_len<<<grid_for(n_vars, 256), 256, 0, st>>>(pad.p, pos_pad.p, n_vars, base_pad, new_len.p);
+                                                        n_short_in, new_row.p, new_len.p);
   DM_LAUNCH_CHECK(ctx);
   DM_TRY(scan_i32(ctx, new_len.p, ctx->row_ptr.p, size_t(n_full)));
   int32_t nnz = 0;
   DM_TRY(read_i32(ctx, ctx->row_ptr.p + n_full, &nnz));
   ctx->nP = n_vars;
-  ctx->n_closed_full = base_long;
+  ctx->n_closed_full = n_short_in;
   ctx->n_rows_full = n_full;
   ctx->nnz_full = nnz;
   DM_ALLOC(ctx, ctx->row_key, size_t(std::max<int64_t>(n_full, 1)));
@@ -229,15 +184,11 @@ dm_status build_ilp(dm_ctx* ctx, int32_t n_vars, int32_t n_rows, int32_t total, 
   DM_ALLOC(ctx, ctx->ent_var, size_t(std::max(nnz, 1)));
   DM_ALLOC(ctx, ctx->ent_coef, size_t(std::max(nnz, 1)));
   DM_ALLOC(ctx, ctx->ent_slot, size_t(std::max(nnz, 1)));
-  DM_ALLOC(ctx, ctx->code, size_t(n_vars) * 4);
+  ctx->code.release();   // a generic problem has no element codes
   if (n_rows > 0)
     k_ilp_fill<<<grid_for(n_rows, 256), 256, 0, st>>>(row_ptr, cols, coefs, b, n_rows, new_row.p, ctx->row_ptr.p,
                                                        ctx->ent_var.p, ctx->ent_coef.p, ctx->row_b.p,
                                                        ctx->row_key.p);
-  k_ilp_fill_pad<<<grid_for(n_vars, 256), 256, 0, st>>>(pad.p, pos_pad.p, n_vars, base_pad, n_rows, ctx->row_ptr.p,
-                                                         ctx->ent_var.p, ctx->ent_coef.p, ctx->row_b.p,
-                                                         ctx->row_key.p);
-  k_ilp_codes<<<grid_for(n_vars, 256), 256, 0, st>>>(deg.p, pad.p, n_vars, ctx->code.p);
   DM_LAUNCH_CHECK(ctx);
   // record slots
   if (nnz > 0) {
@@ -245,11 +196,10 @@ dm_status build_ilp(dm_ctx* ctx, int32_t n_vars, int32_t n_rows, int32_t total, 
     DArr<int32_t> val;
     DM_ALLOC(ctx, key, size_t(nnz));
     DM_ALLOC(ctx, val, size_t(nnz));
-    k_ilp_slot_keys<<<grid_for(n_full, 256), 256, 0, st>>>(ctx->row_ptr.p, ctx->ent_var.p, ctx->ent_coef.p,
-                                                            int32_t(n_full), key.p, val.p);
+    k_ilp_slot_keys<<<grid_for(n_full, 256), 256, 0, st>>>(ctx->row_ptr.p, ctx->ent_var.p, int32_t(n_full), key.p,
+                                                            val.p);
     DM_LAUNCH_CHECK(ctx);
-    DM_TRY(sort_pairs_u64(ctx, key.p, val.p, size_t(nnz),
-                          bits_for(uint64_t(n_vars) * uint64_t(n_full) * 2u)));
+    DM_TRY(sort_pairs_u64(ctx, key.p, val.p, size_t(nnz), bits_for(uint64_t(n_vars) * uint64_t(n_full))));
     DM_HIP(ctx, hipMemsetAsync(err.p, 0, sizeof(int), st));
     k_ilp_slots<<<grid_for(nnz, 256), 256, 0, st>>>(key.p, val.p, nnz, int32_t(n_full), ctx->ent_slot.p, err.p);
     DM_LAUNCH_CHECK(ctx);

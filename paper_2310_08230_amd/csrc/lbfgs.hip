@@ -3,8 +3,8 @@
 //
 // Vectors with one value per multiplier (the subgradient g, the history pairs
 // s and y, the direction q / d) are five slot planes of n_free values: slot k
-// of variable i (k as in the records; slot 4 only for variables with five
-// rows, zero otherwise) at k * n_free + i, so every pass reads and writes
+// of variable i (k as in the records; slots at or above the variable's row
+// count are zero) at k * n_free + i, so every pass reads and writes
 // whole planes coalesced.  g and y only take the values 0/1 and -1/0/1 and
 // are stored as bytes, so a history pair costs 5 reals and 5 bytes per
 // variable.
@@ -79,12 +79,13 @@ __device__ inline double dot5(const double a[5], const double b[5]) {
   return (((a[0] * b[0] + a[1] * b[1]) + a[2] * b[2]) + a[3] * b[3]) + a[4] * b[4];
 }
 
-// subtract the mean over the variable's rows (slot 4 only with five rows)
-__device__ inline void project5(double v[5], bool d5) {
-  const double sum = (((v[0] + v[1]) + v[2]) + v[3]) + (d5 ? v[4] : 0.0);
-  const double mean = sum / (d5 ? 5.0 : 4.0);
-  for (int k = 0; k < 4; ++k) v[k] -= mean;
-  v[4] = d5 ? v[4] - mean : 0.0;
+// subtract the mean over the variable's d rows (slots 0 to d - 1; the others
+// stay zero)
+__device__ inline void project5(double v[5], int d) {
+  double sum = 0.0;
+  for (int k = 0; k < 5; ++k) sum += k < d ? v[k] : 0.0;
+  const double mean = sum / double(d);
+  for (int k = 0; k < 5; ++k) v[k] = k < d ? v[k] - mean : 0.0;
 }
 
 // ---------------------------------------------------------------- direction passes
@@ -94,7 +95,7 @@ __global__ __launch_bounds__(VB) void k_qn_project_g(const uint8_t* g8, const ui
   for (int64_t i = int64_t(blockIdx.x) * VB + threadIdx.x; i < n; i += int64_t(gridDim.x) * VB) {
     double v[5];
     load5_u8(g8, i, n, v);
-    project5(v, deg[i] == 5);
+    project5(v, deg[i]);
     store5<R>(d, i, n, v);
   }
 }
@@ -165,7 +166,7 @@ __global__ __launch_bounds__(VB) void k_qn_loop2(const R* q_in, const R* s, cons
       load5_i8(y_next, i, n, yv);
       acc += dot5(yv, qv);
     } else {
-      project5(qv, deg[i] == 5);
+      project5(qv, deg[i]);
     }
     store5<R>(q_out, i, n, qv);
   }
@@ -185,10 +186,9 @@ __global__ __launch_bounds__(VB) void k_qn_hist_pass(const R* rec_old, const R* 
   __shared__ double red[4];
   double a_sy = 0.0, a_yy = 0.0;
   for (int64_t i = int64_t(blockIdx.x) * VB + threadIdx.x; i < n; i += int64_t(gridDim.x) * VB) {
-    const bool d5 = deg[i] == 5;
     R lo[5], ln[5];
-    rec_lambdas<R>(rec_old, size_t(i), d5, lo);
-    rec_lambdas<R>(rec_new, size_t(i), d5, ln);
+    rec_lambdas<R>(rec_old, size_t(i), lo);
+    rec_lambdas<R>(rec_new, size_t(i), ln);
     double go[5], gn[5], sv[5], yv[5];
     load5_u8(g_old, i, n, go);
     load5_u8(g_new, i, n, gn);

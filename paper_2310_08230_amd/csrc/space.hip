@@ -379,7 +379,7 @@ __global__ void k_row_residual(const int32_t* row_ptr, const int32_t* ent_var, c
 
 __global__ void k_reduced_fill(const int32_t* row_ptr, const int32_t* ent_var, const int8_t* ent_coef,
                                const uint8_t* ent_slot, int64_t nrows, const int8_t* state,
-                               const int32_t* var_red, const int32_t* code, const int32_t* free_var,
+                               const int32_t* var_red, const int32_t* free_var,
                                const uint8_t* keep, const int32_t* new_id, const int32_t* cnt_excl,
                                const int32_t* resid, int32_t* rrow_orig, int32_t* rrow_ptr,
                                int32_t* rrow_b, int32_t* rent_var, int8_t* rent_coef,
@@ -396,11 +396,9 @@ __global__ void k_reduced_fill(const int32_t* row_ptr, const int32_t* ent_var, c
     if (state[v] >= 0) continue;
     int32_t rv = var_red[v];
     int a = ent_coef[i];
-    bool deg5 = code[4 * int64_t(v)] == 0 && (code[4 * int64_t(v) + 2] >> 3) == 0;
     rent_var[pos] = rv;
     rent_coef[pos] = int8_t(a);
-    rent_word[pos] = (a < 0 ? W_NEG : 0u) | (deg5 ? W_DEG5 : 0u) |
-                     (uint32_t(ent_slot[i]) << W_SLOT_SHIFT) | uint32_t(rv);
+    rent_word[pos] = (a < 0 ? W_NEG : 0u) | (uint32_t(ent_slot[i]) << W_SLOT_SHIFT) | uint32_t(rv);
     ++pos;
   }
 }
@@ -480,7 +478,7 @@ __global__ __launch_bounds__(256) void k_row_residual_proj(const int32_t* row_pt
 
 __global__ __launch_bounds__(256) void k_reduced_fill_proj(
     const int32_t* row_ptr, const int32_t* ent_var, const uint8_t* ent_slot, int64_t nc, const int8_t* state,
-    const int32_t* var_red, const int32_t* code, const uint8_t* keep, const int32_t* new_id,
+    const int32_t* var_red, const uint8_t* keep, const int32_t* new_id,
     const int32_t* cnt_excl, const int32_t* resid, int32_t* rrow_orig, int32_t* rrow_ptr, int32_t* rrow_b,
     int32_t* rent_var, int8_t* rent_coef, uint32_t* rent_word) {
   __shared__ int sh[4];
@@ -502,20 +500,27 @@ __global__ __launch_bounds__(256) void k_reduced_fill_proj(
     const int off = block_excl_flag(f, sh, &total);
     if (f) {
       const int32_t rv = var_red[v];
-      const bool deg5 = code[4 * int64_t(v)] == 0 && (code[4 * int64_t(v) + 2] >> 3) == 0;
       rent_var[pos + off] = rv;
       rent_coef[pos + off] = 1;
-      rent_word[pos + off] = (deg5 ? W_DEG5 : 0u) | (uint32_t(ent_slot[i]) << W_SLOT_SHIFT) | uint32_t(rv);
+      rent_word[pos + off] = (uint32_t(ent_slot[i]) << W_SLOT_SHIFT) | uint32_t(rv);
     }
     pos += total;
   }
 }
 
-__global__ void k_var_deg(const int32_t* free_var, const int32_t* code, int64_t n, uint8_t* deg) {
+__global__ void k_var_deg(const int32_t* free_var, const uint8_t* elem_deg, int64_t n, uint8_t* deg) {
   int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (i >= n) return;
-  int64_t p = free_var[i];
-  deg[i] = uint8_t(3 + (code[4 * p] == 0 ? 1 : 0) + ((code[4 * p + 2] >> 3) == 0 ? 1 : 0));
+  deg[i] = elem_deg[free_var[i]];
+}
+
+// rows of every product triangle: three closedness rows, plus the X projection
+// row when its X element is a face and the Y projection row when its Y
+// element is a face
+__global__ void k_elem_deg(const int32_t* code, int64_t n, uint8_t* deg) {
+  int64_t p = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (p >= n) return;
+  deg[p] = uint8_t(3 + (code[4 * p] == 0 ? 1 : 0) + ((code[4 * p + 2] >> 3) == 0 ? 1 : 0));
 }
 
 // flags[2]: longest short row; flags[3] bit 1: a row with < 2 entries, bit 0:
@@ -750,6 +755,8 @@ dm_status space_build(dm_ctx* ctx, const int32_t* cand_xy, const int32_t* cand_y
     DM_ALLOC(ctx, ctx->pv, size_t(nP) * 3);
     DM_ALLOC(ctx, ctx->code, size_t(nP) * 4);
     k_enum_fill<<<grid_for(g.Q, 256), 256, 0, st>>>(g, mask.p, off.p, ctx->pv.p, ctx->code.p);
+    DM_ALLOC(ctx, ctx->elem_deg, size_t(std::max<int64_t>(nP, 1)));
+    if (nP > 0) k_elem_deg<<<grid_for(nP, 256), 256, 0, st>>>(ctx->code.p, nP, ctx->elem_deg.p);
     DM_LAUNCH_CHECK(ctx);
   }
   const int64_t nP = ctx->nP;
@@ -946,18 +953,18 @@ dm_status presolve_reduce(dm_ctx* ctx, const int8_t* fix) {
   if (nc > 0)
     k_reduced_fill<<<grid_for(nc, 128), 128, 0, st>>>(
         ctx->row_ptr.p, ctx->ent_var.p, ctx->ent_coef.p, ctx->ent_slot.p, nc, ctx->state.p, ctx->var_red.p,
-        ctx->code.p, ctx->free_var.p, keep.p, new_id.p, cnt_excl.p, resid.p, ctx->rrow_orig.p, ctx->rrow_ptr.p,
+        ctx->free_var.p, keep.p, new_id.p, cnt_excl.p, resid.p, ctx->rrow_orig.p, ctx->rrow_ptr.p,
         ctx->rrow_b.p, ctx->rent_var.p, ctx->rent_coef.p, ctx->rent_word.p);
   if (nrows > nc)
     k_reduced_fill_proj<<<unsigned(nrows - nc), 256, 0, st>>>(
-      ctx->row_ptr.p, ctx->ent_var.p, ctx->ent_slot.p, nc, ctx->state.p, ctx->var_red.p, ctx->code.p, keep.p,
+      ctx->row_ptr.p, ctx->ent_var.p, ctx->ent_slot.p, nc, ctx->state.p, ctx->var_red.p, keep.p,
       new_id.p, cnt_excl.p, resid.p, ctx->rrow_orig.p, ctx->rrow_ptr.p, ctx->rrow_b.p, ctx->rent_var.p,
       ctx->rent_coef.p, ctx->rent_word.p);
   k_set_i32<<<1, 1, 0, st>>>(ctx->rrow_ptr.p, nr, rnnz);
   DM_LAUNCH_CHECK(ctx);
   DM_ALLOC(ctx, ctx->var_deg, size_t(std::max(nfree, 1)));
   if (nfree > 0)
-    k_var_deg<<<grid_for(nfree, 256), 256, 0, st>>>(ctx->free_var.p, ctx->code.p, nfree, ctx->var_deg.p);
+    k_var_deg<<<grid_for(nfree, 256), 256, 0, st>>>(ctx->free_var.p, ctx->elem_deg.p, nfree, ctx->var_deg.p);
   DM_HIP(ctx, hipMemsetAsync(err.p, 0, 4 * sizeof(int), st));
   if (nr > 0)
     k_row_stats<<<grid_for(nr, 256), 256, 0, st>>>(ctx->rrow_ptr.p, ctx->rrow_b.p, nshort, nr, err.p);

@@ -1,7 +1,7 @@
 """GPU generic 0-1 ILP path (Appendix "Other ILPs") against the oracle: the
-padded full problem and the presolved reduced problem are integer results
-and must agree exactly; FP64 bounds agree to rounding; rounding and the exact
-search are checked against HiGHS."""
+full problem (one subproblem per input row, Eq. (D)) and the presolved
+reduced problem are integer results and must agree exactly; FP64 bounds agree
+to rounding; rounding and the exact search are checked against HiGHS."""
 import numpy as np
 import pytest
 import torch
@@ -87,9 +87,8 @@ def test_ilp_errors_and_refused_calls():
 
 
 def test_ilp_smoothed_dual_parity():
-    """The smoothed dual on a generic ILP (padding rows run in the 8-lane
-    soft segments, side rows up to 16 lanes, assignment rows on the
-    exactly-one path)."""
+    """The smoothed dual on a generic ILP (side rows in the 8- and 16-lane
+    soft segments, assignment rows on the exactly-one path)."""
     S, ctx, _ = _both(20, 60, 1)
     T = 0.1
     r0 = S.lower_bound(S.init_lambda(), T)
