@@ -2,6 +2,7 @@
 traffic summary behind the roofline's `traffic` field, its guard against a
 changed sweep source, and the host description of the CPU baseline."""
 import csv
+import hashlib
 import json
 import os
 import shutil
@@ -42,16 +43,18 @@ def test_traffic_summary_scales_by_the_copy_calibration(tmp_path):
 
 
 def test_traffic_field_follows_the_profiled_source(tmp_path, monkeypatch):
-    committed = json.load(open(os.path.join(bench.ROOT, "profiles", "sweep_plain_fp32_500_hbm_traffic.json")))
-    # a copy of the tree's two inputs: the same source gives the stored figure
+    # a tree whose traffic summary was taken on its own sweep source gives the
+    # stored figure; once the source changes the counters no longer describe it
     (tmp_path / "profiles").mkdir()
     src_dir = tmp_path / "paper_2310_08230_amd" / "csrc"
     src_dir.mkdir(parents=True)
-    shutil.copy(os.path.join(bench.ROOT, "profiles", "sweep_plain_fp32_500_hbm_traffic.json"), tmp_path / "profiles")
     shutil.copy(os.path.join(bench.ROOT, "paper_2310_08230_amd", "csrc", "dual.hip"), src_dir)
+    sha = hashlib.sha256(open(src_dir / "dual.hip", "rb").read()).hexdigest()
+    rec = {"bytes_per_launch": 28401200, "dual_hip_sha256": sha}
+    with open(tmp_path / "profiles" / "sweep_plain_fp32_500_hbm_traffic.json", "w") as f:
+        json.dump(rec, f)
     monkeypatch.setattr(bench, "ROOT", str(tmp_path))
-    assert bench._traffic() == committed["bytes_per_launch"]
-    # a changed sweep source: the counters no longer describe it
+    assert bench._traffic() == 28401200
     with open(src_dir / "dual.hip", "a") as f:
         f.write("\n// changed\n")
     assert bench._traffic() is None
