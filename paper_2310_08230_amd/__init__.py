@@ -93,6 +93,12 @@ def lib():
             "dm_lbfgs_direction": [P, I32, I32, P, P, P, P],
             "dm_confident_fixing": [P, I32, P, D, P, P, P],
             "dm_fix_variables": [P, P, P],
+            "dm_build_ilp": [P, I32, I32, P, P, P, P, P],
+            "dm_set_costs": [P, P],
+            "dm_nearest_vertices": [P, P, I32, P, I32, P],
+            "dm_matched_pairs": [P, P, P, I32, P],
+            "dm_ring_candidates": [P, P, P, P, I32, I32, I32, P, P, P],
+            "dm_exact_search": [P, P, P, P, P, P, P, P, P],
         }
         for name, args in sig.items():
             fn = getattr(L, name)
@@ -131,6 +137,9 @@ class Context:
         self.h = h
         self.info = None
         self._keep = []
+        # counts the calls that replace the problem or its costs; a smoothed
+        # bound's backward pass must see the problem its forward pass solved
+        self.generation = 0
 
     def close(self):
         if getattr(self, "h", None):
@@ -143,7 +152,12 @@ class Context:
         except Exception:
             pass
 
+    _CHANGES_PROBLEM = frozenset(("dm_build_product_space", "dm_build_ilp", "dm_build_costs", "dm_set_costs",
+                                  "dm_fix_variables", "dm_exact_search"))
+
     def _call(self, name, *args):
+        if name in self._CHANGES_PROBLEM:
+            self.generation += 1
         L = lib()
         L.dm_set_stream(self.h, C.c_void_p(torch.cuda.current_stream(self.device).cuda_stream))
         st = getattr(L, name)(self.h, *args)
@@ -450,7 +464,9 @@ class SmoothedBound(torch.autograd.Function):
     forward(DX, DY, ctx_obj, iters, T, omega) builds the costs from DX, DY
     (FP32), runs ``iters`` smoothed Jacobi iterations from c/|J_i| and returns
     L_T as a 0-d float64 tensor; backward calls dm_smoothed_backward with the
-    final multipliers held as c/|J_i| + phi, phi fixed."""
+    final multipliers held as c/|J_i| + phi, phi fixed.  The backward pass
+    reads the context's costs and problem, so it refuses to run when the
+    context changed after the forward pass (Context.generation)."""
 
     @staticmethod
     def forward(fctx, DX, DY, dm: Context, iters: int, T: float, omega: float = 0.5, prec: str = "fp32"):
@@ -458,12 +474,16 @@ class SmoothedBound(torch.autograd.Function):
         lam = dm.init_lambda("fp32")
         dm.dual_solve(lam, iters, omega, T, trace=False)
         val = dm.lower_bound(lam, T)
-        fctx.dm, fctx.T = dm, T
+        fctx.dm, fctx.T, fctx.generation = dm, T, dm.generation
         fctx.save_for_backward(DX, DY, lam)
         return torch.tensor(val, dtype=torch.float64, device=DX.device)
 
     @staticmethod
     def backward(fctx, g):
         DX, DY, lam = fctx.saved_tensors
+        if fctx.dm.generation != fctx.generation:
+            raise RuntimeError("SmoothedBound.backward: the context's problem or costs changed after this "
+                               "forward pass (another forward, build or fixing on the same Context); use one "
+                               "Context per smoothed bound in a graph")
         _, gX, gY, _ = fctx.dm.smoothed_backward(lam, fctx.T, DX.detach(), DY.detach(), float(g))
         return gX.to(DX.dtype), gY.to(DY.dtype), None, None, None, None, None

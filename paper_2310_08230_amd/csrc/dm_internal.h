@@ -220,6 +220,17 @@ struct dm_ctx {
   DArr<unsigned long long> chunk_mask;  // per chunk: bit e set when entry e starts a row
   DArr<uint32_t> chunk_word;  // 64 per chunk: the chunk's entry words, CHUNK_PAD past its end
   DArr<int8_t> chunk_b;       // 64 per chunk: right-hand side of each entry's row
+  // launch layout of the hard sweep (layout.hip): short rows are packed into
+  // the chunks in region/key order; projection rows run in long_perm order;
+  // block b takes item xcd_item[(b % 8) * xcd_stride + b / 8] (-1: none)
+  int32_t long_wpr = 1;       // waves per projection row: 1 or 4 (4 rows or 1 row per block)
+  int32_t n_long_items = 0;   // projection-row blocks
+  int32_t xcd_stride = 0;
+  int32_t n_tiles = 0;        // 64-row tiles of short rows with b = 0 (one lane per row)
+  int32_t n_tile_items = 0;   // blocks of four tiles
+  DArr<uint32_t> tile_word;   // per tile 16 x 64 entry words: 8 slots of +1 entries, 8 of -1 entries
+  DArr<int32_t> long_perm;    // n_rows - n_short: projection rows (relative to n_short) in launch order
+  DArr<int32_t> xcd_item;     // 8 * xcd_stride
   DArr<int32_t> soft_row;     // short rows sorted (stably) by length, for the smoothed sweep
   int64_t soft_c8 = 0, soft_c16 = 0;   // how many of them have <= 7 / 8..15 entries
 
@@ -300,6 +311,7 @@ dm_status cost_offset(dm_ctx* ctx);   // offset = summed costs of elements fixed
 dm_status corner_lists(dm_ctx* ctx);  // corners per candidate pair (built once per product space)
 void fill_info(dm_ctx* ctx, dm_space_info* info);   // sizes of the current (reduced) problem
 dm_status presolve_reduce(dm_ctx* ctx, const int8_t* fix);  // presolve from fixings, reduced problem
+dm_status sweep_layout(dm_ctx* ctx);   // chunks, projection-row order and per-XCD items of the hard sweep
 
 // One sweep over all rows of the presolved problem (dual.hip).  Modes: update
 // the multipliers (rin -> out), write min-marginals (or soft marginals) per

@@ -219,12 +219,19 @@ struct SweepArgs {
   const unsigned long long* chunk_mask;   // bit e: entry e of the chunk starts a row
   const uint32_t* chunk_word;   // 64 words per chunk, CHUNK_PAD past its end
   const int8_t* chunk_b;        // 64 per chunk: right-hand side of the entry's row
-  int32_t n_short_blocks;
+  int32_t n_short_blocks;   // items of short rows (hard form: row tiles, then chunks)
+  int32_t n_tile_items;     // hard form: blocks of four 64-row tiles
+  int32_t n_tiles;
+  const uint32_t* tile_word;  // per tile: 16 x 64 entry words (slot j of lane l at j * 64 + l), CHUNK_PAD
   int32_t n_short;
   int32_t n_rows;
   int32_t n_items;          // short-row blocks + long-row blocks
   int32_t n_chunks;         // wave chunks of short rows (hard form)
   int32_t long_wpr;         // waves per projection row: 1 or 4
+  int32_t n_long;           // projection rows
+  const int32_t* long_perm; // projection rows (relative to n_short) in launch order
+  const int32_t* xcd_item;  // hard form: item of block b at (b % 8) * xcd_stride + b / 8, or -1
+  int32_t xcd_stride;
   double* partial;          // this launch's per-block partials
   const double* prev_partial; // previous launch's partials still to be summed, or NULL
   int32_t prev_n;
@@ -329,6 +336,70 @@ __device__ inline double short_chunk_hard(const SweepArgs& A, const R* __restric
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     constexpr int V = 16 / int(sizeof(R));   // values per 16-byte read
     using Vec = typename LdsVec<R>::type;
+    if (__ballot(act && b != 0) == 0ull) {   // uniform: every row of the chunk has b = 0
+      // Rows with b = 0 choose k entries of each sign.  With P and Q the
+      // sorted +1 and -1 groups, the pair sums p_(j) + q_(j) never decrease,
+      // so the minimiser takes the k* pairs with negative sums.  An entry of
+      // rank r (1-based, ties by lane) is taken iff the other group holds at
+      // least r values whose sum with it is negative.  Its min-marginal needs
+      // only the order statistics around k*: with U = min(p_(k*+1), -q_(k*))
+      // and V = min(q_(k*+1), -p_(k*)) (empty terms +inf),
+      //   taken +1: p - U,  left +1: p + V,  taken -1: q - V,  left -1: q + U,
+      // and the row minimum is the sum of the taken values.
+      int32_t rank = 0, cnt = 0;
+      if (act) {
+        const R nlam = -lam;
+        for (int a = s & ~(V - 1); a < s + n; a += V) {
+          const Vec v = *reinterpret_cast<const Vec*>(wave_vals + a);
+#pragma unroll
+          for (int u = 0; u < V; ++u) {
+            const int src = a + u;
+            const R lq = LdsVec<R>::get(v, u);
+            const int gq = int((negm >> src) & 1ull);
+            if (src >= s && src < s + n) {
+              if (gq == g) rank += (lq < lam) || (lq == lam && src < lane);
+              else cnt += lq < nlam;
+            }
+          }
+        }
+      }
+      const bool sel = act && cnt > rank;
+      // U collects left +1 and taken -1 entries, V left -1 and taken +1
+      // entries, each as +-lambda
+      const R t = sel ? -lam : lam;
+      R* uvals = wave_vals + 64;
+      R* vvals = wave_vals + 128;
+      uvals[lane] = (act && g == int(sel)) ? t : rinf<R>();
+      vvals[lane] = (act && g != int(sel)) ? t : rinf<R>();
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+      if (act) {
+        R U = rinf<R>(), Vv = rinf<R>();
+        if (MODE == MODE_UPDATE || MODE == MODE_EVAL) {
+          for (int a = s & ~(V - 1); a < s + n; a += V) {
+            const Vec uv = *reinterpret_cast<const Vec*>(uvals + a);
+            const Vec vv = *reinterpret_cast<const Vec*>(vvals + a);
+#pragma unroll
+            for (int u = 0; u < V; ++u) {
+              const int src = a + u;
+              if (src >= s && src < s + n) {
+                U = fmin(U, LdsVec<R>::get(uv, u));
+                Vv = fmin(Vv, LdsVec<R>::get(vv, u));
+              }
+            }
+          }
+          const R Wm = g == int(sel) ? Vv : U;
+          const R M = sel ? lam - Wm : lam + Wm;
+          if (MODE == MODE_UPDATE) write_out<R>(out, w, lam - omega * M);
+          if (MODE == MODE_EVAL) write_out<R>(out, w, M);
+        }
+        if (MODE == MODE_SUBGRAD) A.gsub[slot_index(A, w)] = uint8_t(sel ? 1 : 0);
+        if (sel) rowpart = double(lam);
+      }
+      return rowpart;
+    }
+    // general right-hand sides: the rank as above, then a sort of the chunk
     int32_t rank = 0;
     if (act) {
       for (int a = s & ~(V - 1); a < s + n; a += V) {   // a + V <= 64: the slice's end
@@ -439,15 +510,176 @@ __device__ inline double short_chunk_hard(const SweepArgs& A, const R* __restric
   return rowpart;
 }
 
-// the four waves of a block take four adjacent chunks (one chunk per wave
-// keeps the most waves in flight; batching chunks per wave measured slower)
+// the four waves of a block take four adjacent chunks
 template <typename R, int MODE>
 __device__ void short_wave_hard(const SweepArgs& A, const R* __restrict__ rin, R* __restrict__ out, R omega,
                                 R gam, unsigned char* smem, double* red, int32_t item) {
   const int wave = threadIdx.x >> 6;
-  R* wave_vals = reinterpret_cast<R*>(smem) + wave * 64;
-  const double rowpart = short_chunk_hard<R, MODE>(A, rin, out, omega, gam, item * 4 + wave, wave_vals);
+  R* wave_vals = reinterpret_cast<R*>(smem) + wave * 192;   // three 64-value slices per wave
+  const int32_t wc = (item - A.n_tile_items) * 4 + wave;
+  const double rowpart = short_chunk_hard<R, MODE>(A, rin, out, omega, gam, wc, wave_vals);
   double part = block_sum(rowpart, red);
+  store_partial(part, A.partial, item);
+}
+
+// ---------------------------------------------------------------- short rows with b = 0, one lane per row
+// Rows with right-hand side 0 and at most TILE_HALF entries of each sign run
+// one lane per row, 64 rows per wave (a tile): the row's +1 entries sit in
+// slots 0 to TILE_HALF - 1 and its -1 entries in the next TILE_HALF slots,
+// each group in row order; slot j of lane l is word j * 64 + l of the tile,
+// CHUNK_PAD where the group has ended.  The multipliers stay in registers and
+// the closed form of the b = 0 rows (see short_chunk_hard) is evaluated over
+// pairs: within a group the earlier entry's rank rises if it is larger, the
+// later one's if it is not smaller; across the groups both counts rise if the
+// pair sums to a negative value.  d = count - rank decides whether an entry
+// is taken (d > 0).  A missing entry holds +inf: it is never taken, never
+// ranked before a value and never pairs to a negative sum.
+constexpr int TILE_HALF = 8;
+
+// a multiplier record as loaded (two 16-byte loads for FP32, four for FP64)
+template <typename R>
+struct RecRaw;
+template <>
+struct RecRaw<float> {
+  float4 lo, hi;
+  __device__ void load(const float* __restrict__ rec, uint32_t i) {
+    lo = *reinterpret_cast<const float4*>(rec + size_t(i) * REC);
+    hi = *reinterpret_cast<const float4*>(rec + size_t(i) * REC + 4);
+  }
+  // lambda of slot k with dual feasibility restored, in the arithmetic of rec_lambdas
+  __device__ float lambda(int k) const {
+    const float sum = (((lo.x + lo.y) + lo.z) + lo.w) + hi.x;
+    const float corr = (hi.y - sum) / hi.z;
+    const float sk = k == 0 ? lo.x : k == 1 ? lo.y : k == 2 ? lo.z : k == 3 ? lo.w : hi.x;
+    return sk + corr;
+  }
+};
+template <>
+struct RecRaw<double> {
+  double2 a, b, c, d;
+  __device__ void load(const double* __restrict__ rec, uint32_t i) {
+    const double* r = rec + size_t(i) * REC;
+    a = *reinterpret_cast<const double2*>(r);
+    b = *reinterpret_cast<const double2*>(r + 2);
+    c = *reinterpret_cast<const double2*>(r + 4);
+    d = *reinterpret_cast<const double2*>(r + 6);
+  }
+  __device__ double lambda(int k) const {
+    const double sum = (((a.x + a.y) + b.x) + b.y) + c.x;
+    const double corr = (c.y - sum) / d.x;
+    const double sk = k == 0 ? a.x : k == 1 ? a.y : k == 2 ? b.x : k == 3 ? b.y : c.x;
+    return sk + corr;
+  }
+};
+
+template <typename R, int MODE>
+__device__ inline double tile_rows(const SweepArgs& A, const R* __restrict__ rin, R* __restrict__ out, R omega,
+                                   R gam, const uint32_t* __restrict__ tw) {
+  constexpr int H = TILE_HALF;
+  // records in flight per batch: every load of a batch is issued before the
+  // first one is used (a missing entry loads record 0 and is then replaced)
+  constexpr int B = sizeof(R) == 4 ? 4 : 2;
+  const int lane = threadIdx.x & 63;
+  uint32_t wv[2 * H];
+#pragma unroll
+  for (int j = 0; j < 2 * H; ++j) wv[j] = tw[j * 64 + lane];
+  R lam[2 * H];   // slots 0 to H - 1: +1 entries, H to 2H - 1: -1 entries
+#pragma unroll
+  for (int j0 = 0; j0 < 2 * H; j0 += B) {
+    RecRaw<R> raw[B];
+#pragma unroll
+    for (int u = 0; u < B; ++u) {
+      const uint32_t w = wv[j0 + u] != CHUNK_PAD ? wv[j0 + u] : 0u;
+      raw[u].load(rin, w & W_VAR_MASK);
+    }
+#pragma unroll
+    for (int u = 0; u < B; ++u) {
+      const uint32_t w = wv[j0 + u];
+      lam[j0 + u] = w != CHUNK_PAD ? raw[u].lambda(int((w >> W_SLOT_SHIFT) & 7u)) : rinf<R>();
+    }
+  }
+  if (A.dir) {   // uniform: rows see lambda + gamma * dir
+    R dv[2 * H];
+#pragma unroll
+    for (int j = 0; j < 2 * H; ++j)
+      dv[j] = static_cast<const R*>(A.dir)[slot_index(A, wv[j] != CHUNK_PAD ? wv[j] : 0u)];
+#pragma unroll
+    for (int j = 0; j < 2 * H; ++j)
+      if (wv[j] != CHUNK_PAD) lam[j] += gam * dv[j];
+  }
+  R* lp = lam;
+  R* lq = lam + H;
+  int32_t d[2 * H];
+#pragma unroll
+  for (int j = 0; j < 2 * H; ++j) d[j] = 0;
+  int32_t* dp = d;
+  int32_t* dq = d + H;
+#pragma unroll
+  for (int j = 1; j < H; ++j)
+#pragma unroll
+    for (int k = 0; k < j; ++k) {
+      const bool lep = lp[k] <= lp[j], leq = lq[k] <= lq[j];   // k is earlier: a tie ranks j after k
+      dp[j] -= lep ? 1 : 0;
+      dp[k] -= lep ? 0 : 1;
+      dq[j] -= leq ? 1 : 0;
+      dq[k] -= leq ? 0 : 1;
+    }
+#pragma unroll
+  for (int j = 0; j < H; ++j)
+#pragma unroll
+    for (int k = 0; k < H; ++k) {
+      const int ng = lp[j] + lq[k] < R(0) ? 1 : 0;   // the pair's sum (its sign is exact)
+      dp[j] += ng;
+      dq[k] += ng;
+    }
+  // U: left +1 and taken -1 entries, V: left -1 and taken +1 entries (as +-lambda)
+  R U = rinf<R>(), V = rinf<R>();
+  double rowmin = 0.0;
+#pragma unroll
+  for (int j = 0; j < H; ++j) {
+    if (dp[j] > 0) {
+      V = fmin(V, -lp[j]);
+      rowmin += double(lp[j]);
+    } else {
+      U = fmin(U, lp[j]);
+    }
+    if (dq[j] > 0) {
+      U = fmin(U, -lq[j]);
+      rowmin += double(lq[j]);
+    } else {
+      V = fmin(V, lq[j]);
+    }
+  }
+  if (MODE == MODE_UPDATE || MODE == MODE_EVAL || MODE == MODE_SUBGRAD) {
+#pragma unroll
+    for (int j = 0; j < 2 * H; ++j) {
+      const uint32_t w = wv[j];
+      if (w == CHUNK_PAD) continue;
+      const bool neg = j >= H;
+      const R lv = lam[j];
+      const bool sel = d[j] > 0;
+      if (MODE == MODE_SUBGRAD) {
+        A.gsub[slot_index(A, w)] = uint8_t(sel ? 1 : 0);
+      } else {
+        // taken +1: p - U, left +1: p + V, taken -1: q - V, left -1: q + U
+        const R Wm = neg == sel ? V : U;
+        const R M = sel ? lv - Wm : lv + Wm;
+        if (MODE == MODE_UPDATE) write_out<R>(out, w, lv - omega * M);
+        if (MODE == MODE_EVAL) write_out<R>(out, w, M);
+      }
+    }
+  }
+  return rowmin;
+}
+
+template <typename R, int MODE>
+__device__ void tile_block(const SweepArgs& A, const R* __restrict__ rin, R* __restrict__ out, R omega, R gam,
+                           double* red, int32_t item) {
+  const int32_t t = item * 4 + int32_t(threadIdx.x >> 6);
+  double rowpart = 0.0;
+  if (t < A.n_tiles)   // uniform across the wave
+    rowpart = tile_rows<R, MODE>(A, rin, out, omega, gam, A.tile_word + size_t(t) * (2 * TILE_HALF * 64));
+  const double part = block_sum(rowpart, red);
   store_partial(part, A.partial, item);
 }
 
@@ -592,6 +824,7 @@ __device__ inline MinState<R> ms_shfl_xor(MinState<R> v, int off) {
 // block per row (long_wpr = 4); each lane keeps up to LONG_REG of its row's
 // multipliers in registers between the two passes
 constexpr int LONG_REG = 8;
+constexpr int LONG_BATCH = 4;   // record loads in flight per lane
 constexpr int32_t LONG_GROUP = 8;   // consecutive projection-row blocks per XCD turn
 
 template <typename R, bool SOFT, int MODE>
@@ -602,9 +835,10 @@ __device__ void long_rows(const SweepArgs& A, const R* __restrict__ rin, R* __re
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int wpr = A.long_wpr;   // uniform
   const int sub = wave & (wpr - 1);
-  const int32_t j = A.n_short + (item - A.n_short_blocks) * (4 / wpr) + wave / wpr;
+  const int32_t lr = (item - A.n_short_blocks) * (4 / wpr) + wave / wpr;
+  const bool has = lr < A.n_long;
+  const int32_t j = has ? A.n_short + A.long_perm[lr] : 0;
   const int32_t step = 64 * wpr, i0 = sub * 64 + lane;
-  const bool has = j < A.n_rows;
   const int32_t s = has ? A.rrow_ptr[j] : 0;
   const int32_t n = has ? A.rrow_ptr[j + 1] - s : 0;
   MinState<R> st;
@@ -612,25 +846,41 @@ __device__ void long_rows(const SweepArgs& A, const R* __restrict__ rin, R* __re
   st.m2 = rinf<R>();
   st.s = R(0);
   st.a = INT32_MAX;
+  // The first LONG_REG entries of every lane are loaded without branches
+  // (past the row's end a lane loads the row's first entry and ignores it), so
+  // that all loads of a batch are in flight together: the words, then the
+  // records in batches of LONG_BATCH.
   uint32_t wv[LONG_REG];
   R lv[LONG_REG];
 #pragma unroll
   for (int u = 0; u < LONG_REG; ++u) {
     const int32_t i = i0 + step * u;
-    wv[u] = i < n ? A.word[s + i] : 0u;
+    wv[u] = n > 0 ? A.word[s + (i < n ? i : 0)] : 0u;
   }
 #pragma unroll
-  for (int u = 0; u < LONG_REG; ++u) {
-    const int32_t i = i0 + step * u;
-    lv[u] = R(0);
-    if (i < n) {
-      lv[u] = row_lambda<R>(A, rin, wv[u], gam);
-      MinState<R> one;
-      one.m = lv[u];
-      one.m2 = rinf<R>();
-      one.s = R(0);
-      one.a = i;
-      st = ms_combine<R, SOFT>(st, one, T);
+  for (int u0 = 0; u0 < LONG_REG; u0 += LONG_BATCH) {
+    if (sub * 64 + step * u0 >= n) break;   // uniform: no lane of the wave has entries left
+    RecRaw<R> raw[LONG_BATCH];
+#pragma unroll
+    for (int u = 0; u < LONG_BATCH; ++u) raw[u].load(rin, wv[u0 + u] & W_VAR_MASK);
+    R dv[LONG_BATCH];
+    if (A.dir)
+#pragma unroll
+      for (int u = 0; u < LONG_BATCH; ++u) dv[u] = static_cast<const R*>(A.dir)[slot_index(A, wv[u0 + u])];
+#pragma unroll
+    for (int u = 0; u < LONG_BATCH; ++u) {
+      const int32_t i = i0 + step * (u0 + u);
+      R v = raw[u].lambda(int((wv[u0 + u] >> W_SLOT_SHIFT) & 7u));
+      if (A.dir) v += gam * dv[u];
+      lv[u0 + u] = v;
+      if (i < n) {
+        MinState<R> one;
+        one.m = v;
+        one.m2 = rinf<R>();
+        one.s = R(0);
+        one.a = i;
+        st = ms_combine<R, SOFT>(st, one, T);
+      }
     }
   }
   for (int32_t i = i0 + step * LONG_REG; i < n; i += step) {   // rows longer than step * LONG_REG
@@ -715,7 +965,7 @@ __device__ void long_rows(const SweepArgs& A, const R* __restrict__ rin, R* __re
 
 template <typename R, bool SOFT>
 constexpr size_t smem_bytes() {
-  return SOFT ? (SOFT_FTAB + 256) * sizeof(R) + 256 : 256 * sizeof(R);
+  return SOFT ? (SOFT_FTAB + 256) * sizeof(R) + 256 : 768 * sizeof(R);
 }
 
 template <typename R, bool SOFT, int MODE>
@@ -727,41 +977,49 @@ __global__ __launch_bounds__(256) void k_sweep(SweepArgs A, const R* __restrict_
   if (blockIdx.x == 0 && A.prev_partial) reduce_partials(A.prev_partial, A.prev_n, A.prev_offset, A.prev_out, red);
   const R gam = A.gamma ? R(*A.gamma) : R(0);
   // Workgroups are dealt to the 8 XCDs round-robin (block b runs on XCD b % 8).
-  // Each XCD takes a contiguous range of short-row chunks, so rows that share
-  // variables share one L2, and projection-row blocks in groups of LONG_GROUP
-  // consecutive blocks (consecutive projection rows of one shape gather
-  // neighbouring records), group g of them on XCD g % 8; the heavier
-  // projection-row blocks come first on each XCD.
-  const int32_t x = int32_t(blockIdx.x % 8u), k = int32_t(blockIdx.x / 8u);
-  const int32_t n_long_blocks = A.n_items - A.n_short_blocks;
-  const int32_t lx = (n_long_blocks + 8 * LONG_GROUP - 1) / (8 * LONG_GROUP) * LONG_GROUP;
+  // The hard form takes the item of block b from the per-XCD table of the
+  // sweep layout (region b % 8, in key order).  The smoothed form gives each
+  // XCD a contiguous range of short-row blocks and projection-row blocks in
+  // groups of LONG_GROUP consecutive blocks, group g on XCD g % 8, the heavier
+  // projection-row blocks first.
+  const int32_t x = int32_t(blockIdx.x % 8u), k0 = int32_t(blockIdx.x / 8u);
+  if (!SOFT) {
+    if (k0 >= A.xcd_stride) return;
+    const int32_t item = A.xcd_item[x * A.xcd_stride + k0];
+    if (item < 0) return;
+    if (item < A.n_tile_items) tile_block<R, MODE>(A, rin, out, omega, gam, red, item);
+    else if (item < A.n_short_blocks) short_wave_hard<R, MODE>(A, rin, out, omega, gam, smem, red, item);
+    else long_rows<R, false, MODE>(A, rin, out, omega, T, gam, red, item);
+    return;
+  }
   int32_t item;
-  if (k < lx) {
-    const int32_t li = ((k / LONG_GROUP) * 8 + x) * LONG_GROUP + k % LONG_GROUP;
-    if (li >= n_long_blocks) return;
-    item = A.n_short_blocks + li;
-  } else {
-    const int32_t pc = (A.n_short_blocks + 7) / 8;
-    const int32_t c = x * pc + (k - lx);
-    if (k - lx >= pc || c >= A.n_short_blocks) return;
-    item = c;
+  {
+    const int32_t n_long_blocks = A.n_items - A.n_short_blocks;
+    const int32_t lx = (n_long_blocks + 8 * LONG_GROUP - 1) / (8 * LONG_GROUP) * LONG_GROUP;
+    if (k0 < lx) {
+      const int32_t li = ((k0 / LONG_GROUP) * 8 + x) * LONG_GROUP + k0 % LONG_GROUP;
+      if (li >= n_long_blocks) return;
+      item = A.n_short_blocks + li;
+    } else {
+      const int32_t pc = (A.n_short_blocks + 7) / 8;
+      const int32_t c = x * pc + (k0 - lx);
+      if (k0 - lx >= pc || c >= A.n_short_blocks) return;
+      item = c;
+    }
   }
   if (item < A.n_short_blocks) {
-    if (SOFT) {
-      const int32_t nb8 = (A.soft_c8 + soft_rpb<8>() - 1) / soft_rpb<8>();
-      const int32_t nb16 = (A.soft_c16 + soft_rpb<16>() - 1) / soft_rpb<16>();
-      const int32_t c816 = A.soft_c8 + A.soft_c16;
-      if (item < nb8)
-        short_rows_soft<R, MODE, 8>(A, rin, out, omega, T, smem, red, item, item, 0, A.soft_c8);
-      else if (item < nb8 + nb16)
-        short_rows_soft<R, MODE, 16>(A, rin, out, omega, T, smem, red, item, item - nb8, A.soft_c8, c816);
-      else
-        short_rows_soft<R, MODE, 32>(A, rin, out, omega, T, smem, red, item, item - nb8 - nb16, c816,
-                                     A.n_short);
-    }
-    else short_wave_hard<R, MODE>(A, rin, out, omega, gam, smem, red, item);
+    const int32_t nb8 = (A.soft_c8 + soft_rpb<8>() - 1) / soft_rpb<8>();
+    const int32_t nb16 = (A.soft_c16 + soft_rpb<16>() - 1) / soft_rpb<16>();
+    const int32_t c816 = A.soft_c8 + A.soft_c16;
+    if (item < nb8)
+      short_rows_soft<R, MODE, 8>(A, rin, out, omega, T, smem, red, item, item, 0, A.soft_c8);
+    else if (item < nb8 + nb16)
+      short_rows_soft<R, MODE, 16>(A, rin, out, omega, T, smem, red, item, item - nb8, A.soft_c8, c816);
+    else
+      short_rows_soft<R, MODE, 32>(A, rin, out, omega, T, smem, red, item, item - nb8 - nb16, c816,
+                                   A.n_short);
   } else {
-    long_rows<R, SOFT, MODE>(A, rin, out, omega, T, gam, red, item);
+    long_rows<R, true, MODE>(A, rin, out, omega, T, gam, red, item);
   }
 }
 
@@ -808,8 +1066,6 @@ __global__ __launch_bounds__(256) void k_reduce_last(const double* partial, int 
   __shared__ double red[256];
   reduce_partials(partial, n, offset, out, red);
 }
-
-constexpr int64_t LONG_BLOCK_ROW = 512;          // mean projection-row length for a block per row
 
 // one sweep launch; with timing events the launch records the kernel's own
 // start and end (hipExtLaunchKernelGGL), as a kernel trace does
@@ -880,12 +1136,18 @@ dm_status dual_sweep(dm_ctx* ctx, int mode, bool soft, const unsigned char* rin,
   const int64_t soft_blocks = (ctx->soft_c8 + soft_rpb<8>() - 1) / soft_rpb<8>() +
                               (ctx->soft_c16 + soft_rpb<16>() - 1) / soft_rpb<16>() +
                               (c32 + soft_rpb<32>() - 1) / soft_rpb<32>();
-  A.n_short_blocks = soft ? int32_t(soft_blocks) : int32_t((ctx->n_chunks + 3) / 4);
-  // projection rows of more than LONG_BLOCK_ROW entries on average get a whole block each
+  A.n_tile_items = soft ? 0 : ctx->n_tile_items;
+  A.n_tiles = ctx->n_tiles;
+  A.tile_word = ctx->tile_word.p;
+  A.n_short_blocks = soft ? int32_t(soft_blocks) : ctx->n_tile_items + int32_t((ctx->n_chunks + 3) / 4);
+  // projection rows: a wave each, or a whole block each when they are long
   const int64_t n_long = ctx->n_rows - ctx->n_short;
-  A.long_wpr = (n_long > 0 && (ctx->nnz - ctx->nnz_short) / n_long > LONG_BLOCK_ROW) ? 4 : 1;
-  const int64_t rows_per_long_block = 4 / A.long_wpr;
-  const int64_t n_long_blocks = (n_long + rows_per_long_block - 1) / rows_per_long_block;
+  A.long_wpr = ctx->long_wpr;
+  A.n_long = int32_t(n_long);
+  A.long_perm = ctx->long_perm.p;
+  A.xcd_item = ctx->xcd_item.p;
+  A.xcd_stride = ctx->xcd_stride;
+  const int64_t n_long_blocks = ctx->n_long_items;
   A.n_short = int32_t(ctx->n_short);
   A.n_rows = int32_t(ctx->n_rows);
   A.plane = ctx->n_free;
@@ -901,7 +1163,7 @@ dm_status dual_sweep(dm_ctx* ctx, int mode, bool soft, const unsigned char* rin,
     return DM_OK;
   }
   // two halves of the partial buffer alternate between consecutive launches
-  const int64_t cap = std::max<int64_t>((ctx->n_chunks + 3) / 4, soft_blocks) + n_long_blocks;
+  const int64_t cap = std::max<int64_t>(ctx->n_tile_items + (ctx->n_chunks + 3) / 4, soft_blocks) + n_long_blocks;
   if (ctx->partial.n < size_t(2 * cap)) {
     DM_TRY(dual_flush(ctx));
     DM_ALLOC(ctx, ctx->partial, size_t(2 * cap));
@@ -915,9 +1177,10 @@ dm_status dual_sweep(dm_ctx* ctx, int mode, bool soft, const unsigned char* rin,
   const R* ri = reinterpret_cast<const R*>(rin);
   R* ro = reinterpret_cast<R*>(out);
   A.n_items = int32_t(nblocks);
-  // 8 XCDs x (projection-row blocks per XCD + chunks per XCD), see k_sweep
+  // 8 XCDs x blocks per XCD, see k_sweep
   const int64_t long_slots = (n_long_blocks + 8 * LONG_GROUP - 1) / (8 * LONG_GROUP) * LONG_GROUP;
-  const unsigned grid = unsigned(8 * (long_slots + (A.n_short_blocks + 7) / 8));
+  const unsigned grid = soft ? unsigned(8 * (long_slots + (A.n_short_blocks + 7) / 8))
+                             : unsigned(8 * int64_t(ctx->xcd_stride));
   hipEvent_t e0 = nullptr, e1 = nullptr;
   if (ctx->timing) {
     while (ctx->ev_pool.size() < ctx->ev_used + 2) {

@@ -584,95 +584,6 @@ __global__ void k_len_bounds(const uint32_t* len, int64_t n, int32_t* bound) {
   if (len[i] <= 15 && nxt > 15) bound[1] = int32_t(i + 1);
 }
 
-// Short rows are packed greedily, in row order, into wave chunks of at most
-// 64 entries (one entry per lane, whole rows only).  The greedy walk runs in
-// parallel over segments of PACK_SEG entries: segment j holds the rows whose
-// first entry lies in [j*PACK_SEG, (j+1)*PACK_SEG).
-constexpr int PACK_SEG = 4096;
-
-__global__ void k_seg_rows(const int32_t* rrow_ptr, int64_t n_short, int32_t n_seg, int32_t* seg_row) {
-  int32_t j = int32_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (j > n_seg) return;
-  if (j == n_seg) {
-    seg_row[j] = int32_t(n_short);
-    return;
-  }
-  int64_t target = int64_t(j) * PACK_SEG;
-  int64_t lo = 0, hi = n_short;
-  while (lo < hi) {
-    int64_t mid = (lo + hi) >> 1;
-    if (rrow_ptr[mid] < target) lo = mid + 1;
-    else hi = mid;
-  }
-  seg_row[j] = int32_t(lo);
-}
-
-// fill == false: count the wave chunks of each segment; fill == true: write
-// their (first row, rows, first entry, entries) at the scanned offsets
-// per chunk, the positions (relative to its first entry) where its rows start
-__global__ void k_chunk_mask(const int4* desc, const int32_t* rrow_ptr, int32_t n_chunks,
-                             unsigned long long* mask) {
-  const int32_t c = int32_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (c >= n_chunks) return;
-  const int4 d = desc[c];
-  unsigned long long m = 0ull;
-  for (int32_t r = 0; r < d.y; ++r) m |= 1ull << (rrow_ptr[d.x + r] - d.z);
-  mask[c] = m;
-}
-
-// padded copy of every chunk: 64 entry words (CHUNK_PAD past the chunk's end)
-// and the right-hand side of each entry's row, so that a wave reads its
-// entries without first reading the chunk descriptor
-__global__ void k_chunk_pad(const int4* desc, const unsigned long long* mask, const uint32_t* word,
-                            const int32_t* rrow_b, int32_t n_chunks, uint32_t* pword, int8_t* pb) {
-  const int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (t >= int64_t(n_chunks) * 64) return;
-  const int32_t c = int32_t(t >> 6), e = int32_t(t & 63);
-  const int4 d = desc[c];
-  if (e < d.w) {
-    const unsigned long long below = mask[c] & (e == 63 ? ~0ull : ((2ull << e) - 1ull));
-    pword[t] = word[d.z + e];
-    pb[t] = int8_t(rrow_b[d.x + __popcll(below) - 1]);
-  } else {
-    pword[t] = CHUNK_PAD;
-    pb[t] = 0;
-  }
-}
-
-// One block per segment: the segment's row pointers are staged in LDS (a
-// segment starts at most PACK_SEG / 2 rows, since every presolved row has at
-// least two entries, which the caller checks first), then one thread walks
-// them.
-__global__ __launch_bounds__(256) void k_pack(const int32_t* seg_row, const int32_t* rrow_ptr, int32_t n_seg,
-                                              int32_t* count, const int32_t* offset, int4* desc, int fill) {
-  __shared__ int32_t rp[PACK_SEG / 2 + 1];
-  const int32_t j = blockIdx.x;
-  const int32_t rs = seg_row[j], nr = seg_row[j + 1] - rs;
-  if (nr > PACK_SEG / 2) return;   // excluded by the caller's check
-  for (int32_t i = threadIdx.x; i <= nr; i += blockDim.x) rp[i] = rrow_ptr[rs + i];
-  __syncthreads();
-  if (threadIdx.x != 0) return;
-  int32_t r = 0, c = 0, o = fill ? offset[j] : 0;
-  while (r < nr) {
-    const int32_t q0 = r, e0 = rp[r];
-    // extend the chunk while the next row still fits, eight row pointers per step
-    for (;;) {
-      int32_t v[8];
-#pragma unroll
-      for (int u = 0; u < 8; ++u) v[u] = r + 1 + u <= nr ? rp[r + 1 + u] : INT32_MAX;
-      int adv = 0;
-#pragma unroll
-      for (int u = 0; u < 8; ++u)
-        if (adv == u && r + u < nr && v[u] - e0 <= 64) adv = u + 1;
-      r += adv;
-      if (adv < 8) break;
-    }
-    if (fill) desc[o + c] = make_int4(rs + q0, r - q0, e0, rp[r] - e0);
-    ++c;
-  }
-  if (!fill) count[j] = c;
-}
-
 }  // namespace
 
 dm_status space_build(dm_ctx* ctx, const int32_t* cand_xy, const int32_t* cand_yx, int32_t K) {
@@ -982,34 +893,7 @@ dm_status presolve_reduce(dm_ctx* ctx, const int8_t* fix) {
   int32_t nnz_short = 0;
   DM_TRY(read_i32(ctx, ctx->rrow_ptr.p + nshort, &nnz_short));
   ctx->nnz_short = nnz_short;
-  const int32_t n_seg = int32_t((int64_t(nnz_short) + PACK_SEG - 1) / PACK_SEG);
-  DArr<int32_t> seg_row, seg_cnt, seg_off;
-  DM_ALLOC(ctx, seg_row, size_t(n_seg) + 1);
-  DM_ALLOC(ctx, seg_cnt, size_t(std::max(n_seg, 1)));
-  DM_ALLOC(ctx, seg_off, size_t(n_seg) + 1);
-  k_seg_rows<<<grid_for(n_seg + 1, 256), 256, 0, st>>>(ctx->rrow_ptr.p, nshort, n_seg, seg_row.p);
-  if (n_seg > 0)
-    k_pack<<<unsigned(n_seg), 256, 0, st>>>(seg_row.p, ctx->rrow_ptr.p, n_seg, seg_cnt.p, nullptr, nullptr, 0);
-  DM_LAUNCH_CHECK(ctx);
-  DM_TRY(scan_i32(ctx, seg_cnt.p, seg_off.p, size_t(n_seg)));
-  int32_t n_chunks = 0;
-  DM_TRY(read_i32(ctx, seg_off.p + n_seg, &n_chunks));
-  ctx->n_chunks = n_chunks;
-  DM_ALLOC(ctx, ctx->chunk_desc, size_t(std::max(n_chunks, 1)));
-  if (n_seg > 0)
-    k_pack<<<unsigned(n_seg), 256, 0, st>>>(seg_row.p, ctx->rrow_ptr.p, n_seg, nullptr, seg_off.p,
-                                            ctx->chunk_desc.p, 1);
-  DM_ALLOC(ctx, ctx->chunk_mask, size_t(std::max(n_chunks, 1)));
-  if (n_chunks > 0)
-    k_chunk_mask<<<grid_for(n_chunks, 256), 256, 0, st>>>(ctx->chunk_desc.p, ctx->rrow_ptr.p, n_chunks,
-                                                          ctx->chunk_mask.p);
-  DM_ALLOC(ctx, ctx->chunk_word, size_t(std::max(n_chunks, 1)) * 64);
-  DM_ALLOC(ctx, ctx->chunk_b, size_t(std::max(n_chunks, 1)) * 64);
-  if (n_chunks > 0)
-    k_chunk_pad<<<grid_for(int64_t(n_chunks) * 64, 256), 256, 0, st>>>(
-        ctx->chunk_desc.p, ctx->chunk_mask.p, ctx->rent_word.p, ctx->rrow_b.p, n_chunks, ctx->chunk_word.p,
-        ctx->chunk_b.p);
-  DM_LAUNCH_CHECK(ctx);
+  DM_TRY(sweep_layout(ctx));
   // the smoothed sweep takes short rows in order of length, in segments of
   // 8, 16 or 32 lanes
   DArr<uint32_t> len;

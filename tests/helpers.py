@@ -171,3 +171,11 @@ def milp_optimum(S):
     res = milp(c, constraints=LinearConstraint(A, b, b), integrality=np.ones(n), bounds=Bounds(0, 1))
     return res.fun + S.offset if res.status == 0 else None
 
+
+
+def bf16_rne(a):
+    """Round float32 values to bfloat16 (round to nearest, ties to even),
+    returned as float32."""
+    u = np.ascontiguousarray(a, np.float32).view(np.uint32).astype(np.uint64)
+    u = (u + (((u >> 16) & 1) + 0x7FFF)) & 0xFFFF0000
+    return u.astype(np.uint32).view(np.float32)

@@ -30,3 +30,12 @@ def test_binding_exposes_abi_names():
     for n in ("build_product_space", "build_costs", "dual_solve", "round_primal", "lower_bound",
               "SmoothedBound", "Context"):
         assert hasattr(m, n)
+
+
+def test_binding_sets_argtypes_for_every_entry_point():
+    """Every declared entry point has its argument types set, so ctypes
+    converts the Python integers and pointers exactly as the header says."""
+    import paper_2310_08230_amd as m
+    L = m.lib()
+    missing = [n for n in _declared() if getattr(L, n).argtypes is None]
+    assert not missing, missing

@@ -5,7 +5,7 @@ import pytest
 import torch
 
 from gpu_common import both, dm, np_, say
-from helpers import full_candidates
+from helpers import bf16_rne, full_candidates
 from oracle import oracle as O
 from synth import make_pair, meshes, tiny_pair
 
@@ -185,14 +185,6 @@ def test_knn_candidates(cfg, prec):
     assert near_ties <= (2 if prec == "fp32" else 0.2 * (len(p.DX) + len(p.DY)))
 
 
-def _bf16_rne(a):
-    """Round float32 values to bfloat16 (round to nearest, ties to even),
-    returned as float32: the inputs the BF16 distance products see."""
-    u = np.ascontiguousarray(a, np.float32).view(np.uint32).astype(np.uint64)
-    u = (u + (((u >> 16) & 1) + 0x7FFF)) & 0xFFFF0000
-    return u.astype(np.uint32).view(np.float32)
-
-
 @pytest.mark.parametrize("case", ["cfg2", "cfg3", "d16", "d72", "d200"])
 def test_knn_bf16_matches_rounded_inputs(case):
     """BF16 candidates against the oracle run on the same BF16-rounded
@@ -213,7 +205,7 @@ def test_knn_bf16_matches_rounded_inputs(case):
         K = 8
     ctx = dm().Context(0)
     cxy, cyx = ctx.knn_candidates(torch.from_numpy(DX), torch.from_numpy(DY), K, "bf16")
-    BX, BY = _bf16_rne(DX), _bf16_rne(DY)
+    BX, BY = bf16_rne(DX), bf16_rne(DY)
     rxy, ryx = O.knn(BX, BY, K)
     bx, by = BX.astype(np.float64), BY.astype(np.float64)
     D2 = (bx ** 2).sum(1)[:, None] + (by ** 2).sum(1)[None] - 2.0 * bx @ by.T
