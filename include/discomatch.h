@@ -78,21 +78,45 @@ typedef struct {
 } dm_space_info;
 
 /* Create a context on HIP device `device`; work is enqueued on `hip_stream`
- * (a hipStream_t, may be NULL for the default stream).  The context's device
- * memory is allocated and freed stream-ordered on that stream (the device's
- * default memory pool, set to keep freed memory for reuse), so the stream
- * must stay valid until dm_destroy.  The release threshold is a property of
- * that pool for the whole process: memory freed to it stays reserved for
- * later stream-ordered allocations (of this library or any other user of
- * the default pool) until the process ends or the pool is trimmed
- * (hipMemPoolTrimTo); PyTorch's caching allocator does not draw from it. */
+ * (a hipStream_t, may be NULL for the default stream).  The memory the
+ * library allocates itself (the build steps' arrays and temporaries, and the
+ * solver state unless the caller supplies it with dm_set_workspace) comes
+ * stream-ordered, on that stream, from a memory pool that the context creates
+ * for itself and destroys in dm_destroy; the pool keeps freed blocks for the
+ * context's later calls and leaves the device's default pool untouched.  The
+ * stream must stay valid until dm_destroy.  Errors: DM_ERR_INVALID_ARG (no
+ * such device), DM_ERR_HIP (the pool or pinned host slots could not be
+ * created). */
 dm_status dm_create(int32_t device, void* hip_stream, dm_ctx** out);
+/* Destroys ctx: synchronises its stream, frees what the library allocated
+ * and destroys the context's pool; caller workspaces are not touched. */
 dm_status dm_destroy(dm_ctx* ctx);
 /* Message of the last error on ctx (empty string if none); owned by ctx. */
 const char* dm_last_error(const dm_ctx* ctx);
 /* Rebind the stream used by later calls; when it changes, the previous
  * stream is synchronised first. */
 dm_status dm_set_stream(dm_ctx* ctx, void* hip_stream);
+
+/* Caller-owned solver state (the "Ownership" of the C ABI: device buffers
+ * may come from the caller, e.g. PyTorch tensors).  After a problem is built
+ * (dm_build_product_space or dm_build_ilp, and after dm_fix_variables) the
+ * Jacobi solver's state of one message precision has a known size:
+ * dm_workspace_query gives it for stage DM_WS_SOLVE_FP32 or DM_WS_SOLVE_FP64
+ * (two multiplier record buffers of n_free x 8 reals and the per-block bound
+ * partials of a sweep).  dm_set_workspace hands the library a device buffer
+ * of at least that many bytes, 256-byte aligned: from then on dm_dual_solve,
+ * dm_lbfgs_solve and the sweeps of that precision keep their records and
+ * partials there instead of allocating them.  The caller owns the buffer,
+ * keeps it alive while it is attached and does not touch it between calls;
+ * the library reads and writes it only on the context's stream.  ptr = NULL
+ * detaches (the library allocates again).  A later problem may need more:
+ * the solver calls then return DM_ERR_WORKSPACE until a larger buffer is
+ * attached.  Errors: DM_ERR_INVALID_ARG (unknown stage, misaligned buffer),
+ * DM_ERR_STATE (no problem built), DM_ERR_WORKSPACE (buffer too small).
+ * Neither call synchronises. */
+enum { DM_WS_SOLVE_FP32 = 0, DM_WS_SOLVE_FP64 = 1 };
+dm_status dm_workspace_query(const dm_ctx* ctx, int32_t stage, size_t* bytes);
+dm_status dm_set_workspace(dm_ctx* ctx, int32_t stage, void* ptr, size_t bytes);
 
 /* Candidate vertex pairs (A2).  Distances d(m,n) = ||F_X(m) - F_Y(n)||_2 from
  * a tiled GEMM (prec = DM_PREC_BF16: BF16 MFMA on descriptors rounded to BF16

@@ -99,6 +99,8 @@ def lib():
             "dm_matched_pairs": [P, P, P, I32, P],
             "dm_ring_candidates": [P, P, P, P, I32, I32, I32, P, P, P],
             "dm_exact_search": [P, P, P, P, P, P, P, P, P],
+            "dm_workspace_query": [P, I32, P],
+            "dm_set_workspace": [P, I32, P, C.c_size_t],
         }
         for name, args in sig.items():
             fn = getattr(L, name)
@@ -163,6 +165,32 @@ class Context:
         st = getattr(L, name)(self.h, *args)
         if st != DM_OK:
             raise DMError(st, L.dm_last_error(self.h).decode())
+
+    # -- caller-owned solver state ----------------------------------------
+    WS_STAGE = {"fp32": 0, "fp64": 1}
+
+    def workspace_bytes(self, msg_prec="fp32"):
+        """Bytes of the Jacobi solver state of one message precision for the
+        current problem (dm_workspace_query)."""
+        n = C.c_size_t(0)
+        st = lib().dm_workspace_query(self.h, self.WS_STAGE[msg_prec], C.byref(n))
+        if st != DM_OK:
+            raise DMError(st, "dm_workspace_query failed (is a problem built?)")
+        return n.value
+
+    def set_workspace(self, msg_prec="fp32", buf=None):
+        """Keep the solver state of one message precision in ``buf``, a device
+        tensor owned by the caller (at least workspace_bytes(msg_prec) bytes,
+        256-byte aligned, e.g. torch.empty(n, dtype=torch.uint8, device=...));
+        None detaches.  The context holds a reference while attached."""
+        if buf is None:
+            self._call("dm_set_workspace", self.WS_STAGE[msg_prec], None, 0)
+            self._ws = {k: v for k, v in getattr(self, "_ws", {}).items() if k != msg_prec}
+            return
+        nbytes = buf.numel() * buf.element_size()
+        self._call("dm_set_workspace", self.WS_STAGE[msg_prec], C.c_void_p(buf.data_ptr()), nbytes)
+        self._ws = dict(getattr(self, "_ws", {}))
+        self._ws[msg_prec] = buf
 
     # -- A2 -------------------------------------------------------------
     def knn_candidates(self, DX, DY, K, prec="fp32"):

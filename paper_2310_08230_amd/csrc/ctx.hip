@@ -26,26 +26,35 @@ extern "C" dm_status dm_create(int32_t device, void* hip_stream, dm_ctx** out) {
   int n = 0;
   if (hipGetDeviceCount(&n) != hipSuccess || device < 0 || device >= n) return DM_ERR_INVALID_ARG;
   if (hipSetDevice(device) != hipSuccess) return DM_ERR_HIP;
-  // keep memory freed to the device's pool for reuse instead of returning it
-  // at every synchronisation (the library's temporaries come and go per call)
+  // the context's own memory pool: it keeps the blocks the library frees for
+  // reuse (the build steps' temporaries come and go per call) until
+  // dm_destroy, and leaves the device's default pool as it was
+  hipMemPoolProps props;
+  std::memset(&props, 0, sizeof(props));
+  props.allocType = hipMemAllocationTypePinned;
+  props.handleTypes = hipMemHandleTypeNone;
+  props.location.type = hipMemLocationTypeDevice;
+  props.location.id = device;
   hipMemPool_t pool = nullptr;
-  if (hipDeviceGetDefaultMemPool(&pool, device) == hipSuccess && pool) {
-    uint64_t keep = UINT64_MAX;
-    (void)hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &keep);
-  }
+  if (hipMemPoolCreate(&pool, &props) != hipSuccess || !pool) return DM_ERR_HIP;
+  uint64_t keep = UINT64_MAX;
+  (void)hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &keep);
   dm_ctx* c = new dm_ctx();
   c->device = device;
   c->stream = static_cast<hipStream_t>(hip_stream);
+  c->pool = pool;
   // pinned landing slots for small device-to-host reads
   if (hipHostMalloc(reinterpret_cast<void**>(&c->host_i32), HOST_SLOTS * sizeof(int32_t), hipHostMallocDefault) !=
       hipSuccess) {
     delete c;
+    (void)hipMemPoolDestroy(pool);
     return DM_ERR_HIP;
   }
   // device address of the allocation-free entry point's scratch array
   if (knn_scratch_init(c) != DM_OK) {
     (void)hipHostFree(c->host_i32);
     delete c;
+    (void)hipMemPoolDestroy(pool);
     return DM_ERR_HIP;
   }
   *out = c;
@@ -57,7 +66,11 @@ extern "C" dm_status dm_destroy(dm_ctx* ctx) {
   (void)hipSetDevice(ctx->device);
   (void)hipStreamSynchronize(ctx->stream);
   if (ctx->host_i32) (void)hipHostFree(ctx->host_i32);
-  delete ctx;
+  hipMemPool_t pool = ctx->pool;
+  hipStream_t st = ctx->stream;
+  delete ctx;   // frees every owned array on the stream
+  (void)hipStreamSynchronize(st);
+  if (pool) (void)hipMemPoolDestroy(pool);
   return DM_OK;
 }
 

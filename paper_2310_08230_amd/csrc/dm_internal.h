@@ -33,37 +33,47 @@ dm_status dm_fail(dm_ctx* ctx, dm_status code, const char* fmt, ...);
 #define DM_LAUNCH_CHECK(ctx) DM_HIP(ctx, hipGetLastError())
 
 // ---------------------------------------------------------------------------
-// owned device array.  Allocations and frees are stream-ordered on the
-// context's stream (hipMallocAsync / hipFreeAsync from the device's memory
-// pool, which keeps freed memory for reuse): the temporaries of the build
-// steps cost no device-wide synchronisation.  A block freed on a stream is
-// reused only by work ordered after the free on that stream.
+// device array.  An owned array is allocated and freed stream-ordered on the
+// context's stream from the context's own memory pool (hipMallocFromPoolAsync
+// / hipFreeAsync; the pool keeps freed blocks for reuse until dm_destroy), so
+// the temporaries of the build steps cost no device-wide synchronisation and
+// no other user of the device's default pool is affected.  A block freed on
+// a stream is reused only by work ordered after the free on that stream.  A
+// view (attach) borrows caller memory and never frees it.
 // ---------------------------------------------------------------------------
 template <typename T>
 struct DArr {
   T* p = nullptr;
   size_t n = 0;
   hipStream_t s = nullptr;   // stream the block was allocated on
+  bool view = false;         // borrowed memory: never freed here
   DArr() = default;
   DArr(const DArr&) = delete;
   DArr& operator=(const DArr&) = delete;
   ~DArr() { release(); }
   void release() {
-    if (p) (void)hipFreeAsync(p, s);
+    if (p && !view) (void)hipFreeAsync(p, s);
     p = nullptr;
     n = 0;
+    view = false;
   }
-  hipError_t resize(size_t count, hipStream_t stream) {
-    if (count == n && p) return hipSuccess;
+  hipError_t resize(size_t count, hipStream_t stream, hipMemPool_t pool) {
+    if (count == n && p && !view) return hipSuccess;
     release();
     n = count;
     s = stream;
     if (count == 0) return hipSuccess;
-    return hipMallocAsync(reinterpret_cast<void**>(&p), count * sizeof(T), stream);
+    return hipMallocFromPoolAsync(reinterpret_cast<void**>(&p), count * sizeof(T), pool, stream);
+  }
+  void attach(T* ptr, size_t count) {
+    release();
+    p = ptr;
+    n = count;
+    view = true;
   }
 };
 
-#define DM_ALLOC(ctx, arr, count) DM_HIP(ctx, (arr).resize(count, (ctx)->stream))
+#define DM_ALLOC(ctx, arr, count) DM_HIP(ctx, (arr).resize(count, (ctx)->stream, (ctx)->pool))
 
 struct MeshDev {
   int32_t nv = 0, nf = 0, ne = 0;
@@ -171,7 +181,12 @@ constexpr int HOST_SLOTS = 16;
 struct dm_ctx {
   int device = 0;
   hipStream_t stream = nullptr;
+  hipMemPool_t pool = nullptr;   // the context's own pool (every DArr allocation)
   std::string err;
+  // caller-owned solver workspace per message precision (0 FP32, 1 FP64),
+  // see dm_set_workspace; NULL when the library allocates the state itself
+  void* ws_ptr[2] = {nullptr, nullptr};
+  size_t ws_bytes[2] = {0, 0};
 
   MeshDev X, Y;
   int32_t K = 0;
@@ -307,6 +322,12 @@ dm_status check_finite(dm_ctx* ctx, const float* a, int64_t na, const float* b, 
 // takes this device's address of the scratch array of dm_knn_candidates_noalloc (once per device)
 dm_status knn_scratch_init(dm_ctx* ctx);
 dm_status dual_flush(dm_ctx* ctx);  // write the bound of the last sweep launch
+// layout of the Jacobi solver's state in a caller workspace: two record
+// buffers, then the sweep partials; sizes for the current problem
+struct SolverLayout {
+  size_t rec_bytes, part_off, part_count, total;
+};
+SolverLayout solver_layout(const dm_ctx* ctx, size_t real_bytes);
 dm_status cost_offset(dm_ctx* ctx);   // offset = summed costs of elements fixed to 1 (synchronises)
 dm_status corner_lists(dm_ctx* ctx);  // corners per candidate pair (built once per product space)
 void fill_info(dm_ctx* ctx, dm_space_info* info);   // sizes of the current (reduced) problem

@@ -1083,11 +1083,53 @@ void launch_sweep(hipStream_t st, unsigned grid, hipEvent_t e0, hipEvent_t e1, c
 // ============================================================================
 // host side (shared with rounding and the backward pass)
 // ============================================================================
+// per-launch partials of one sweep (hard and smoothed forms): the partial
+// buffer holds two halves of this many doubles
+static int64_t sweep_partial_cap(const dm_ctx* ctx) {
+  const int64_t c32 = ctx->n_short - ctx->soft_c8 - ctx->soft_c16;
+  const int64_t soft_blocks = (ctx->soft_c8 + soft_rpb<8>() - 1) / soft_rpb<8>() +
+                              (ctx->soft_c16 + soft_rpb<16>() - 1) / soft_rpb<16>() +
+                              (c32 + soft_rpb<32>() - 1) / soft_rpb<32>();
+  return std::max<int64_t>(int64_t(ctx->n_tile_items) + (ctx->n_chunks + 3) / 4, soft_blocks) +
+         ctx->n_long_items;
+}
+
+static size_t align256(size_t b) { return (b + 255) / 256 * 256; }
+
+SolverLayout solver_layout(const dm_ctx* ctx, size_t real_bytes) {
+  SolverLayout L;
+  L.rec_bytes = align256(size_t(std::max<int64_t>(ctx->n_free, 1)) * REC * real_bytes);
+  L.part_off = 2 * L.rec_bytes;
+  L.part_count = size_t(2 * std::max<int64_t>(sweep_partial_cap(ctx), 1));
+  L.total = L.part_off + align256(L.part_count * sizeof(double));
+  return L;
+}
+
+// the caller's workspace of this precision, checked against the current
+// problem (NULL when none is attached)
+static dm_status solver_workspace(dm_ctx* ctx, size_t real_bytes, unsigned char** base, SolverLayout* L) {
+  const int k = real_bytes == 4 ? 0 : 1;
+  *base = static_cast<unsigned char*>(ctx->ws_ptr[k]);
+  *L = solver_layout(ctx, real_bytes);
+  if (*base && ctx->ws_bytes[k] < L->total)
+    return dm_fail(ctx, DM_ERR_WORKSPACE, "the attached %s solver workspace has %zu bytes; the current problem needs %zu",
+                   k == 0 ? "FP32" : "FP64", ctx->ws_bytes[k], L->total);
+  return DM_OK;
+}
+
 template <typename R>
 dm_status dual_import(dm_ctx* ctx, const R* lam, DArr<unsigned char>* bufs) {
   const size_t bytes = size_t(std::max<int64_t>(ctx->n_free, 1)) * REC * sizeof(R);
-  DM_ALLOC(ctx, bufs[0], bytes);
-  DM_ALLOC(ctx, bufs[1], bytes);
+  unsigned char* ws = nullptr;
+  SolverLayout L;
+  if (bufs == ctx->rec) DM_TRY(solver_workspace(ctx, sizeof(R), &ws, &L));
+  if (ws) {   // the solver's records live in the caller's workspace
+    bufs[0].attach(ws, bytes);
+    bufs[1].attach(ws + L.rec_bytes, bytes);
+  } else {
+    DM_ALLOC(ctx, bufs[0], bytes);
+    DM_ALLOC(ctx, bufs[1], bytes);
+  }
   DM_HIP(ctx, hipMemsetAsync(bufs[0].p, 0, bytes, ctx->stream));
   DM_HIP(ctx, hipMemsetAsync(bufs[1].p, 0, bytes, ctx->stream));
   R* r0 = reinterpret_cast<R*>(bufs[0].p);
@@ -1162,9 +1204,19 @@ dm_status dual_sweep(dm_ctx* ctx, int mode, bool soft, const unsigned char* rin,
     DM_LAUNCH_CHECK(ctx);
     return DM_OK;
   }
-  // two halves of the partial buffer alternate between consecutive launches
-  const int64_t cap = std::max<int64_t>(ctx->n_tile_items + (ctx->n_chunks + 3) / 4, soft_blocks) + n_long_blocks;
-  if (ctx->partial.n < size_t(2 * cap)) {
+  // two halves of the partial buffer alternate between consecutive launches;
+  // with a caller workspace of this precision they live there
+  const int64_t cap = sweep_partial_cap(ctx);
+  unsigned char* ws = nullptr;
+  SolverLayout L;
+  DM_TRY(solver_workspace(ctx, sizeof(R), &ws, &L));
+  if (ws) {
+    double* want = reinterpret_cast<double*>(ws + L.part_off);
+    if (ctx->partial.p != want || ctx->partial.n < size_t(2 * cap)) {
+      DM_TRY(dual_flush(ctx));
+      ctx->partial.attach(want, L.part_count);
+    }
+  } else if (ctx->partial.view || ctx->partial.n < size_t(2 * cap)) {
     DM_TRY(dual_flush(ctx));
     DM_ALLOC(ctx, ctx->partial, size_t(2 * cap));
   }
@@ -1324,4 +1376,37 @@ extern "C" dm_status dm_lower_bound(dm_ctx* ctx, const void* lambda, double temp
   if (msg_prec == DM_PREC_FP32)
     return bound_impl<float>(ctx, static_cast<const float*>(lambda), float(temperature), lb);
   return bound_impl<double>(ctx, static_cast<const double*>(lambda), temperature, lb);
+}
+
+extern "C" dm_status dm_workspace_query(const dm_ctx* ctx, int32_t stage, size_t* bytes) {
+  if (!ctx || !bytes) return DM_ERR_INVALID_ARG;
+  if (stage != DM_WS_SOLVE_FP32 && stage != DM_WS_SOLVE_FP64) return DM_ERR_INVALID_ARG;
+  if (!ctx->has_space) return DM_ERR_STATE;
+  *bytes = solver_layout(ctx, stage == DM_WS_SOLVE_FP32 ? 4 : 8).total;
+  return DM_OK;
+}
+
+extern "C" dm_status dm_set_workspace(dm_ctx* ctx, int32_t stage, void* ptr, size_t bytes) {
+  if (!ctx) return DM_ERR_INVALID_ARG;
+  ctx->err.clear();
+  if (stage != DM_WS_SOLVE_FP32 && stage != DM_WS_SOLVE_FP64)
+    return dm_fail(ctx, DM_ERR_INVALID_ARG, "dm_set_workspace: unknown stage %d", stage);
+  const int k = stage == DM_WS_SOLVE_FP32 ? 0 : 1;
+  DM_HIP(ctx, hipSetDevice(ctx->device));
+  DM_TRY(dual_flush(ctx));   // a pending bound may still read the old partials
+  if (ptr) {
+    if (reinterpret_cast<uintptr_t>(ptr) % 256 != 0)
+      return dm_fail(ctx, DM_ERR_INVALID_ARG, "dm_set_workspace: the buffer must be 256-byte aligned");
+    if (!ctx->has_space) return dm_fail(ctx, DM_ERR_STATE, "dm_set_workspace: no problem built");
+    const size_t need = solver_layout(ctx, k == 0 ? 4 : 8).total;
+    if (bytes < need)
+      return dm_fail(ctx, DM_ERR_WORKSPACE, "dm_set_workspace: %zu bytes given, %zu needed", bytes, need);
+  }
+  // the solver's state moves: its own arrays (or views of the old buffer) go
+  ctx->rec[0].release();
+  ctx->rec[1].release();
+  ctx->partial.release();
+  ctx->ws_ptr[k] = ptr;
+  ctx->ws_bytes[k] = ptr ? bytes : 0;
+  return DM_OK;
 }
