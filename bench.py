@@ -6,13 +6,16 @@ costs (A4), initial multipliers (A5), the Jacobi dual iterations with the FP64
 bound trace (A6-A8), rounding to an exactly checked primal and the gap
 (A9, A10).  The default workload is the 500-face plain-FP32 pair (64-d
 descriptors, K = 16, 1000 iterations).  ``value`` is dual iterations per
-second of whole-step wall time.
+second of whole-step wall time.  Gaps use a certified bound: the FP64 dual
+objective at the multipliers re-projected onto dual feasibility.
 
 Also reported (same JSON line): the dominant kernel's roofline (the sweep
 kernel: algorithmic bytes per launch / its average launch duration from HIP
-events around each launch), the FP64 oracle timed on a bounded sample on the
-host, and time-to-1%-gap of the plain FP32, mixed (BF16 costs) and
-differentiable (smoothed T = 0.1, with the backward pass) forms.
+events around each launch), the sweep at the other pairs, time-to-1%-gap of
+the plain FP32, mixed (BF16 costs) and differentiable (smoothed T = 0.1 with
+the backward pass) forms on the same pairs, the largest pair's full pipeline
+timed end to end, a plain copy's bandwidth against the HBM peak, and the
+FP64 oracle on the host (seconds per iteration and time to a 1 % gap).
 """
 from __future__ import annotations
 
@@ -42,12 +45,13 @@ def parse():
     ap.add_argument("--config", type=int, default=2)
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--iters", type=int, default=None)
+    ap.add_argument("--k", type=int, default=None, help="candidates per vertex (default: the config's K)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-gap", action="store_true")
     ap.add_argument("--no-pairs", action="store_true", help="skip the per-pair sweep rooflines")
     ap.add_argument("--no-search", action="store_true", help="skip the exact-search timing")
-    ap.add_argument("--cpu-sample-iters", type=int, default=100)
-    ap.add_argument("--gap-seeds", default="0,1,2,3,4", help="seeds of the time-to-1%%-gap runs (median reported)")
+    ap.add_argument("--cpu-sample-iters", type=int, default=20)
+    ap.add_argument("--gap-seeds", default="0,1,2", help="seeds of the time-to-1%%-gap runs (median reported)")
     return ap.parse_args()
 
 
@@ -85,8 +89,10 @@ class Workload:
         out = {"lam": lam, "trace": tr}
         if with_round:
             x, pobj, feas, rounds = c.round_primal(lam, seed=0)
-            dmax = float(tr.max()) if self.iters else c.lower_bound(lam)
-            out.update(pobj=pobj, feasible=feas, rounds=rounds,
+            # certified bound: the FP64 dual objective at the multipliers
+            # re-projected onto dual feasibility with the FP64 costs
+            dmax = c.lower_bound(lam.double())
+            out.update(pobj=pobj, feasible=feas, rounds=rounds, bound=dmax,
                        gap=(pobj - dmax) / pobj if pobj else 0.0)
         return out
 
@@ -225,62 +231,137 @@ def sweep_roofline(cfg, seed, iters=200, temperature=0.0, **over):
             "frac": round(gbs / HBM_PEAK_GBS, 4)}
 
 
-def time_to_gap(cfg, seed, smoothed=False, check_every=50, max_iters=2000, smooth_iters=50, solver="jacobi",
-                qn_check_every=10, qn_max_iters=400, **over):
+FORMS = {
+    # name: (distance / cost precision, smoothed start with the backward pass)
+    "plain_fp32": ("fp32", False),
+    "mixed_bf16": ("bf16", False),
+    "diff_t0.1": ("bf16", True),
+}
+
+
+def time_to_gap(cfg, seed, form="plain_fp32", check_every=10, max_iters=3000, smooth_iters=50, solver="jacobi",
+                qn_check_every=10, qn_max_iters=400, rounds=10, **over):
     """Wall time from the first dual iteration until a rounding reaches a
-    primal-dual gap <= 1e-2 (rounding time included); build excluded.
+    primal-dual gap <= 1e-2 (roundings and bound checks included; build
+    excluded), for one of the three forms on one pair:
 
-    solver "jacobi": rounding every ``check_every`` Jacobi iterations;
-    "lbfgs": the quasi-Newton powered MMA (Alg. 1), rounding every
-    ``qn_check_every`` iterations (each iteration costs about eight sweeps),
-    the search state resumed between checks.
+      plain_fp32  FP32 distances and costs, FP32 messages;
+      mixed_bf16  BF16 MFMA distances (FP32 accumulation), FP32 messages;
+      diff_t0.1   as mixed, preceded by ``smooth_iters`` smoothed iterations
+                  at T = 0.1 and one backward pass to the descriptors (their
+                  time included), hard iterations from the smoothed
+                  multipliers.
 
-    Differentiable form: ``smooth_iters`` smoothed iterations at the config's
-    temperature and one backward pass to the descriptors come first (their
-    time is included and reported), then hard iterations continue from the
-    smoothed multipliers.  The bound is always the hard dual objective (valid
-    at any multipliers); the best gap is reported if 1 % is not reached."""
+    Every ``check_every`` Jacobi iterations (solver "jacobi") or
+    ``qn_check_every`` quasi-Newton iterations (solver "lbfgs", the search
+    state resumed between checks) the multipliers are rounded with ``rounds``
+    perturbation rounds.  The bound is certified: the FP64 dual objective at
+    the FP32 multipliers re-projected onto dual feasibility with the FP64
+    costs (Eq. (D) holds at any feasible multipliers), maximised over the
+    checks; d_max and p are both in FP64."""
     import torch
+    prec, smoothed = FORMS[form]
     w = Workload(cfg, seed, **over)
     c = w.ctx
-    cxy, cyx = c.knn_candidates(w.DX, w.DY, w.spec.k, w.knn_prec)
+    cxy, cyx = c.knn_candidates(w.DX, w.DY, w.spec.k, "bf16" if prec == "bf16" else "fp32")
     c.build_product_space(w.VX, w.FX, w.VY, w.FY, cxy, cyx)
-    c.build_costs(w.DX, w.DY, w.cost)
-    lam = c.init_lambda(w.msg)
+    c.build_costs(w.DX, w.DY, prec)
+    lam = c.init_lambda("fp32")
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    out = {}
+    out = {"form": form, "solver": solver}
     if smoothed:
-        T = w.spec.temperature
+        T = 0.1
         lam, _ = c.dual_solve(lam, smooth_iters, w.spec.omega, T, trace=False)
         _, gX, gY, LT = c.smoothed_backward(lam, T, w.DX, w.DY)
         torch.cuda.synchronize()
-        out.update(smooth_seconds=round(time.perf_counter() - t0, 6), smooth_iters=smooth_iters,
-                   L_T=LT, hard_bound_after_smoothing=c.lower_bound(lam, 0.0))
+        out.update(smooth_seconds=round(time.perf_counter() - t0, 6), smooth_iters=smooth_iters, L_T=LT)
     dmax = -float("inf")
     it = 0
     best = None
     cap = qn_max_iters if solver == "lbfgs" else max_iters
     while it < cap:
         if solver == "lbfgs":
-            lam, tr, _, _ = c.lbfgs_solve(lam, qn_check_every, omega=w.spec.omega, resume=it > 0)
+            lam, _, _, _ = c.lbfgs_solve(lam, qn_check_every, omega=w.spec.omega, resume=it > 0)
             it += qn_check_every
         else:
-            lam, tr = c.dual_solve(lam, check_every, w.spec.omega, 0.0)
+            lam, _ = c.dual_solve(lam, check_every, w.spec.omega, 0.0, trace=False)
             it += check_every
-        dmax = max(dmax, float(tr.max()))
-        _, pobj, feas, _ = c.round_primal(lam, rounds=10, seed=0)
+        dmax = max(dmax, c.lower_bound(lam.double()))
+        _, pobj, feas, _ = c.round_primal(lam, rounds=rounds, seed=0)
         if feas:
             g = (pobj - dmax) / pobj
             best = g if best is None else min(best, g)
             if g <= 1e-2:
                 torch.cuda.synchronize()
-                out.update(seconds=round(time.perf_counter() - t0, 6), iters=it, gap=g)
+                out.update(seconds=round(time.perf_counter() - t0, 6), iters=it, gap=g, bound=dmax, primal=pobj)
                 return out
     torch.cuda.synchronize()
     out.update(seconds=None, iters=it, gap=None, best_gap=best, bound=dmax,
                note="1% gap not reached within the iteration cap")
     return out
+
+
+def pipeline_run(cfg=5, seed=0, iters=None, T=0.1):
+    """The full pipeline on one pair, timed end to end with a synchronisation
+    after each stage: BF16 candidates, product space + presolve, BF16 costs,
+    FP32 Jacobi iterations with the FP64 bound trace, the certified FP64
+    bound, rounding, and the smoothed backward pass (one soft sweep at the
+    final multipliers and the chain to both descriptor sets)."""
+    import torch
+    w = Workload(cfg, seed, iters)
+    c = w.ctx
+    stages = {}
+
+    def mark(name, t):
+        torch.cuda.synchronize()
+        now = time.perf_counter()
+        stages[name] = round(now - t, 6)
+        return now
+
+    torch.cuda.synchronize()
+    t0 = t = time.perf_counter()
+    cxy, cyx = c.knn_candidates(w.DX, w.DY, w.spec.k, "bf16")
+    t = mark("candidates_bf16", t)
+    info = c.build_product_space(w.VX, w.FX, w.VY, w.FY, cxy, cyx)
+    t = mark("product_space_presolve", t)
+    c.build_costs(w.DX, w.DY, "bf16")
+    t = mark("costs_bf16", t)
+    lam, tr = c.dual_solve(c.init_lambda("fp32"), w.iters, w.spec.omega)
+    t = mark("jacobi_fp32", t)
+    lb = c.lower_bound(lam.double())
+    t = mark("certified_bound_fp64", t)
+    x, pobj, feas, _ = c.round_primal(lam, seed=0)
+    t = mark("rounding", t)
+    _, gX, gY, LT = c.smoothed_backward(lam, T, w.DX, w.DY)
+    t = mark("smoothed_backward", t)
+    return {"pair": f"{w.spec.faces_x}/{w.spec.faces_y} faces, K={w.spec.k}, D={w.spec.dim}, seed {seed}",
+            "nnz": info["nnz"], "jacobi_iters": w.iters, "seconds": round(t - t0, 6), "stages": stages,
+            "bound_certified": lb, "bound_trace_max": float(tr.max()), "primal": pobj, "feasible": feas,
+            "gap": (pobj - lb) / pobj if feas and pobj else None, "L_T": LT,
+            "grad_finite": bool(torch.isfinite(gX).all() and torch.isfinite(gY).all())}
+
+
+def copy_bandwidth(nbytes=1 << 31, reps=10):
+    """Achieved bandwidth of a plain device-to-device copy (the runtime's copy
+    kernel) of ``nbytes`` bytes: read + written bytes over the time of
+    ``reps`` copies between HIP events; the reference for the 8 TB/s HBM
+    peak."""
+    import torch
+    src = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(reps):
+        dst.copy_(src)
+    e1.record()
+    torch.cuda.synchronize()
+    s = e0.elapsed_time(e1) / 1e3
+    gbs = 2 * nbytes * reps / s / 1e9
+    return {"bytes": nbytes, "reps": reps, "achieved_GBps": round(gbs, 1), "peak_GBps": HBM_PEAK_GBS,
+            "frac": round(gbs / HBM_PEAK_GBS, 4)}
 
 
 def _traffic(n_launch_bytes_note=None):
@@ -300,22 +381,46 @@ def _traffic(n_launch_bytes_note=None):
     return rec.get("bytes_per_launch")
 
 
-def cpu_baseline(cfg, seed, iters):
-    """The FP64 oracle (single thread) on a bounded sample of the workload:
-    candidates, product space, presolve, costs and ``iters`` Jacobi
-    iterations; reported in dual iterations per second of that wall time."""
+def cpu_baseline(cfg, seed, iters, runs=3, gap_cap_s=3600.0, check_every=10, rounds=10):
+    """The FP64 oracle (single thread, its build excluded) on the same pair:
+    seconds per Jacobi iteration as the median of ``runs`` runs of ``iters``
+    iterations, reported as iterations per second; and its time to a 1 %
+    gap with the GPU's schedule (rounding with ``rounds`` rounds every
+    ``check_every`` iterations), capped at ``gap_cap_s`` seconds."""
+    import statistics
+
     from oracle import oracle as O
     from synth import make_pair
     p = make_pair(cfg, seed)
-    t0 = time.perf_counter()
     cxy, cyx = O.knn(p.DX, p.DY, p.spec.k)
     S = O.Space(p.VX, p.FX, p.VY, p.FY, cxy, cyx)
     S.costs(p.DX, p.DY)
-    S.dual_solve(iters)
-    dt = time.perf_counter() - t0
-    return {"value": iters / dt, "unit": "dual iterations/s", "cores": 1, "kind": "oracle",
-            "sample": f"FP64 oracle, same pair (config {cfg}, seed {seed}): candidates, product space, "
-                      f"presolve, costs and {iters} Jacobi iterations in {dt:.1f} s",
+    per_it = []
+    for _ in range(runs):
+        t0 = time.perf_counter()
+        S.dual_solve(iters)
+        per_it.append((time.perf_counter() - t0) / iters)
+    s_it = statistics.median(per_it)
+    # time to a 1 % gap
+    t0 = time.perf_counter()
+    lam, dmax, it, gap = None, -float("inf"), 0, None
+    while time.perf_counter() - t0 < gap_cap_s:
+        lam, tr = S.dual_solve(check_every, lam=lam)
+        it += check_every
+        dmax = max(dmax, float(tr.max()))
+        _, pobj, feas, _ = S.round(lam, R=rounds)
+        if feas and (pobj - dmax) / pobj <= 1e-2:
+            gap = (pobj - dmax) / pobj
+            break
+    ttg = time.perf_counter() - t0
+    return {"value": round(1.0 / s_it, 3), "unit": "dual iterations/s", "cores": 1, "kind": "oracle",
+            "sample": f"FP64 oracle on the same pair (config {cfg}, seed {seed}), build excluded: median of "
+                      f"{runs} runs of {iters} Jacobi iterations, {s_it:.4f} s per iteration "
+                      f"({', '.join(f'{x:.4f}' for x in per_it)})",
+            "seconds_per_iteration": round(s_it, 6),
+            "time_to_1pct_gap": {"seconds": round(ttg, 3) if gap is not None else None, "iters": it, "gap": gap,
+                                 "schedule": f"rounding ({rounds} rounds) every {check_every} iterations",
+                                 "cap_seconds": gap_cap_s},
             "host": host_cpu()}
 
 
@@ -364,8 +469,9 @@ def summarize_counters(fetch_csv, write_csv, copy_fetch_csv, copy_write_csv, out
 
     cf, _ = per_kernel(copy_fetch_csv, "FETCH_SIZE", "copyBuffer")
     cw, _ = per_kernel(copy_write_csv, "WRITE_SIZE", "copyBuffer")
-    f, nf = per_kernel(fetch_csv, "FETCH_SIZE", "k_sweep<float, false, 0>")
-    wv, nw = per_kernel(write_csv, "WRITE_SIZE", "k_sweep<float, false, 0>")
+    # the hard FP32 update sweep, with or without row tiles: k_sweep<float, false, 0, ...>
+    f, nf = per_kernel(fetch_csv, "FETCH_SIZE", "k_sweep<float, false, 0")
+    wv, nw = per_kernel(write_csv, "WRITE_SIZE", "k_sweep<float, false, 0")
     kib = copy_bytes / 1024.0
     ffac, wfac = kib / cf, kib / cw
     fetch_b = f * ffac * 1024.0
@@ -421,7 +527,7 @@ def main():
     if not torch.cuda.is_available():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(2)
-    w = Workload(a.config, a.seed, a.iters)
+    w = Workload(a.config, a.seed, a.iters, **({"k": a.k} if a.k else {}))
     log(f"[bench] config {a.config} ({w.spec.name}) iters={w.iters} warmup={a.warmup} steps={a.steps}")
     for i in range(a.warmup):
         r = w.step()
@@ -497,27 +603,32 @@ def main():
         import statistics
         gaps = {}
         seeds = [int(x) for x in a.gap_seeds.split(",")]
-        # (name, config, smoothed, Jacobi check interval, quasi-Newton check interval)
-        forms = [("plain_fp32", 2, False, 50, 10), ("mixed_bf16", 3, False, 50, 10),
-                 ("diff_t0.1", 4, True, 50, 10), ("largest_bf16", 5, False, 250, 20)]
-        for name, cfg, sm, every, qn_every in forms:
-            for solver, key in (("jacobi", name), ("lbfgs", name + "_lbfgs")):
-                kw = dict(smoothed=sm, solver=solver, check_every=every, max_iters=5000,
-                          qn_check_every=qn_every, qn_max_iters=400)
+        # the three forms on the same pairs: the 1000-face pair (Jacobi) and
+        # the largest pair (Jacobi and quasi-Newton)
+        runs = [(3, "jacobi"), (5, "jacobi"), (5, "lbfgs")]
+        for cfg, solver in runs:
+            for form in FORMS:
+                key = f"config_{cfg}_{form}_{solver}"
                 per_seed = {}
                 for sd in seeds:
                     log(f"[bench] time-to-1%-gap {key}, seed {sd}")
+                    kw = dict(form=form, solver=solver, check_every=10, qn_check_every=10)
                     try:
-                        time_to_gap(cfg, sd, **kw)   # untimed: loads the kernels
+                        if sd == seeds[0]:
+                            time_to_gap(cfg, sd, max_iters=10, qn_max_iters=10, **kw)   # untimed: loads the kernels
                         per_seed[str(sd)] = time_to_gap(cfg, sd, **kw)
                     except RuntimeError as e:   # e.g. a pair that presolve proves infeasible
                         per_seed[str(sd)] = {"error": str(e)}
                     log(f"[bench]   {per_seed[str(sd)]}")
-                ok = [v for v in per_seed.values() if "seconds" in v]
+                ok = [v for v in per_seed.values() if v.get("seconds") is not None]
                 gaps[key] = {"median_seconds": round(statistics.median([v["seconds"] for v in ok]), 6) if ok else None,
-                             "seeds_reaching_1pct": sum(1 for v in ok if v["gap"] <= 1e-2),
-                             "per_seed": per_seed}
+                             "median_iters": statistics.median([v["iters"] for v in ok]) if ok else None,
+                             "seeds_reaching_1pct": len(ok), "per_seed": per_seed}
         out["time_to_1pct_gap"] = gaps
+        log("[bench] full pipeline, largest pair")
+        pipeline_run(5, a.seed, iters=20)   # untimed: loads the kernels
+        out["pipeline_largest"] = pipeline_run(5, a.seed)
+        log(f"[bench]   {out['pipeline_largest']}")
     if not a.no_gap:
         log("[bench] coarse-to-fine 500 -> 1000 -> 2000 -> 4000 faces")
         c2f_run(a.seed, levels=(500, 1000))   # untimed: loads the kernels
@@ -531,6 +642,9 @@ def main():
         log("[bench] exact search, 80-face pair with noisy descriptors (noise 1.0, K = 16)")
         out["exact_search"] = exact_search_run()
         log(f"[bench]   {out['exact_search']}")
+    log("[bench] copy bandwidth (HBM peak check)")
+    out["copy_bandwidth"] = copy_bandwidth()
+    log(f"[bench]   {out['copy_bandwidth']}")
     if not a.no_cpu_baseline:
         log("[bench] CPU oracle baseline")
         out["cpu_baseline"] = cpu_baseline(a.config, a.seed, a.cpu_sample_iters)

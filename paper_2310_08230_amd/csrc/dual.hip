@@ -824,10 +824,10 @@ __device__ inline MinState<R> ms_shfl_xor(MinState<R> v, int off) {
 // block per row (long_wpr = 4); each lane keeps up to LONG_REG of its row's
 // multipliers in registers between the two passes
 constexpr int LONG_REG = 8;
-constexpr int LONG_BATCH = 4;   // record loads in flight per lane
 constexpr int32_t LONG_GROUP = 8;   // consecutive projection-row blocks per XCD turn
 
-template <typename R, bool SOFT, int MODE>
+// LONG_BATCH: record loads in flight per lane
+template <typename R, bool SOFT, int MODE, int LONG_BATCH>
 __device__ void long_rows(const SweepArgs& A, const R* __restrict__ rin, R* __restrict__ out, R omega, R T,
                           R gam, double* red, int32_t item) {
   __shared__ R xm[4], xm2[4], xs[4];
@@ -968,7 +968,10 @@ constexpr size_t smem_bytes() {
   return SOFT ? (SOFT_FTAB + 256) * sizeof(R) + 256 : 768 * sizeof(R);
 }
 
-template <typename R, bool SOFT, int MODE>
+// TILES: the hard form's launch has one-lane-per-row tiles (their register
+// use sets the occupancy of the whole kernel, so launches without tiles take
+// the instantiation without them)
+template <typename R, bool SOFT, int MODE, bool TILES>
 __global__ __launch_bounds__(256) void k_sweep(SweepArgs A, const R* __restrict__ rin, R* __restrict__ out,
                                                R omega, R T) {
   __shared__ __align__(16) unsigned char smem[smem_bytes<R, SOFT>()];
@@ -987,9 +990,9 @@ __global__ __launch_bounds__(256) void k_sweep(SweepArgs A, const R* __restrict_
     if (k0 >= A.xcd_stride) return;
     const int32_t item = A.xcd_item[x * A.xcd_stride + k0];
     if (item < 0) return;
-    if (item < A.n_tile_items) tile_block<R, MODE>(A, rin, out, omega, gam, red, item);
+    if (TILES && item < A.n_tile_items) tile_block<R, MODE>(A, rin, out, omega, gam, red, item);
     else if (item < A.n_short_blocks) short_wave_hard<R, MODE>(A, rin, out, omega, gam, smem, red, item);
-    else long_rows<R, false, MODE>(A, rin, out, omega, T, gam, red, item);
+    else long_rows<R, false, MODE, TILES ? 4 : 2>(A, rin, out, omega, T, gam, red, item);
     return;
   }
   int32_t item;
@@ -1019,7 +1022,7 @@ __global__ __launch_bounds__(256) void k_sweep(SweepArgs A, const R* __restrict_
       short_rows_soft<R, MODE, 32>(A, rin, out, omega, T, smem, red, item, item - nb8 - nb16, c816,
                                    A.n_short);
   } else {
-    long_rows<R, true, MODE>(A, rin, out, omega, T, gam, red, item);
+    long_rows<R, true, MODE, 2>(A, rin, out, omega, T, gam, red, item);
   }
 }
 
@@ -1069,13 +1072,21 @@ __global__ __launch_bounds__(256) void k_reduce_last(const double* partial, int 
 
 // one sweep launch; with timing events the launch records the kernel's own
 // start and end (hipExtLaunchKernelGGL), as a kernel trace does
-template <typename R, bool SOFT, int MODE>
+template <typename R, bool SOFT, int MODE, bool TILES = false>
 void launch_sweep(hipStream_t st, unsigned grid, hipEvent_t e0, hipEvent_t e1, const SweepArgs& A, const R* ri,
                   R* ro, R omega, R T) {
   if (e0)
-    hipExtLaunchKernelGGL(k_sweep<R, SOFT, MODE>, dim3(grid), dim3(256), 0, st, e0, e1, 0, A, ri, ro, omega, T);
+    hipExtLaunchKernelGGL(k_sweep<R, SOFT, MODE, TILES>, dim3(grid), dim3(256), 0, st, e0, e1, 0, A, ri, ro, omega,
+                          T);
   else
-    k_sweep<R, SOFT, MODE><<<grid, 256, 0, st>>>(A, ri, ro, omega, T);
+    k_sweep<R, SOFT, MODE, TILES><<<grid, 256, 0, st>>>(A, ri, ro, omega, T);
+}
+
+template <typename R, int MODE>
+void launch_hard(bool tiles, hipStream_t st, unsigned grid, hipEvent_t e0, hipEvent_t e1, const SweepArgs& A,
+                 const R* ri, R* ro, R omega, R T) {
+  if (tiles) launch_sweep<R, false, MODE, true>(st, grid, e0, e1, A, ri, ro, omega, T);
+  else launch_sweep<R, false, MODE, false>(st, grid, e0, e1, A, ri, ro, omega, T);
 }
 
 }  // namespace
@@ -1250,10 +1261,11 @@ dm_status dual_sweep(dm_ctx* ctx, int mode, bool soft, const unsigned char* rin,
     else if (mode == MODE_EVAL) launch_sweep<R, true, MODE_EVAL>(st, grid, e0, e1, A, ri, ro, omega, T);
     else launch_sweep<R, true, MODE_BOUND>(st, grid, e0, e1, A, ri, ro, omega, T);
   } else {
-    if (mode == MODE_UPDATE) launch_sweep<R, false, MODE_UPDATE>(st, grid, e0, e1, A, ri, ro, omega, T);
-    else if (mode == MODE_EVAL) launch_sweep<R, false, MODE_EVAL>(st, grid, e0, e1, A, ri, ro, omega, T);
-    else if (mode == MODE_BOUND) launch_sweep<R, false, MODE_BOUND>(st, grid, e0, e1, A, ri, ro, omega, T);
-    else launch_sweep<R, false, MODE_SUBGRAD>(st, grid, e0, e1, A, ri, ro, omega, T);
+    const bool tiles = ctx->n_tiles > 0;
+    if (mode == MODE_UPDATE) launch_hard<R, MODE_UPDATE>(tiles, st, grid, e0, e1, A, ri, ro, omega, T);
+    else if (mode == MODE_EVAL) launch_hard<R, MODE_EVAL>(tiles, st, grid, e0, e1, A, ri, ro, omega, T);
+    else if (mode == MODE_BOUND) launch_hard<R, MODE_BOUND>(tiles, st, grid, e0, e1, A, ri, ro, omega, T);
+    else launch_hard<R, MODE_SUBGRAD>(tiles, st, grid, e0, e1, A, ri, ro, omega, T);
   }
   DM_LAUNCH_CHECK(ctx);
   ctx->pend_half ^= 1;

@@ -118,10 +118,30 @@ __global__ void k_iota(int32_t* a, int64_t n) {
   if (i < n) a[i] = int32_t(i);
 }
 
-// entries per key
-__global__ void k_key_weight(const uint32_t* word, int64_t nnz, const int32_t* vkey, int32_t* w) {
-  const int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (e < nnz) atomicAdd(&w[vkey[word[e] & W_VAR_MASK]], 1);
+// entries per key: every free variable adds its row count to its key's bin.
+// Each block takes a contiguous range of variables (in canonical order, so
+// few distinct keys) into an LDS histogram and adds its non-empty bins to
+// the global one; nkeys <= KEY_BINS_LDS.
+constexpr int KEY_BINS_LDS = 16384;
+constexpr int KEY_VARS_PER_BLOCK = 4096;
+
+__global__ __launch_bounds__(256) void k_key_weight(const int32_t* vkey, const uint8_t* deg, int64_t nfree,
+                                                    int32_t nkeys, int32_t* w) {
+  extern __shared__ int32_t hist[];
+  for (int32_t k = threadIdx.x; k < nkeys; k += 256) hist[k] = 0;
+  __syncthreads();
+  const int64_t lo = int64_t(blockIdx.x) * KEY_VARS_PER_BLOCK;
+  const int64_t hi = lo + KEY_VARS_PER_BLOCK < nfree ? lo + KEY_VARS_PER_BLOCK : nfree;
+  for (int64_t i = lo + threadIdx.x; i < hi; i += 256) atomicAdd(&hist[vkey[i]], int32_t(deg[i]));
+  __syncthreads();
+  for (int32_t k = threadIdx.x; k < nkeys; k += 256)
+    if (hist[k]) atomicAdd(&w[k], hist[k]);
+}
+
+// a generic problem keys every variable by itself: its weight is its row count
+__global__ void k_deg_weight(const uint8_t* deg, int64_t n, int32_t* w) {
+  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i < n) w[i] = deg[i];
 }
 
 // region of a key: the eighth of all entries in which the middle of the
@@ -142,7 +162,8 @@ __global__ void k_region_bounds(const int32_t* pre, const int32_t* w, int32_t nk
   atomicMax(&bounds[2 * r + 1], k);
 }
 
-// key of every row: the smallest key of its entries
+// key of every row: the smallest key of its entries; short rows one thread
+// each, projection rows one wave each
 __global__ void k_row_keys(const int32_t* rrow_ptr, const uint32_t* word, const int32_t* vkey, int64_t n_rows,
                            int32_t* rkey) {
   const int64_t j = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
@@ -152,16 +173,34 @@ __global__ void k_row_keys(const int32_t* rrow_ptr, const uint32_t* word, const 
   rkey[j] = m == INT32_MAX ? 0 : m;
 }
 
-// short rows: sort key (tile row or not, row key, row).  Rows with b = 0 and
-// at most TILE_HALF entries of each sign go first (they run one lane per row
-// in 64-row tiles), the others follow; both in key order.  Bit 63 marks the
-// others, bits 32-57 hold the row key.
+__global__ void k_long_row_keys(const int32_t* rrow_ptr, const uint32_t* word, const int32_t* vkey, int64_t n_short,
+                                int64_t n_rows, int32_t* rkey) {
+  const int64_t j = n_short + int64_t(blockIdx.x) * (blockDim.x >> 6) + (threadIdx.x >> 6);
+  if (j >= n_rows) return;   // uniform across the wave
+  const int lane = threadIdx.x & 63;
+  int32_t m = INT32_MAX;
+  for (int32_t e = rrow_ptr[j] + lane; e < rrow_ptr[j + 1]; e += 64) m = min(m, vkey[word[e] & W_VAR_MASK]);
+  for (int off = 32; off > 0; off >>= 1) m = min(m, __shfl_xor(m, off));
+  if (lane == 0) rkey[j] = m == INT32_MAX ? 0 : m;
+}
+
+// short rows: sort key (tile row or not, row key), sorted stably so that
+// equal keys keep the row order.  Rows with b = 0 and at most TILE_HALF
+// entries of each sign go first (they run one lane per row in 64-row tiles),
+// the others follow; both in key order.  Bit kbits marks the others.
 constexpr int TILE_HALF = 8;
 constexpr int TILE_WORDS = 2 * TILE_HALF * 64;
+// Tiles cut the sweep's vector instructions several times over, but a tile
+// wave touches the records of 64 rows at once: on problems of more than
+// TILE_NNZ_MAX nonzeros (records well past what the L2s hold) the wider
+// footprint costs more in record traffic than the instructions save, and all
+// short rows stay in chunks.
+constexpr int64_t TILE_NNZ_MAX = int64_t(8) << 20;
 
 __global__ void k_short_sort_keys(const int32_t* rkey, const int32_t* rrow_ptr, const int32_t* rrow_b,
-                                  const uint32_t* word, int64_t n_short, uint64_t* key, int32_t* val,
-                                  int32_t* n_tile_rows) {
+                                  const uint32_t* word, int64_t n_short, int tiles_on, int kbits, uint32_t* key,
+                                  int32_t* val,
+                                  int32_t* n_tile_rows /* [2]: rows, entries */) {
   const int64_t j = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (j >= n_short) return;
   int32_t np = 0, nq = 0;
@@ -169,11 +208,13 @@ __global__ void k_short_sort_keys(const int32_t* rkey, const int32_t* rrow_ptr, 
     if (word[e] & W_NEG) ++nq;
     else ++np;
   }
-  const bool tile = rrow_b[j] == 0 && np <= TILE_HALF && nq <= TILE_HALF;
-  const uint64_t rk = uint64_t(min(rkey[j], (1 << 26) - 1));
-  key[j] = (tile ? 0ull : (1ull << 63)) | (rk << 32) | uint64_t(j);
+  const bool tile = tiles_on && rrow_b[j] == 0 && np <= TILE_HALF && nq <= TILE_HALF;
+  key[j] = (tile ? 0u : (1u << kbits)) | uint32_t(rkey[j]);
   val[j] = int32_t(j);
-  if (tile) atomicAdd(n_tile_rows, 1);
+  if (tile) {
+    atomicAdd(&n_tile_rows[0], 1);
+    atomicAdd(&n_tile_rows[1], np + nq);   // their entries
+  }
 }
 
 // words of every tile row into its lane of its tile: +1 entries in slots 0 to
@@ -192,14 +233,21 @@ __global__ void k_tile_fill(const int32_t* perm, int64_t n_tile_rows, const int3
   }
 }
 
-// long rows: sort key (region, key, row); an X projection row (or any long
-// row of a generic problem) takes its own key's region; the o-th Y
-// projection row goes to region o % 8 at a key spread over that region's
-// range.  Long rows of reduced index >= first_y (full row index in rrow_orig)
-// are Y projection rows.
+// long rows: sort key (region, key), sorted stably (equal keys keep the row
+// order); an X projection row (or any long row of a generic problem) takes
+// its own key's region; the o-th Y projection row goes to region o % 8 at a
+// key spread over that region's range.  Long rows whose full row index
+// (rrow_orig) is at least first_y_full are Y projection rows; *first_y_long
+// counts the long rows before them.
+__global__ void k_count_below(const int32_t* rrow_orig, int64_t n_short, int64_t n_long, int64_t first_y_full,
+                              int32_t* count) {
+  const int64_t l = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (l < n_long && rrow_orig[n_short + l] < first_y_full) atomicAdd(count, 1);
+}
+
 __global__ void k_long_sort_keys(const int32_t* rkey, const int32_t* rrow_orig, int64_t n_short, int64_t n_long,
-                                 int64_t first_y_full, int64_t first_y_long, int64_t n_y, const int32_t* pre,
-                                 const int32_t* w, int64_t total, const int32_t* bounds, uint64_t* key,
+                                 int64_t first_y_full, const int32_t* first_y_long, int kbits, const int32_t* pre,
+                                 const int32_t* w, int64_t total, const int32_t* bounds, uint32_t* key,
                                  int32_t* val) {
   const int64_t l = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (l >= n_long) return;
@@ -209,14 +257,15 @@ __global__ void k_long_sort_keys(const int32_t* rkey, const int32_t* rrow_orig, 
     k = rkey[j];
     r = region_of(pre, w, k, total);
   } else {
-    const int64_t o = l - first_y_long;
+    const int64_t fy = *first_y_long, n_y = n_long - fy;
+    const int64_t o = l - fy;
     r = int32_t(o % NREG);
     const int64_t per = (n_y - r + NREG - 1) / NREG;   // Y rows of region r
     const int32_t lo = bounds[2 * r], hi = bounds[2 * r + 1];
     const int64_t span = hi >= lo ? int64_t(hi) - lo + 1 : 1;
     k = int32_t((hi >= lo ? lo : 0) + ((o / NREG) * span) / (per > 0 ? per : 1));
   }
-  key[l] = (uint64_t(r) << 61) | (uint64_t(uint32_t(k)) << 32) | uint64_t(l);
+  key[l] = (uint32_t(r) << kbits) | uint32_t(k);
   val[l] = int32_t(l);
 }
 
@@ -334,33 +383,31 @@ __global__ void k_chunk_pad(const int4* desc, const unsigned long long* mask, co
 // row, a chunk item (four chunks) those of its first row, a long item those
 // of its first long row.  Items are numbered [tile items | chunk items | long
 // items].
-__global__ void k_item_keys(int32_t n_tile_items, const uint64_t* skey,
-                            const int4* desc, int32_t n_chunk_items, const int32_t* prkey, const int32_t* pre,
-                            const int32_t* w, int64_t total, const uint64_t* lkey_sorted, int32_t n_long_items,
-                            int32_t rows_per_long, uint64_t* key, int32_t* val) {
+__global__ void k_item_keys(int32_t n_tile_items, const uint32_t* skey, uint32_t kmask, const int4* desc,
+                            int32_t n_chunk_items, const int32_t* prkey, const int32_t* pre, const int32_t* w,
+                            int64_t total, const uint32_t* lkey_sorted, int32_t n_long_items, int32_t rows_per_long,
+                            int kbits, uint32_t* key, int32_t* val) {
   const int32_t i = int32_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (i >= n_tile_items + n_chunk_items + n_long_items) return;
-  uint64_t r, k;
+  uint32_t r, k;
   if (i < n_tile_items) {
-    const int32_t kk = int32_t((skey[int64_t(i) * 256] >> 32) & 0x3FFFFFFull);
-    k = uint32_t(kk);
-    r = uint64_t(region_of(pre, w, kk, total));
+    k = skey[int64_t(i) * 256] & kmask;
+    r = uint32_t(region_of(pre, w, int32_t(k), total));
   } else if (i < n_tile_items + n_chunk_items) {
-    const int32_t kk = prkey[desc[4 * (i - n_tile_items)].x];
-    k = uint32_t(kk);
-    r = uint64_t(region_of(pre, w, kk, total));
+    k = uint32_t(prkey[desc[4 * (i - n_tile_items)].x]);
+    r = uint32_t(region_of(pre, w, int32_t(k), total));
   } else {
-    const uint64_t lk = lkey_sorted[int64_t(i - n_tile_items - n_chunk_items) * rows_per_long];
-    r = lk >> 61;
-    k = (lk >> 32) & 0x1FFFFFFFull;
+    const uint32_t lk = lkey_sorted[int64_t(i - n_tile_items - n_chunk_items) * rows_per_long];
+    r = lk >> kbits;
+    k = lk & kmask;
   }
-  key[i] = (r << 61) | (k << 32) | uint64_t(uint32_t(i));
+  key[i] = (r << kbits) | k;
   val[i] = i;
 }
 
-__global__ void k_region_count(const uint64_t* key, int32_t n, int32_t* cnt) {
+__global__ void k_region_count(const uint32_t* key, int32_t n, int kbits, int32_t* cnt) {
   const int32_t i = int32_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (i < n) atomicAdd(&cnt[int(key[i] >> 61)], 1);
+  if (i < n) atomicAdd(&cnt[int(key[i] >> kbits)], 1);
 }
 
 __global__ void k_xcd_table(const int32_t* sorted_item, int32_t n_items, const int32_t* start, int32_t stride,
@@ -418,7 +465,14 @@ dm_status sweep_layout(dm_ctx* ctx) {
   DM_ALLOC(ctx, wpre, size_t(nkeys) + 1);
   DM_ALLOC(ctx, bounds, 2 * NREG);
   DM_HIP(ctx, hipMemsetAsync(wcount.p, 0, sizeof(int32_t) * nkeys, st));
-  if (rnnz > 0) k_key_weight<<<grid_for(rnnz, 256), 256, 0, st>>>(ctx->rent_word.p, rnnz, vkey.p, wcount.p);
+  if (mesh && nfree > 0) {
+    if (nkeys > KEY_BINS_LDS)
+      return dm_fail(ctx, DM_ERR_WORKSPACE, "sweep layout: %d faces exceed %d key bins", nkeys, KEY_BINS_LDS);
+    k_key_weight<<<grid_for(nfree, KEY_VARS_PER_BLOCK), 256, size_t(nkeys) * sizeof(int32_t), st>>>(
+        vkey.p, ctx->var_deg.p, nfree, nkeys, wcount.p);
+  } else if (nfree > 0) {
+    k_deg_weight<<<grid_for(nfree, 256), 256, 0, st>>>(ctx->var_deg.p, nfree, wcount.p);
+  }
   DM_LAUNCH_CHECK(ctx);
   DM_TRY(scan_i32(ctx, wcount.p, wpre.p, size_t(nkeys)));
   for (int r = 0; r < NREG; ++r) {
@@ -427,25 +481,40 @@ dm_status sweep_layout(dm_ctx* ctx) {
   }
   k_region_bounds<<<grid_for(nkeys, 256), 256, 0, st>>>(wpre.p, wcount.p, nkeys, rnnz, bounds.p);
   DM_ALLOC(ctx, rkey, size_t(std::max<int64_t>(nr, 1)));
-  if (nr > 0) k_row_keys<<<grid_for(nr, 256), 256, 0, st>>>(ctx->rrow_ptr.p, ctx->rent_word.p, vkey.p, nr, rkey.p);
+  if (nshort > 0)
+    k_row_keys<<<grid_for(nshort, 256), 256, 0, st>>>(ctx->rrow_ptr.p, ctx->rent_word.p, vkey.p, nshort, rkey.p);
+  if (nlong > 0)
+    k_long_row_keys<<<grid_for(nlong, 4), 256, 0, st>>>(ctx->rrow_ptr.p, ctx->rent_word.p, vkey.p, nshort, nr,
+                                                         rkey.p);
   DM_LAUNCH_CHECK(ctx);
 
   // ---- short rows: 64-row tiles of b = 0 rows, then the rest in wave chunks, both in key order
-  DArr<uint64_t> skey;
+  // stable radix sorts on compact keys: keys take kbits bits, one more bit
+  // marks non-tile rows, three more bits above them hold the region
+  const int kbits = bits_for(uint64_t(nkeys));
+  const uint32_t kmask = (1u << kbits) - 1u;
+  DArr<uint32_t> skey;
   DArr<int32_t> perm, plen, prow_ptr, pb, prkey, ntr;
   DArr<uint32_t> pword;
   DM_ALLOC(ctx, skey, size_t(std::max<int64_t>(nshort, 1)));
   DM_ALLOC(ctx, perm, size_t(std::max<int64_t>(nshort, 1)));
-  DM_ALLOC(ctx, ntr, 1);
-  DM_HIP(ctx, hipMemsetAsync(ntr.p, 0, sizeof(int32_t), st));
+  DM_ALLOC(ctx, ntr, 2);
+  DM_HIP(ctx, hipMemsetAsync(ntr.p, 0, 2 * sizeof(int32_t), st));
   if (nshort > 0) {
     k_short_sort_keys<<<grid_for(nshort, 256), 256, 0, st>>>(rkey.p, ctx->rrow_ptr.p, ctx->rrow_b.p,
-                                                             ctx->rent_word.p, nshort, skey.p, perm.p, ntr.p);
+                                                             ctx->rent_word.p, nshort, rnnz <= TILE_NNZ_MAX ? 1 : 0,
+                                                             kbits, skey.p, perm.p, ntr.p);
     DM_LAUNCH_CHECK(ctx);
-    DM_TRY(sort_pairs_u64(ctx, skey.p, perm.p, size_t(nshort), 64));
+    DM_TRY(sort_pairs_u32(ctx, skey.p, perm.p, size_t(nshort), kbits + 1));
   }
-  int32_t n_tile_rows = 0;
-  DM_TRY(read_i32(ctx, ntr.p, &n_tile_rows));
+  int32_t n_tile_rows = 0, nnz_chunk = 0;
+  {
+    const int32_t* src[2] = {ntr.p, ntr.p + 1};
+    int32_t v[2];
+    DM_TRY(read_i32s(ctx, 2, src, v));
+    n_tile_rows = v[0];
+    nnz_chunk = int32_t(ctx->nnz_short) - v[1];   // entries of the short rows left to the chunks
+  }
   ctx->n_tiles = (n_tile_rows + 63) / 64;
   ctx->n_tile_items = (ctx->n_tiles + 3) / 4;
   const size_t twords = size_t(ctx->n_tiles) * TILE_WORDS;
@@ -468,8 +537,6 @@ dm_status sweep_layout(dm_ctx* ctx) {
     DM_LAUNCH_CHECK(ctx);
   }
   DM_TRY(scan_i32(ctx, plen.p, prow_ptr.p, size_t(nchr)));
-  int32_t nnz_chunk = 0;
-  DM_TRY(read_i32(ctx, prow_ptr.p + nchr, &nnz_chunk));
   DM_ALLOC(ctx, pword, size_t(std::max(nnz_chunk, 1)));
   if (nchr > 0) {
     k_perm_words<<<grid_for(nchr, 256), 256, 0, st>>>(cperm, ctx->rrow_ptr.p, prow_ptr.p, ctx->rent_word.p, nchr,
@@ -509,45 +576,40 @@ dm_status sweep_layout(dm_ctx* ctx) {
   const int32_t rows_per_long = 4 / ctx->long_wpr;
   const int32_t n_long_items = int32_t((nlong + rows_per_long - 1) / rows_per_long);
   const int32_t n_chunk_items = (n_chunks + 3) / 4;
-  DArr<uint64_t> lkey;
+  DArr<uint32_t> lkey;
+  DArr<int32_t> fyl;
   DM_ALLOC(ctx, lkey, size_t(std::max<int64_t>(nlong, 1)));
+  DM_ALLOC(ctx, fyl, 1);
   DM_ALLOC(ctx, ctx->long_perm, size_t(std::max<int64_t>(nlong, 1)));
   if (nlong > 0) {
     // Y projection rows follow the X ones: count the long rows of a full
     // index below the first Y projection row
     const int64_t first_y_full = mesh ? ctx->n_closed_full + ctx->X.nf : INT64_MAX;
-    int64_t first_y_long = nlong;
-    if (mesh) {
-      std::vector<int32_t> host(static_cast<size_t>(nlong));
-      DM_HIP(ctx, hipMemcpyAsync(host.data(), ctx->rrow_orig.p + nshort, sizeof(int32_t) * nlong,
-                                 hipMemcpyDeviceToHost, st));
-      DM_HIP(ctx, hipStreamSynchronize(st));
-      first_y_long = std::lower_bound(host.begin(), host.end(), int32_t(first_y_full)) - host.begin();
-    }
-    k_long_sort_keys<<<grid_for(nlong, 256), 256, 0, st>>>(rkey.p, ctx->rrow_orig.p, nshort, nlong,
-                                                           first_y_full, first_y_long, nlong - first_y_long,
-                                                           wpre.p, wcount.p, rnnz, bounds.p, lkey.p,
+    DM_HIP(ctx, hipMemsetAsync(fyl.p, 0, sizeof(int32_t), st));
+    k_count_below<<<grid_for(nlong, 256), 256, 0, st>>>(ctx->rrow_orig.p, nshort, nlong, first_y_full, fyl.p);
+    k_long_sort_keys<<<grid_for(nlong, 256), 256, 0, st>>>(rkey.p, ctx->rrow_orig.p, nshort, nlong, first_y_full,
+                                                           fyl.p, kbits, wpre.p, wcount.p, rnnz, bounds.p, lkey.p,
                                                            ctx->long_perm.p);
     DM_LAUNCH_CHECK(ctx);
-    DM_TRY(sort_pairs_u64(ctx, lkey.p, ctx->long_perm.p, size_t(nlong), 64));
+    DM_TRY(sort_pairs_u32(ctx, lkey.p, ctx->long_perm.p, size_t(nlong), kbits + 3));
   }
 
   // ---- items in (region, key) order and the per-XCD table
   const int32_t n_items = ctx->n_tile_items + n_chunk_items + n_long_items;
   ctx->n_long_items = n_long_items;
-  DArr<uint64_t> ikey;
+  DArr<uint32_t> ikey;
   DArr<int32_t> iorder, cnt;
   DM_ALLOC(ctx, ikey, size_t(std::max(n_items, 1)));
   DM_ALLOC(ctx, iorder, size_t(std::max(n_items, 1)));
   DM_ALLOC(ctx, cnt, NREG);
   DM_HIP(ctx, hipMemsetAsync(cnt.p, 0, NREG * sizeof(int32_t), st));
   if (n_items > 0) {
-    k_item_keys<<<grid_for(n_items, 256), 256, 0, st>>>(ctx->n_tile_items, skey.p, ctx->chunk_desc.p,
+    k_item_keys<<<grid_for(n_items, 256), 256, 0, st>>>(ctx->n_tile_items, skey.p, kmask, ctx->chunk_desc.p,
                                                         n_chunk_items, prkey.p, wpre.p, wcount.p, rnnz, lkey.p,
-                                                        n_long_items, rows_per_long, ikey.p, iorder.p);
+                                                        n_long_items, rows_per_long, kbits, ikey.p, iorder.p);
     DM_LAUNCH_CHECK(ctx);
-    DM_TRY(sort_pairs_u64(ctx, ikey.p, iorder.p, size_t(n_items), 64));
-    k_region_count<<<grid_for(n_items, 256), 256, 0, st>>>(ikey.p, n_items, cnt.p);
+    DM_TRY(sort_pairs_u32(ctx, ikey.p, iorder.p, size_t(n_items), kbits + 3));
+    k_region_count<<<grid_for(n_items, 256), 256, 0, st>>>(ikey.p, n_items, kbits, cnt.p);
     DM_LAUNCH_CHECK(ctx);
   }
   int32_t hc[NREG];
