@@ -462,10 +462,14 @@ def summarize_counters(fetch_csv, write_csv, copy_fetch_csv, copy_write_csv, out
     import hashlib
     import statistics
 
+    names = set()
+
     def per_kernel(path, counter, name_has):
-        vals = [float(r["Counter_Value"]) for r in csv.DictReader(open(path))
+        rows = [r for r in csv.DictReader(open(path))
                 if r["Counter_Name"] == counter and name_has in r["Kernel_Name"]]
-        return statistics.median(vals), len(vals)
+        if name_has.startswith("k_sweep"):
+            names.update(r["Kernel_Name"].strip() for r in rows)
+        return statistics.median(float(r["Counter_Value"]) for r in rows), len(rows)
 
     cf, _ = per_kernel(copy_fetch_csv, "FETCH_SIZE", "copyBuffer")
     cw, _ = per_kernel(copy_write_csv, "WRITE_SIZE", "copyBuffer")
@@ -477,7 +481,7 @@ def summarize_counters(fetch_csv, write_csv, copy_fetch_csv, copy_write_csv, out
     fetch_b = f * ffac * 1024.0
     write_b = wv * wfac * 1024.0
     src = os.path.join(ROOT, "paper_2310_08230_amd", "csrc", "dual.hip")
-    rec = {"kernel": "k_sweep<float,false,MODE_UPDATE>", "workload": workload,
+    rec = {"kernel": " / ".join(sorted(names)), "workload": workload,
            "fetch_kib_median": f, "write_kib_median": wv, "dispatches": [nf, nw],
            "copy_calibration": {"bytes": copy_bytes, "fetch_kib": cf, "write_kib": cw,
                                 "fetch_factor": ffac, "write_factor": wfac},
