@@ -157,16 +157,17 @@ __device__ inline R seg_sum(R v) {
   return v;
 }
 
-// soft-min over the W lanes of a segment in scaled units, every lane gets the
-// result: the hard minimum, one exponential per lane, a sum, one logarithm.
-// With the minimum clamped to the largest finite value, lanes holding inf
-// add E(-inf) = 0, and a segment of infs gives L(0) = -inf, so inf.
+// soft-min over the W lanes of a segment in scaled units, as the two parts
+// every lane gets: the hard minimum mc and the sum e of one exponential per
+// lane; the soft-min is mc - L(e), left to the caller so that only the lane
+// that needs it takes the logarithm.  With the minimum clamped to the largest
+// finite value, lanes holding inf add E(-inf) = 0, and a segment of infs
+// gives L(0) = -inf, so inf.
 template <int W, typename R>
-__device__ inline R seg_softmin(R x) {
+__device__ inline void seg_softmin_parts(R x, R& mc, R& e) {
   const R m = seg_min<W, R>(x);
-  const R mc = m < SoftUnits<R>::big ? m : SoftUnits<R>::big;
-  const R e = seg_sum<W, R>(SoftUnits<R>::E(mc - x));
-  return mc - SoftUnits<R>::L(e);
+  mc = m < SoftUnits<R>::big ? m : SoftUnits<R>::big;
+  e = seg_sum<W, R>(SoftUnits<R>::E(mc - x));
 }
 
 // multiplier of entry word w from the previous record buffer, with dual
@@ -751,7 +752,9 @@ __device__ void short_rows_soft(const SweepArgs& A, const R* __restrict__ rin, R
       if (!valid) F = rinf<R>();
     }
     R Bv = (valid && sigma == b) ? R(0) : rinf<R>();
-    R myM = R(0), my1 = R(0);
+    // lane l keeps the parts of its entry's two soft-mins (x_l = 1 and
+    // x_l = 0); the logarithms are taken once, after the recursion
+    R m1 = R(0), e1 = R(1), m0 = R(0), e0 = R(1);
     for (int32_t l = n - 1; l >= 0; --l) {
       const int a = aL[l];
       const R Fl = Ftab[l * W + lane];
@@ -759,17 +762,20 @@ __device__ void short_rows_soft(const SweepArgs& A, const R* __restrict__ rin, R
       R sh = a > 0 ? from_hi : from_lo;                                       // Bv[lane + a]
       if ((unsigned(lane + a) >= unsigned(W)) | !valid) sh = rinf<R>();
       // inf + finite and inf + inf stay inf
-      R x1 = Fl + lamL[l] + sh;
-      R x0 = Fl + Bv;
-      x1 = seg_softmin<W, R>(x1);
-      x0 = seg_softmin<W, R>(x0);
+      R pm1, pe1, pm0, pe0;
+      seg_softmin_parts<W, R>(Fl + lamL[l] + sh, pm1, pe1);
+      seg_softmin_parts<W, R>(Fl + Bv, pm0, pe0);
       if (lane == l) {
-        myM = (x1 - x0) * unit;
-        my1 = x1;
+        m1 = pm1;
+        e1 = pe1;
+        m0 = pm0;
+        e0 = pe0;
       }
       Bv = smin2u<R>(Bv, sh + lamL[l]);
       if (!valid) Bv = rinf<R>();
     }
+    const R my1 = m1 - SoftUnits<R>::L(e1);
+    const R myM = (my1 - (m0 - SoftUnits<R>::L(e0))) * unit;
     // soft row value B_0(0) sits on lane N
     const R rowv = __shfl(Bv, N, W);
     if (lane < n) {
