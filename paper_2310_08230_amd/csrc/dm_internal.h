@@ -91,38 +91,40 @@ struct MeshDev {
 constexpr uint32_t W_NEG = 1u << 31;
 constexpr int W_SLOT_SHIFT = 27;
 constexpr uint32_t W_VAR_MASK = (1u << 27) - 1u;
-constexpr int REC = 8;          // record stride: 5 multiplier slots, cost, degree, 1 spare
+constexpr int REC = 8;          // record stride: 5 multiplier slots, cost, 1 / degree, 1 spare
 constexpr int REC_COST = 5;
-constexpr int REC_DEG = 6;
+constexpr int REC_RDEG = 6;
 constexpr int MAX_SHORT_ROW = 64;
 constexpr int SOFT_MAX_ROW = 24;
 constexpr uint32_t CHUNK_PAD = 0xFFFFFFFFu;   // entry word of an unused chunk slot
 
 // Multipliers of free variable i from its record (slots 0-4 hold s_k, slot 5
-// the cost c_i, slot 6 the number |J_i| of rows the variable lies in, 1 to
-// 5), with dual feasibility restored: lambda_k = s_k + (c_i - sum_k s_k) /
-// |J_i|.  Slots at or above |J_i| hold zero and are never written, so the sum
-// runs over all five.  Every reader of a record (the row sweeps and the
-// per-variable passes) goes through this one function, so they all see
-// bit-identical multipliers.
+// the cost c_i, slot 6 the reciprocal 1/|J_i| of the number of rows the
+// variable lies in, 1 to 5, rounded to the record's precision), with dual
+// feasibility restored: lambda_k = s_k + (c_i - sum_k s_k) * (1/|J_i|).  The
+// product by the stored reciprocal replaces a division on every record read.
+// Slots at or above |J_i| hold zero and are never written, so the sum runs
+// over all five.  Every reader of a record (the row sweeps and the
+// per-variable passes) goes through this one function or its batched copy in
+// the row tiles, so they all see bit-identical multipliers.
 template <typename R>
 __device__ inline void rec_lambdas(const R* __restrict__ rec, size_t i, R lam[5]) {
   const R* r = rec + i * REC;
-  R s0, s1, s2, s3, s4, c, d;
+  R s0, s1, s2, s3, s4, c, rd;
   if constexpr (sizeof(R) == 4) {
     // records are 32-byte aligned: two 16-byte loads of one 32-byte sector
     const float4 lo = *reinterpret_cast<const float4*>(r);
     const float4 hi = *reinterpret_cast<const float4*>(r + 4);
-    s0 = lo.x, s1 = lo.y, s2 = lo.z, s3 = lo.w, s4 = hi.x, c = hi.y, d = hi.z;
+    s0 = lo.x, s1 = lo.y, s2 = lo.z, s3 = lo.w, s4 = hi.x, c = hi.y, rd = hi.z;
   } else {
     const double2 a = *reinterpret_cast<const double2*>(r);
     const double2 b = *reinterpret_cast<const double2*>(r + 2);
     const double2 e = *reinterpret_cast<const double2*>(r + 4);
     const double2 f = *reinterpret_cast<const double2*>(r + 6);
-    s0 = a.x, s1 = a.y, s2 = b.x, s3 = b.y, s4 = e.x, c = e.y, d = f.x;
+    s0 = a.x, s1 = a.y, s2 = b.x, s3 = b.y, s4 = e.x, c = e.y, rd = f.x;
   }
   const R sum = (((s0 + s1) + s2) + s3) + s4;
-  const R corr = (c - sum) / d;
+  const R corr = (c - sum) * rd;
   lam[0] = s0 + corr;
   lam[1] = s1 + corr;
   lam[2] = s2 + corr;

@@ -550,7 +550,7 @@ struct RecRaw<float> {
   // lambda of slot k with dual feasibility restored, in the arithmetic of rec_lambdas
   __device__ float lambda(int k) const {
     const float sum = (((lo.x + lo.y) + lo.z) + lo.w) + hi.x;
-    const float corr = (hi.y - sum) / hi.z;
+    const float corr = (hi.y - sum) * hi.z;
     const float sk = k == 0 ? lo.x : k == 1 ? lo.y : k == 2 ? lo.z : k == 3 ? lo.w : hi.x;
     return sk + corr;
   }
@@ -567,7 +567,7 @@ struct RecRaw<double> {
   }
   __device__ double lambda(int k) const {
     const double sum = (((a.x + a.y) + b.x) + b.y) + c.x;
-    const double corr = (c.y - sum) / d.x;
+    const double corr = (c.y - sum) * d.x;
     const double sk = k == 0 ? a.x : k == 1 ? a.y : k == 2 ? b.x : k == 3 ? b.y : c.x;
     return sk + corr;
   }
@@ -1044,12 +1044,12 @@ __global__ void k_set_cost(const int32_t* free_var, const double* c64, const uin
                            R* rec1) {
   int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (i >= nfree) return;
-  const R c = R(c64[free_var[i]]), d = R(deg[i]);
+  const R c = R(c64[free_var[i]]), rd = R(1) / R(deg[i]);
   rec0[size_t(i) * REC + REC_COST] = c;
-  rec0[size_t(i) * REC + REC_DEG] = d;
+  rec0[size_t(i) * REC + REC_RDEG] = rd;
   if (rec1) {
     rec1[size_t(i) * REC + REC_COST] = c;
-    rec1[size_t(i) * REC + REC_DEG] = d;
+    rec1[size_t(i) * REC + REC_RDEG] = rd;
   }
 }
 
