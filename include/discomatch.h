@@ -126,7 +126,10 @@ dm_status dm_set_workspace(dm_ctx* ctx, int32_t stage, void* ptr, size_t bytes);
  * here is the library's.
  *  FX [device] float32 [nvx*D] row-major; FY [device] float32 [nvy*D];
  *  cand_xy [device] int32 [nvx*K] out; cand_yx [device] int32 [nvy*K] out.
- *  Errors: K < 1, K > nvx or nvy, nvx or nvy > 4096, D < 1. */
+ *  The K nearest are selected exactly at any size (rows longer than 4096
+ *  are processed in chunks that keep the best K so far).
+ *  Errors: K < 1, K > nvx or nvy, K > 2048 when nvx or nvy exceeds 4096,
+ *  nvx or nvy > 2^21, D < 1. */
 dm_status dm_knn_candidates(dm_ctx* ctx, const float* FX, int32_t nvx, const float* FY,
                             int32_t nvy, int32_t D, int32_t K, int32_t prec, int32_t* cand_xy,
                             int32_t* cand_yx);
@@ -139,8 +142,8 @@ dm_status dm_knn_candidates(dm_ctx* ctx, const float* FX, int32_t nvx, const flo
  * process ends.  No call allocates or frees memory.  Arguments, layouts and
  * errors as dm_knn_candidates; in addition DM_ERR_WORKSPACE when the
  * temporaries exceed 16 MiB: 4*nvx*nvy bytes of distances, plus
- * 2*D8*(nvx64 + nvy64) + 4*(nvx64 + nvy64) in BF16, with D8 = D rounded up
- * to 8 and nvx64, nvy64 rounded up to 64, each piece rounded up to 256 bytes
+ * 2*D16*(nvx64 + nvy64) + 4*(nvx64 + nvy64) in BF16, with D16 = D rounded up
+ * to 16 and nvx64, nvy64 rounded up to 64, each piece rounded up to 256 bytes
  * (about 2000 x 2000 vertices at D = 128).  Every call on one GPU shares
  * that GPU's array and leaves its last contents there; calls that overlap on
  * one GPU (other threads, other streams, other contexts) race and must be

@@ -159,7 +159,6 @@ extern "C" dm_status dm_build_costs(dm_ctx* ctx, const float* FX, const float* F
   DM_ALLOC(ctx, ctx->pair_d, size_t(nC));
   DM_ALLOC(ctx, ctx->pair_a, size_t(nC));
   if (prec == DM_PREC_BF16) {
-    if (nvx > 4096 || nvy > 4096) return dm_fail(ctx, DM_ERR_INVALID_ARG, "BF16 costs need nv <= 4096");
     DArr<float> d2;
     DM_ALLOC(ctx, d2, size_t(nvx) * nvy);
     DM_TRY(knn_distances(ctx, FX, nvx, FY, nvy, D, DM_PREC_BF16, d2.p));

@@ -16,10 +16,12 @@
 
 namespace {
 
-typedef short bf16x4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 
-constexpr int TOPK_MAX = 4096;
+constexpr int TOPK_MAX = 4096;      // keys in the LDS table of one top-K block
+constexpr int GEMM_KC = 128;        // K values per LDS stage of the distance GEMM
+constexpr int GEMM_LDS_ROW = GEMM_KC + 8;   // bf16 per staged row (16-byte pad)
 
 __device__ inline uint16_t f32_to_bf16_rne(float f) {
   uint32_t u = __float_as_uint(f);
@@ -47,30 +49,48 @@ __global__ void k_to_bf16(const float* F, int32_t nv, int32_t D, int32_t nvp, in
 }
 
 // 64x64 output tile per 256-thread block; each wave owns a 32x32 quarter and
-// runs v_mfma_f32_32x32x8bf16_1k over K in steps of 8.  Operand layout of that
-// instruction: lane l holds A[l%32][4*(l/32) .. +3] and B[4*(l/32) .. +3][l%32];
-// accumulator register r of lane l is C[8*(r/4) + 4*(l/32) + r%4][l%32].
-// Both operands are read straight from the row-major [vertex][Dp] arrays (B =
-// F_Y^T), 8 bytes per lane per step.
+// runs the gfx950 v_mfma_f32_32x32x16_bf16 over K in steps of 16.  Operand
+// layout of that instruction: lane l holds A[l%32][8*(l/32) .. +7] and
+// B[8*(l/32) .. +7][l%32]; accumulator register r of lane l is
+// C[8*(r/4) + 4*(l/32) + r%4][l%32].  The block stages its 64 rows of A and
+// 64 rows of B (B = F_Y^T, so rows of F_Y), GEMM_KC values of K at a time, in
+// LDS with coalesced 16-byte loads; the waves read their fragments from there
+// (row stride padded by 16 bytes, so the 32 rows of a fragment read start in
+// different banks).
 __global__ __launch_bounds__(256) void k_gemm_bf16_dist(const uint16_t* A, const uint16_t* B,
                                                         const float* na, const float* nb, int32_t nva,
                                                         int32_t nvb, int32_t Dp, float* d2) {
+  __shared__ __align__(16) uint16_t As[64 * GEMM_LDS_ROW];
+  __shared__ __align__(16) uint16_t Bs[64 * GEMM_LDS_ROW];
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
-  const int32_t m0 = int32_t(blockIdx.y) * 64 + (wave >> 1) * 32;
-  const int32_t n0 = int32_t(blockIdx.x) * 64 + (wave & 1) * 32;
-  const int row = lane & 31, kg = (lane >> 5) * 4;
+  const int32_t mb = int32_t(blockIdx.y) * 64, nbk = int32_t(blockIdx.x) * 64;
+  const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
+  const int row = lane & 31, kg = (lane >> 5) * 8;
   f32x16 acc;
   for (int r = 0; r < 16; ++r) acc[r] = 0.0f;
-  // arrays are padded to multiples of 64 rows, so these reads stay in bounds
-  const uint16_t* pa = A + int64_t(m0 + row) * Dp + kg;
-  const uint16_t* pb = B + int64_t(n0 + row) * Dp + kg;
-  for (int32_t k = 0; k < Dp; k += 8) {
-    bf16x4 a = *reinterpret_cast<const bf16x4*>(pa + k);
-    bf16x4 b = *reinterpret_cast<const bf16x4*>(pb + k);
-    acc = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(a, b, acc, 0, 0, 0);
+  // arrays are padded to multiples of 64 rows and Dp to a multiple of 16,
+  // so every staged load stays in bounds
+  for (int32_t k0 = 0; k0 < Dp; k0 += GEMM_KC) {
+    const int kc = Dp - k0 < GEMM_KC ? int(Dp - k0) : GEMM_KC;
+    const int pieces = kc / 8;   // 16-byte pieces per row
+    __syncthreads();             // the previous stage has been read
+    for (int idx = threadIdx.x; idx < 64 * pieces; idx += 256) {
+      const int r = idx / pieces, c = (idx % pieces) * 8;
+      *reinterpret_cast<uint4*>(As + r * GEMM_LDS_ROW + c) =
+          *reinterpret_cast<const uint4*>(A + int64_t(mb + r) * Dp + k0 + c);
+      *reinterpret_cast<uint4*>(Bs + r * GEMM_LDS_ROW + c) =
+          *reinterpret_cast<const uint4*>(B + int64_t(nbk + r) * Dp + k0 + c);
+    }
+    __syncthreads();
+    for (int k = 0; k < kc; k += 16) {
+      const bf16x8 a = *reinterpret_cast<const bf16x8*>(As + (wm + row) * GEMM_LDS_ROW + k + kg);
+      const bf16x8 b = *reinterpret_cast<const bf16x8*>(Bs + (wn + row) * GEMM_LDS_ROW + k + kg);
+      acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, acc, 0, 0, 0);
+    }
   }
-  const int32_t col = n0 + (lane & 31);
+  const int32_t m0 = mb + wm;
+  const int32_t col = nbk + wn + (lane & 31);
   for (int r = 0; r < 16; ++r) {
     int32_t mrow = m0 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
     if (mrow < nva && col < nvb) {
@@ -100,24 +120,8 @@ __global__ void k_nonfinite(const float* a, int64_t n, int* err) {
   if (i < n && !isfinite(a[i])) atomicOr(err, 1);
 }
 
-// one block per query vertex: bitonic sort of (squared distance, index) keys
-// in LDS, first K indices out.  dir 0: rows of d2 (X queries), 1: columns.
-__global__ __launch_bounds__(256) void k_topk(const float* d2, int32_t nvx, int32_t nvy, int dir,
-                                              int32_t K, int32_t* out) {
-  __shared__ uint64_t keys[TOPK_MAX];
-  const int32_t q = blockIdx.x;
-  const int32_t n = dir == 0 ? nvy : nvx;
-  int32_t np2 = 1;
-  while (np2 < n) np2 <<= 1;
-  for (int32_t i = threadIdx.x; i < np2; i += blockDim.x) {
-    uint64_t key = ~uint64_t(0);
-    if (i < n) {
-      float v = dir == 0 ? d2[int64_t(q) * nvy + i] : d2[int64_t(i) * nvy + q];
-      key = (uint64_t(__float_as_uint(v + 0.0f)) << 32) | uint32_t(i);
-    }
-    keys[i] = key;
-  }
-  __syncthreads();
+// ascending bitonic sort of np2 keys (a power of two) in LDS by one block
+__device__ void bitonic_lds(uint64_t* keys, int32_t np2) {
   for (int32_t size = 2; size <= np2; size <<= 1) {
     for (int32_t stride = size >> 1; stride > 0; stride >>= 1) {
       for (int32_t i = threadIdx.x; i < np2; i += blockDim.x) {
@@ -134,9 +138,42 @@ __global__ __launch_bounds__(256) void k_topk(const float* d2, int32_t nvx, int3
       __syncthreads();
     }
   }
-  for (int32_t k = threadIdx.x; k < K; k += blockDim.x) out[int64_t(q) * K + k] = int32_t(keys[k] & 0xFFFFFFFFu);
 }
 
+// one block per query vertex: (squared distance, index) keys sorted in LDS,
+// first K indices out.  dir 0: rows of d2 (X queries), 1: columns.  A row of
+// at most TOPK_MAX keys is sorted whole.  A longer row goes through the table
+// in chunks: the K best keys so far stay in front, the rest of the table
+// takes the next keys of the row, and the table is sorted again (the caller
+// checks K <= TOPK_MAX / 2), so the result is the same K smallest keys.
+__global__ __launch_bounds__(256) void k_topk(const float* d2, int32_t nvx, int32_t nvy, int dir,
+                                              int32_t K, int32_t* out) {
+  __shared__ uint64_t keys[TOPK_MAX];
+  const int32_t q = blockIdx.x;
+  const int32_t n = dir == 0 ? nvy : nvx;
+  auto key = [&](int32_t i) -> uint64_t {
+    if (i >= n) return ~uint64_t(0);
+    const float v = dir == 0 ? d2[int64_t(q) * nvy + i] : d2[int64_t(i) * nvy + q];
+    return (uint64_t(__float_as_uint(v + 0.0f)) << 32) | uint32_t(i);
+  };
+  if (n <= TOPK_MAX) {
+    int32_t np2 = 1;
+    while (np2 < n) np2 <<= 1;
+    for (int32_t i = threadIdx.x; i < np2; i += blockDim.x) keys[i] = key(i);
+    __syncthreads();
+    bitonic_lds(keys, np2);
+  } else {
+    int32_t next = 0, kept = 0;   // uniform across the block
+    while (next < n) {
+      for (int32_t i = kept + int32_t(threadIdx.x); i < TOPK_MAX; i += blockDim.x) keys[i] = key(next + i - kept);
+      __syncthreads();
+      bitonic_lds(keys, TOPK_MAX);
+      next += TOPK_MAX - kept;
+      kept = K;
+    }
+  }
+  for (int32_t k = threadIdx.x; k < K; k += blockDim.x) out[int64_t(q) * K + k] = int32_t(keys[k] & 0xFFFFFFFFu);
+}
 
 __global__ void k_zero_i32(int* p) { *p = 0; }
 
@@ -168,7 +205,7 @@ size_t knn_layout(int32_t nvx, int32_t nvy, int32_t D, int32_t prec, bool with_d
   b.err = reinterpret_cast<int*>(take(sizeof(int)));
   if (with_d2) b.d2 = reinterpret_cast<float*>(take(sizeof(float) * size_t(nvx) * size_t(nvy)));
   if (prec == DM_PREC_BF16) {
-    const size_t Dp = size_t(D + 7) / 8 * 8;
+    const size_t Dp = size_t(D + 15) / 16 * 16;
     const size_t nxp = size_t(nvx + 63) / 64 * 64, nyp = size_t(nvy + 63) / 64 * 64;
     b.A = reinterpret_cast<uint16_t*>(take(sizeof(uint16_t) * nxp * Dp));
     b.B = reinterpret_cast<uint16_t*>(take(sizeof(uint16_t) * nyp * Dp));
@@ -205,7 +242,7 @@ dm_status distances_into(dm_ctx* ctx, const float* FX, int32_t nvx, const float*
   hipStream_t st = ctx->stream;
   DM_TRY(check_finite_into(ctx, FX, int64_t(nvx) * D, FY, int64_t(nvy) * D, w.err));
   if (prec == DM_PREC_BF16) {
-    const int32_t Dp = (D + 7) / 8 * 8;
+    const int32_t Dp = (D + 15) / 16 * 16;
     const int32_t nxp = (nvx + 63) / 64 * 64, nyp = (nvy + 63) / 64 * 64;
     k_to_bf16<<<grid_for(nxp, 128), 128, 0, st>>>(FX, nvx, D, nxp, Dp, w.A, w.na);
     k_to_bf16<<<grid_for(nyp, 128), 128, 0, st>>>(FY, nvy, D, nyp, Dp, w.B, w.nb);
@@ -226,7 +263,8 @@ dm_status knn_check_args(dm_ctx* ctx, const char* name, const float* FX, int32_t
                          int32_t nvy, int32_t D, int32_t K, int32_t prec, const int32_t* cand_xy,
                          const int32_t* cand_yx) {
   if (!FX || !FY || !cand_xy || !cand_yx) return dm_fail(ctx, DM_ERR_INVALID_ARG, "%s: NULL argument", name);
-  if (nvx < 1 || nvy < 1 || nvx > TOPK_MAX || nvy > TOPK_MAX || D < 1 || K < 1 || K > nvx || K > nvy)
+  if (nvx < 1 || nvy < 1 || D < 1 || K < 1 || K > nvx || K > nvy ||
+      ((nvx > TOPK_MAX || nvy > TOPK_MAX) && K > TOPK_MAX / 2) || nvx > (1 << 21) || nvy > (1 << 21))
     return dm_fail(ctx, DM_ERR_INVALID_ARG, "%s: nvx=%d nvy=%d D=%d K=%d out of range", name, nvx, nvy, D, K);
   if (prec != DM_PREC_BF16 && prec != DM_PREC_FP32 && prec != DM_PREC_FP64)
     return dm_fail(ctx, DM_ERR_INVALID_ARG, "%s: unknown precision %d", name, prec);

@@ -185,6 +185,43 @@ def test_knn_candidates(cfg, prec):
     assert near_ties <= (2 if prec == "fp32" else 0.2 * (len(p.DX) + len(p.DY)))
 
 
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+def test_knn_rows_longer_than_one_lds_table(prec):
+    """Both sides above the top-K kernel's 4096-key LDS table (5000 and 4500
+    vertices), so every query row goes through the table in chunks that keep
+    the best K so far: the sets must equal the oracle's K nearest (on the
+    BF16-rounded descriptors for the BF16 form) except where the K-th and
+    (K+1)-th squared distances lie within the FP32 error of the distance
+    computation.  K = 2049 is refused at this size."""
+    rng = np.random.default_rng(5)
+    DX = rng.standard_normal((5000, 24)).astype(np.float32)
+    DY = rng.standard_normal((4500, 24)).astype(np.float32)
+    K = 40
+    say(f"[knn-long] prec={prec} nvx=5000 nvy=4500 D=24 K={K}")
+    ctx = dm().Context(0)
+    cxy, cyx = ctx.knn_candidates(torch.from_numpy(DX), torch.from_numpy(DY), K, prec)
+    BX, BY = (bf16_rne(DX), bf16_rne(DY)) if prec == "bf16" else (DX, DY)
+    rxy, ryx = O.knn(BX, BY, K)
+    bx, by = BX.astype(np.float64), BY.astype(np.float64)
+    D2 = (bx ** 2).sum(1)[:, None] + (by ** 2).sum(1)[None] - 2.0 * bx @ by.T
+    nx, ny = (bx ** 2).sum(1), (by ** 2).sum(1)
+    eps = 4.0 * bx.shape[1] * 2.0 ** -24
+    differ = 0
+    for G, R, Dm, nq, nc in [(np_(cxy), rxy, D2, nx, ny), (np_(cyx), ryx, D2.T, ny, nx)]:
+        assert G.min() >= 0 and G.max() < Dm.shape[1]
+        for q in range(len(G)):
+            assert len(set(G[q])) == K
+            if set(G[q]) == set(R[q]):
+                continue
+            srt = np.sort(Dm[q])
+            assert srt[K] - srt[K - 1] <= eps * (nq[q] + nc.max()), (q, srt[K - 1], srt[K])
+            differ += 1
+    say(f"  candidate sets differing at FP32 near ties: {differ} of 9500")
+    assert differ <= 0.01 * 9500
+    with pytest.raises(dm().DMError):
+        ctx.knn_candidates(torch.from_numpy(DX), torch.from_numpy(DY), 2049, prec)
+
+
 @pytest.mark.parametrize("case", ["cfg2", "cfg3", "d16", "d72", "d200"])
 def test_knn_bf16_matches_rounded_inputs(case):
     """BF16 candidates against the oracle run on the same BF16-rounded
