@@ -70,7 +70,7 @@ def test_dual_fp64_parity(cfg, over, K, iters):
 
 
 @pytest.mark.parametrize("cfg,over,K,iters", [(2, {}, 16, 60), (1, {"desc_noise": 1.0}, 16, 300),
-                                              (2, {"desc_noise": 0.5}, 16, 40)])
+                                              (2, {"desc_noise": 0.5}, 16, 40), (2, {}, 16, 1000)])
 def test_dual_fp32_parity(cfg, over, K, iters):
     p = make_pair(cfg, 0, **over)
     S, ctx = both(p, K, "fp32")

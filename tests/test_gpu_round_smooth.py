@@ -20,7 +20,8 @@ from synth import make_pair
 pytestmark = pytest.mark.gpu
 
 
-@pytest.mark.parametrize("cfg,seed,prec", [(1, 0, "fp64"), (1, 2, "fp32"), (2, 0, "fp32"), (2, 3, "fp32")])
+@pytest.mark.parametrize("cfg,seed,prec", [(1, 0, "fp64"), (1, 2, "fp32"), (2, 0, "fp32"), (2, 3, "fp32"),
+                                           (3, 0, "fp32")])
 def test_rounding_feasible(cfg, seed, prec):
     p = make_pair(cfg, seed)
     S, ctx = both(p, p.spec.k, "fp64" if prec == "fp64" else "fp32")
