@@ -43,6 +43,7 @@ extern "C" dm_status dm_create(int32_t device, void* hip_stream, dm_ctx** out) {
   c->device = device;
   c->stream = static_cast<hipStream_t>(hip_stream);
   c->pool = pool;
+  c->cache.stream = c->stream;
   // pinned landing slots for small device-to-host reads
   if (hipHostMalloc(reinterpret_cast<void**>(&c->host_i32), HOST_SLOTS * sizeof(int32_t), hipHostMallocDefault) !=
       hipSuccess) {
@@ -68,7 +69,7 @@ extern "C" dm_status dm_destroy(dm_ctx* ctx) {
   if (ctx->host_i32) (void)hipHostFree(ctx->host_i32);
   hipMemPool_t pool = ctx->pool;
   hipStream_t st = ctx->stream;
-  delete ctx;   // frees every owned array on the stream
+  delete ctx;   // frees every owned array and cached block on the stream
   (void)hipStreamSynchronize(st);
   if (pool) (void)hipMemPoolDestroy(pool);
   return DM_OK;
@@ -84,8 +85,10 @@ extern "C" dm_status dm_set_stream(dm_ctx* ctx, void* hip_stream) {
   if (s != ctx->stream) {
     DM_HIP(ctx, hipSetDevice(ctx->device));
     DM_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    ctx->cache.release_all();   // cached blocks were last used on the old stream
   }
   ctx->stream = s;
+  ctx->cache.stream = s;
   return DM_OK;
 }
 

@@ -6,6 +6,7 @@
 
 #include <cstdint>
 #include <cstdio>
+#include <map>
 #include <string>
 #include <vector>
 
@@ -33,13 +34,54 @@ dm_status dm_fail(dm_ctx* ctx, dm_status code, const char* fmt, ...);
 #define DM_LAUNCH_CHECK(ctx) DM_HIP(ctx, hipGetLastError())
 
 // ---------------------------------------------------------------------------
-// device array.  An owned array is allocated and freed stream-ordered on the
-// context's stream from the context's own memory pool (hipMallocFromPoolAsync
-// / hipFreeAsync; the pool keeps freed blocks for reuse until dm_destroy), so
-// the temporaries of the build steps cost no device-wide synchronisation and
-// no other user of the device's default pool is affected.  A block freed on
-// a stream is reused only by work ordered after the free on that stream.  A
-// view (attach) borrows caller memory and never frees it.
+// Blocks a context has freed, kept for its later allocations.  Returning a
+// block to a stream-ordered pool costs the host about 12 us per
+// hipFreeAsync (more for large blocks), and a product-space build frees
+// about ninety temporaries, so a context keeps them here by size class
+// (bytes rounded up to 256) and an allocation of the same class takes one
+// back without a runtime call.  Every block is used on the context's
+// stream, so stream order alone makes the reuse safe: a block is taken only
+// by work ordered after everything that used it before.  The cache holds at
+// most MAX_BYTES; blocks beyond that, and every block when the context's
+// stream changes or the context is destroyed, go back to the pool.
+// ---------------------------------------------------------------------------
+struct BlockCache {
+  static constexpr size_t MAX_BYTES = size_t(4) << 30;
+  std::multimap<size_t, void*> blocks;
+  size_t bytes = 0;
+  hipStream_t stream = nullptr;   // the stream every cached block was last used on
+  static size_t size_class(size_t b) { return (b + 255) / 256 * 256; }
+  void* take(size_t cls) {
+    auto it = blocks.find(cls);
+    if (it == blocks.end()) return nullptr;
+    void* q = it->second;
+    blocks.erase(it);
+    bytes -= cls;
+    return q;
+  }
+  bool keep(void* q, size_t cls) {
+    if (bytes + cls > MAX_BYTES) return false;
+    blocks.emplace(cls, q);
+    bytes += cls;
+    return true;
+  }
+  void release_all() {
+    for (auto& kv : blocks) (void)hipFreeAsync(kv.second, stream);
+    blocks.clear();
+    bytes = 0;
+  }
+  ~BlockCache() { release_all(); }
+};
+
+// ---------------------------------------------------------------------------
+// device array.  An owned array is allocated stream-ordered on the context's
+// stream from the context's own memory pool (hipMallocFromPoolAsync) or from
+// the context's block cache, and given back to the cache (or, past its
+// limit, freed with hipFreeAsync), so the temporaries of the build steps cost
+// no device-wide synchronisation and no other user of the device's default
+// pool is affected.  A block freed on a stream is reused only by work
+// ordered after the free on that stream.  A view (attach) borrows caller
+// memory and never frees it.
 // ---------------------------------------------------------------------------
 template <typename T>
 struct DArr {
@@ -47,23 +89,36 @@ struct DArr {
   size_t n = 0;
   hipStream_t s = nullptr;   // stream the block was allocated on
   bool view = false;         // borrowed memory: never freed here
+  BlockCache* cache = nullptr;   // where the block goes back to, or NULL
+  size_t cls = 0;                // its size class in bytes
   DArr() = default;
   DArr(const DArr&) = delete;
   DArr& operator=(const DArr&) = delete;
   ~DArr() { release(); }
   void release() {
-    if (p && !view) (void)hipFreeAsync(p, s);
+    if (p && !view && !(cache && cache->stream == s && cache->keep(p, cls))) (void)hipFreeAsync(p, s);
     p = nullptr;
     n = 0;
     view = false;
+    cache = nullptr;
+    cls = 0;
   }
-  hipError_t resize(size_t count, hipStream_t stream, hipMemPool_t pool) {
+  hipError_t resize(size_t count, hipStream_t stream, hipMemPool_t pool, BlockCache* bc = nullptr) {
     if (count == n && p && !view) return hipSuccess;
     release();
+    if (count == 0) return hipSuccess;
+    const size_t c = BlockCache::size_class(count * sizeof(T));
+    void* q = (bc && bc->stream == stream) ? bc->take(c) : nullptr;
+    if (!q) {
+      const hipError_t e = hipMallocFromPoolAsync(&q, c, pool, stream);
+      if (e != hipSuccess) return e;
+    }
+    p = static_cast<T*>(q);
     n = count;
     s = stream;
-    if (count == 0) return hipSuccess;
-    return hipMallocFromPoolAsync(reinterpret_cast<void**>(&p), count * sizeof(T), pool, stream);
+    cache = bc;
+    cls = c;
+    return hipSuccess;
   }
   void attach(T* ptr, size_t count) {
     release();
@@ -73,7 +128,7 @@ struct DArr {
   }
 };
 
-#define DM_ALLOC(ctx, arr, count) DM_HIP(ctx, (arr).resize(count, (ctx)->stream, (ctx)->pool))
+#define DM_ALLOC(ctx, arr, count) DM_HIP(ctx, (arr).resize(count, (ctx)->stream, (ctx)->pool, &(ctx)->cache))
 
 struct MeshDev {
   int32_t nv = 0, nf = 0, ne = 0;
@@ -184,6 +239,7 @@ struct dm_ctx {
   int device = 0;
   hipStream_t stream = nullptr;
   hipMemPool_t pool = nullptr;   // the context's own pool (every DArr allocation)
+  BlockCache cache;              // declared before every array: destroyed after them
   std::string err;
   // caller-owned solver workspace per message precision (0 FP32, 1 FP64),
   // see dm_set_workspace; NULL when the library allocates the state itself
