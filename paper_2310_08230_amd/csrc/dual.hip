@@ -573,13 +573,14 @@ struct RecRaw<double> {
   }
 };
 
-template <typename R, int MODE>
+// TB: FP32 records in flight per batch (8 or 16); every load of a batch is
+// issued before the first one is used (a missing entry loads record 0 and is
+// then replaced).  FP64 records are twice as wide and go two at a time.
+template <typename R, int MODE, int TB>
 __device__ inline double tile_rows(const SweepArgs& A, const R* __restrict__ rin, R* __restrict__ out, R omega,
                                    R gam, const uint32_t* __restrict__ tw) {
   constexpr int H = TILE_HALF;
-  // records in flight per batch: every load of a batch is issued before the
-  // first one is used (a missing entry loads record 0 and is then replaced)
-  constexpr int B = sizeof(R) == 4 ? 4 : 2;
+  constexpr int B = sizeof(R) == 4 ? TB : 2;
   const int lane = threadIdx.x & 63;
   uint32_t wv[2 * H];
 #pragma unroll
@@ -673,13 +674,13 @@ __device__ inline double tile_rows(const SweepArgs& A, const R* __restrict__ rin
   return rowmin;
 }
 
-template <typename R, int MODE>
+template <typename R, int MODE, int TB>
 __device__ void tile_block(const SweepArgs& A, const R* __restrict__ rin, R* __restrict__ out, R omega, R gam,
                            double* red, int32_t item) {
   const int32_t t = item * 4 + int32_t(threadIdx.x >> 6);
   double rowpart = 0.0;
   if (t < A.n_tiles)   // uniform across the wave
-    rowpart = tile_rows<R, MODE>(A, rin, out, omega, gam, A.tile_word + size_t(t) * (2 * TILE_HALF * 64));
+    rowpart = tile_rows<R, MODE, TB>(A, rin, out, omega, gam, A.tile_word + size_t(t) * (2 * TILE_HALF * 64));
   const double part = block_sum(rowpart, red);
   store_partial(part, A.partial, item);
 }
@@ -974,10 +975,10 @@ constexpr size_t smem_bytes() {
   return SOFT ? (SOFT_FTAB + 256) * sizeof(R) + 256 : 768 * sizeof(R);
 }
 
-// TILES: the hard form's launch has one-lane-per-row tiles (their register
-// use sets the occupancy of the whole kernel, so launches without tiles take
-// the instantiation without them)
-template <typename R, bool SOFT, int MODE, bool TILES>
+// TB > 0: the hard form's launch has one-lane-per-row tiles, whose record
+// loads go TB at a time (their register use sets the occupancy of the whole
+// kernel, so launches without tiles take the instantiation TB = 0)
+template <typename R, bool SOFT, int MODE, int TB>
 __global__ __launch_bounds__(256) void k_sweep(SweepArgs A, const R* __restrict__ rin, R* __restrict__ out,
                                                R omega, R T) {
   __shared__ __align__(16) unsigned char smem[smem_bytes<R, SOFT>()];
@@ -996,9 +997,14 @@ __global__ __launch_bounds__(256) void k_sweep(SweepArgs A, const R* __restrict_
     if (k0 >= A.xcd_stride) return;
     const int32_t item = A.xcd_item[x * A.xcd_stride + k0];
     if (item < 0) return;
-    if (TILES && item < A.n_tile_items) tile_block<R, MODE>(A, rin, out, omega, gam, red, item);
-    else if (item < A.n_short_blocks) short_wave_hard<R, MODE>(A, rin, out, omega, gam, smem, red, item);
-    else long_rows<R, false, MODE, TILES ? 4 : 2>(A, rin, out, omega, T, gam, red, item);
+    if constexpr (TB > 0) {
+      if (item < A.n_tile_items) {
+        tile_block<R, MODE, TB>(A, rin, out, omega, gam, red, item);
+        return;
+      }
+    }
+    if (item < A.n_short_blocks) short_wave_hard<R, MODE>(A, rin, out, omega, gam, smem, red, item);
+    else long_rows<R, false, MODE, (TB > 0 ? 4 : 2)>(A, rin, out, omega, T, gam, red, item);
     return;
   }
   int32_t item;
@@ -1078,21 +1084,27 @@ __global__ __launch_bounds__(256) void k_reduce_last(const double* partial, int 
 
 // one sweep launch; with timing events the launch records the kernel's own
 // start and end (hipExtLaunchKernelGGL), as a kernel trace does
-template <typename R, bool SOFT, int MODE, bool TILES = false>
+template <typename R, bool SOFT, int MODE, int TB = 0>
 void launch_sweep(hipStream_t st, unsigned grid, hipEvent_t e0, hipEvent_t e1, const SweepArgs& A, const R* ri,
                   R* ro, R omega, R T) {
   if (e0)
-    hipExtLaunchKernelGGL(k_sweep<R, SOFT, MODE, TILES>, dim3(grid), dim3(256), 0, st, e0, e1, 0, A, ri, ro, omega,
-                          T);
+    hipExtLaunchKernelGGL(k_sweep<R, SOFT, MODE, TB>, dim3(grid), dim3(256), 0, st, e0, e1, 0, A, ri, ro, omega, T);
   else
-    k_sweep<R, SOFT, MODE, TILES><<<grid, 256, 0, st>>>(A, ri, ro, omega, T);
+    k_sweep<R, SOFT, MODE, TB><<<grid, 256, 0, st>>>(A, ri, ro, omega, T);
 }
 
+// Tile record loads: 16 in flight per lane once there are at least
+// TILE_WIDE_BATCH tiles (more latency hidden per wave, 1000-face pair 46 ->
+// 42 us), 8 below (the 500-face pair's 900 tiles are 1 % faster so); FP64
+// sweeps take one instantiation (their batches are two records).
+constexpr int32_t TILE_WIDE_BATCH = 2048;
 template <typename R, int MODE>
-void launch_hard(bool tiles, hipStream_t st, unsigned grid, hipEvent_t e0, hipEvent_t e1, const SweepArgs& A,
+void launch_hard(int32_t n_tiles, hipStream_t st, unsigned grid, hipEvent_t e0, hipEvent_t e1, const SweepArgs& A,
                  const R* ri, R* ro, R omega, R T) {
-  if (tiles) launch_sweep<R, false, MODE, true>(st, grid, e0, e1, A, ri, ro, omega, T);
-  else launch_sweep<R, false, MODE, false>(st, grid, e0, e1, A, ri, ro, omega, T);
+  if (n_tiles <= 0) launch_sweep<R, false, MODE, 0>(st, grid, e0, e1, A, ri, ro, omega, T);
+  else if (sizeof(R) == 4 && n_tiles >= TILE_WIDE_BATCH)
+    launch_sweep<R, false, MODE, 16>(st, grid, e0, e1, A, ri, ro, omega, T);
+  else launch_sweep<R, false, MODE, 8>(st, grid, e0, e1, A, ri, ro, omega, T);
 }
 
 }  // namespace
@@ -1267,7 +1279,7 @@ dm_status dual_sweep(dm_ctx* ctx, int mode, bool soft, const unsigned char* rin,
     else if (mode == MODE_EVAL) launch_sweep<R, true, MODE_EVAL>(st, grid, e0, e1, A, ri, ro, omega, T);
     else launch_sweep<R, true, MODE_BOUND>(st, grid, e0, e1, A, ri, ro, omega, T);
   } else {
-    const bool tiles = ctx->n_tiles > 0;
+    const int32_t tiles = ctx->n_tiles;
     if (mode == MODE_UPDATE) launch_hard<R, MODE_UPDATE>(tiles, st, grid, e0, e1, A, ri, ro, omega, T);
     else if (mode == MODE_EVAL) launch_hard<R, MODE_EVAL>(tiles, st, grid, e0, e1, A, ri, ro, omega, T);
     else if (mode == MODE_BOUND) launch_hard<R, MODE_BOUND>(tiles, st, grid, e0, e1, A, ri, ro, omega, T);

@@ -192,10 +192,12 @@ constexpr int TILE_HALF = 8;
 constexpr int TILE_WORDS = 2 * TILE_HALF * 64;
 // Tiles cut the sweep's vector instructions several times over, but a tile
 // wave touches the records of 64 rows at once: on problems of more than
-// TILE_NNZ_MAX nonzeros (records well past what the L2s hold) the wider
-// footprint costs more in record traffic than the instructions save, and all
-// short rows stay in chunks.
-constexpr int64_t TILE_NNZ_MAX = int64_t(8) << 20;
+// TILE_NNZ_MAX nonzeros (records well past what the L2s and the Infinity
+// Cache hold) the wider footprint costs more in record traffic than the
+// instructions save, and all short rows stay in chunks (2000/3000-face pair,
+// 17.8 M nonzeros: 250 us with tiles, 260 us in chunks; the same geometry
+// with 52.7 M nonzeros: 875 us with tiles, 839 us in chunks).
+constexpr int64_t TILE_NNZ_MAX = int64_t(24) << 20;
 
 __global__ void k_short_sort_keys(const int32_t* rkey, const int32_t* rrow_ptr, const int32_t* rrow_b,
                                   const uint32_t* word, int64_t n_short, int tiles_on, int kbits, uint32_t* key,
