@@ -84,7 +84,10 @@ typedef struct {
  * stream-ordered, on that stream, from a memory pool that the context creates
  * for itself and destroys in dm_destroy; the pool keeps freed blocks for the
  * context's later calls and leaves the device's default pool untouched.  The
- * stream must stay valid until dm_destroy.  Errors: DM_ERR_INVALID_ARG (no
+ * context also keeps up to 4 GiB of the blocks it frees, by size, and hands
+ * them to its later allocations of the same size without a runtime call
+ * (dm_set_stream to another stream, and dm_destroy, return them to the
+ * pool).  The stream must stay valid until dm_destroy.  Errors: DM_ERR_INVALID_ARG (no
  * such device), DM_ERR_HIP (the pool or pinned host slots could not be
  * created). */
 dm_status dm_create(int32_t device, void* hip_stream, dm_ctx** out);
