@@ -437,6 +437,27 @@ dm_status dm_exact_search(dm_ctx* ctx, const dm_search_params* params, const int
                           double* primal_obj, double* bound, int32_t* nodes, int32_t* status,
                           dm_space_info* info);
 
+/* Local repair of a primal (Appendix "Coarse-to-fine solving strategy": the
+ * confident part of an assignment stays fixed and the rest is solved
+ * exactly, here by the exact search above).  The rows of the full ILP that x
+ * violates define a neighbourhood: step 1 takes every element of those rows,
+ * each further step adds the elements of the closedness rows that touch the
+ * neighbourhood (projection rows, which span a face's candidates, are not
+ * followed).  Every element outside the neighbourhood keeps its value in x
+ * (elements fixed by presolve keep theirs), and dm_exact_search with params
+ * solves the neighbourhood; when it has no feasible completion the
+ * neighbourhood grows by one step, up to max_hops steps.  A feasible x is
+ * returned unchanged with its objective.  The problem the context held
+ * before the call (with any dm_fix_variables fixings) is in place afterwards,
+ * so its multiplier arrays stay valid.
+ *  x [device] uint8 [n_prod_tri] in/out: the repaired assignment when one is
+ *  found, else unchanged; *primal_obj [host] (+inf if none), *feasible
+ *  [host], *hops_used [host] (steps of the last neighbourhood searched, 0 if
+ *  x was feasible), *n_free [host] (its free elements).  Errors as
+ *  dm_exact_search; DM_ERR_INVALID_ARG for max_hops < 1.  Synchronises. */
+dm_status dm_repair_primal(dm_ctx* ctx, const dm_search_params* params, int32_t max_hops, uint8_t* x,
+                           double* primal_obj, int32_t* feasible, int32_t* hops_used, int64_t* n_free);
+
 /* Gradient of the smoothed bound L_T(lambda) (A11).  With
  * lambda^j_i = c_i/|J_i| + phi^j_i and phi held fixed:
  *   dL/dc_i = mean_j mu^j_i (free), 1 (fixed to 1), 0 (fixed to 0),

@@ -99,6 +99,7 @@ def lib():
             "dm_matched_pairs": [P, P, P, I32, P],
             "dm_ring_candidates": [P, P, P, P, I32, I32, I32, P, P, P],
             "dm_exact_search": [P, P, P, P, P, P, P, P, P],
+            "dm_repair_primal": [P, P, I32, P, P, P, P, P],
             "dm_workspace_query": [P, I32, P],
             "dm_set_workspace": [P, I32, P, C.c_size_t],
         }
@@ -155,7 +156,7 @@ class Context:
             pass
 
     _CHANGES_PROBLEM = frozenset(("dm_build_product_space", "dm_build_ilp", "dm_build_costs", "dm_set_costs",
-                                  "dm_fix_variables", "dm_exact_search"))
+                                  "dm_fix_variables", "dm_exact_search", "dm_repair_primal"))
 
     def _call(self, name, *args):
         if name in self._CHANGES_PROBLEM:
@@ -424,6 +425,19 @@ class Context:
         finally:   # the problem with base_fix is in place afterwards
             self.info = {k: getattr(info, k) for k, _ in dm_space_info._fields_}
         return x, p.value, b.value, n.value, SEARCH_STATUS[st.value]
+
+    def repair_primal(self, x, max_hops=8, max_nodes=200, dual_iters=100, omega=0.5, rel_tol=1e-9,
+                      msg_prec="fp32", rounds=10, iters_per_round=25, delta0=0.0, gamma=1.5, seed=0):
+        """Local exact repair of x around the rows it violates; returns (x,
+        primal objective, feasible, steps of the last neighbourhood, its free
+        elements).  x is repaired in place when it is a uint8 device tensor."""
+        x = _dev(x, torch.uint8, self.device)
+        R = dm_round_params(rounds, iters_per_round, delta0, gamma, seed, omega, PREC[msg_prec])
+        P = dm_search_params(max_nodes, dual_iters, omega, rel_tol, R)
+        p, feas, hops, nfree = C.c_double(0), C.c_int32(0), C.c_int32(0), C.c_int64(0)
+        self._call("dm_repair_primal", C.byref(P), int(max_hops), _ptr(x), C.byref(p), C.byref(feas),
+                   C.byref(hops), C.byref(nfree))
+        return x, p.value, bool(feas.value), hops.value, nfree.value
 
     def check_primal(self, x):
         x = _dev(x, torch.uint8, self.device)

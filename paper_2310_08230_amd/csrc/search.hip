@@ -65,6 +65,54 @@ __global__ void k_state_to_x(const int8_t* state, int64_t nP, uint8_t* x) {
   if (p < nP) x[p] = state[p] == 1 ? 1 : 0;
 }
 
+// ---- local repair: the neighbourhood of the rows a primal violates
+// rows of the full problem that x violates (one thread per row)
+__global__ void k_viol_flags(const int32_t* row_ptr, const int32_t* ent_var, const int8_t* ent_coef,
+                             const int32_t* row_b, int64_t nrows, const uint8_t* x, uint8_t* rflag, int* count) {
+  const int64_t j = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (j >= nrows) return;
+  int64_t s = 0;
+  for (int32_t i = row_ptr[j]; i < row_ptr[j + 1]; ++i)
+    if (x[ent_var[i]]) s += ent_coef[i];
+  const bool v = s != row_b[j];
+  rflag[j] = v ? 1 : 0;
+  if (v) atomicAdd(count, 1);
+}
+
+// every element of a flagged row joins the neighbourhood (one thread per row;
+// a plain store of 1, so concurrent marks of one element agree)
+__global__ void k_mark_elems(const int32_t* row_ptr, const int32_t* ent_var, int64_t nrows, const uint8_t* rflag,
+                             uint8_t* eflag) {
+  const int64_t j = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (j >= nrows || !rflag[j]) return;
+  for (int32_t i = row_ptr[j]; i < row_ptr[j + 1]; ++i) eflag[ent_var[i]] = 1;
+}
+
+// a closedness row that touches the neighbourhood is flagged for the next
+// step (projection rows span a whole face's candidates and are not followed)
+__global__ void k_mark_rows(const int32_t* row_ptr, const int32_t* ent_var, int64_t nc, const uint8_t* eflag,
+                            uint8_t* rflag) {
+  const int64_t j = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (j >= nc || rflag[j]) return;
+  for (int32_t i = row_ptr[j]; i < row_ptr[j + 1]; ++i)
+    if (eflag[ent_var[i]]) {
+      rflag[j] = 1;
+      return;
+    }
+}
+
+// fixings of the repair: presolve's own fixings stay, the neighbourhood is
+// free, every other element keeps its value in x
+__global__ void k_repair_fix(const int8_t* state, const uint8_t* eflag, const uint8_t* x, int64_t nP, int8_t* fix,
+                             int* nfree) {
+  const int64_t p = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (p >= nP) return;
+  const int8_t st = state[p];
+  const bool free_ = st < 0 && eflag[p];
+  fix[p] = st >= 0 ? st : (free_ ? int8_t(-1) : int8_t(x[p] ? 1 : 0));
+  if (free_) atomicAdd(nfree, 1);
+}
+
 struct Decision {
   int32_t elem, value;
 };
@@ -270,4 +318,98 @@ extern "C" dm_status dm_exact_search(dm_ctx* ctx, const dm_search_params* params
   const dm_status s = exact_search(ctx, params, base_fix, x, primal_obj, bound, nodes, status);
   if (info && ctx->has_space) fill_info(ctx, info);   // also after an error: the sizes in force
   return s;
+}
+
+// Local repair of a primal (Appendix "Coarse-to-fine solving strategy": the
+// confident part of an assignment stays fixed and the rest is solved
+// exactly).  The neighbourhood of the rows x violates is freed step by step:
+// step 1 frees every element of the violated rows; each further step frees
+// the elements of the closedness rows that touch the neighbourhood.  Every
+// other element keeps its value in x (or its presolve value), and the exact
+// search solves the neighbourhood; a neighbourhood without a feasible
+// completion grows by one step, up to max_hops.
+static dm_status repair_primal(dm_ctx* ctx, const dm_search_params& P, int32_t max_hops, uint8_t* x,
+                               double* primal_obj, int32_t* feasible, int32_t* hops_used, int64_t* n_free) {
+  hipStream_t st = ctx->stream;
+  const int64_t nP = ctx->nP, nrows = ctx->n_rows_full, nc = ctx->n_closed_full;
+  *feasible = 0;
+  *hops_used = 0;
+  *n_free = 0;
+  *primal_obj = std::numeric_limits<double>::infinity();
+  DArr<uint8_t> rflag, eflag, xbest;
+  DArr<int8_t> fix, held;
+  DArr<int> cnt;
+  DM_ALLOC(ctx, rflag, size_t(std::max<int64_t>(nrows, 1)));
+  DM_ALLOC(ctx, eflag, size_t(std::max<int64_t>(nP, 1)));
+  DM_ALLOC(ctx, fix, size_t(std::max<int64_t>(nP, 1)));
+  DM_ALLOC(ctx, xbest, size_t(std::max<int64_t>(nP, 1)));
+  DM_ALLOC(ctx, cnt, 2);
+  DM_HIP(ctx, hipMemsetAsync(cnt.p, 0, 2 * sizeof(int), st));
+  k_viol_flags<<<grid_for(std::max<int64_t>(nrows, 1), 256), 256, 0, st>>>(
+      ctx->row_ptr.p, ctx->ent_var.p, ctx->ent_coef.p, ctx->row_b.p, nrows, x, rflag.p, cnt.p);
+  DM_LAUNCH_CHECK(ctx);
+  int32_t nviol = 0;
+  DM_TRY(read_i32(ctx, cnt.p, &nviol));
+  if (nviol == 0) {   // already feasible: nothing to repair
+    DM_ALLOC(ctx, ctx->scal, 16);
+    DM_TRY(sum_f64(ctx, ctx->cost64.p, nP, x, SUM_U8_NZ, ctx->scal.p + 1));
+    DM_HIP(ctx, hipMemcpyAsync(primal_obj, ctx->scal.p + 1, sizeof(double), hipMemcpyDeviceToHost, st));
+    DM_HIP(ctx, hipStreamSynchronize(st));
+    *feasible = 1;
+    return DM_OK;
+  }
+  // the fixings in force now (a presolve fixpoint), to restore this problem
+  DM_ALLOC(ctx, held, size_t(std::max<int64_t>(nP, 1)));
+  DM_HIP(ctx, hipMemcpyAsync(held.p, ctx->state.p, size_t(nP), hipMemcpyDeviceToDevice, st));
+  DM_HIP(ctx, hipMemsetAsync(eflag.p, 0, size_t(nP), st));
+  dm_status result = DM_OK;
+  for (int32_t h = 1; h <= max_hops; ++h) {
+    if (h > 1)
+      k_mark_rows<<<grid_for(std::max<int64_t>(nc, 1), 256), 256, 0, st>>>(ctx->row_ptr.p, ctx->ent_var.p, nc,
+                                                                           eflag.p, rflag.p);
+    k_mark_elems<<<grid_for(std::max<int64_t>(nrows, 1), 256), 256, 0, st>>>(ctx->row_ptr.p, ctx->ent_var.p, nrows,
+                                                                             rflag.p, eflag.p);
+    DM_HIP(ctx, hipMemsetAsync(cnt.p + 1, 0, sizeof(int), st));
+    k_repair_fix<<<grid_for(nP, 256), 256, 0, st>>>(ctx->state.p, eflag.p, x, nP, fix.p, cnt.p + 1);
+    DM_LAUNCH_CHECK(ctx);
+    int32_t nf = 0;
+    DM_TRY(read_i32(ctx, cnt.p + 1, &nf));
+    *hops_used = h;
+    *n_free = nf;
+    double pobj = 0.0, bound = 0.0;
+    int32_t nodes = 0, status = 0;
+    result = exact_search(ctx, &P, fix.p, xbest.p, &pobj, &bound, &nodes, &status);
+    if (result != DM_OK) break;
+    if (std::isfinite(pobj)) {
+      DM_HIP(ctx, hipMemcpyAsync(x, xbest.p, size_t(nP), hipMemcpyDeviceToDevice, st));
+      *primal_obj = pobj;
+      *feasible = 1;
+      break;
+    }
+  }
+  // back to the problem the context held (the search leaves its base in place)
+  const std::string msg = ctx->err;
+  const dm_status rs = presolve_reduce(ctx, held.p);
+  if (rs != DM_OK) {
+    ctx->has_space = false;
+    return result != DM_OK ? result : rs;
+  }
+  if (ctx->has_cost) DM_TRY(cost_offset(ctx));
+  ++ctx->cost_generation;
+  ctx->err = msg;
+  DM_HIP(ctx, hipStreamSynchronize(st));
+  return result;
+}
+
+extern "C" dm_status dm_repair_primal(dm_ctx* ctx, const dm_search_params* params, int32_t max_hops, uint8_t* x,
+                                      double* primal_obj, int32_t* feasible, int32_t* hops_used, int64_t* n_free) {
+  if (!ctx) return DM_ERR_INVALID_ARG;
+  ctx->err.clear();
+  if (!ctx->has_space || !ctx->has_cost) return dm_fail(ctx, DM_ERR_STATE, "dm_repair_primal: build space and costs first");
+  if (!params || !x || !primal_obj || !feasible || !hops_used || !n_free)
+    return dm_fail(ctx, DM_ERR_INVALID_ARG, "dm_repair_primal: NULL argument");
+  if (max_hops < 1) return dm_fail(ctx, DM_ERR_INVALID_ARG, "dm_repair_primal: max_hops must be at least 1");
+  DM_HIP(ctx, hipSetDevice(ctx->device));
+  DM_TRY(dual_flush(ctx));
+  return repair_primal(ctx, *params, max_hops, x, primal_obj, feasible, hops_used, n_free);
 }
