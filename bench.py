@@ -240,7 +240,7 @@ FORMS = {
 
 
 def time_to_gap(cfg, seed, form="plain_fp32", check_every=10, max_iters=3000, smooth_iters=50, solver="jacobi",
-                qn_check_every=10, qn_max_iters=400, rounds=10, **over):
+                qn_check_every=10, qn_max_iters=400, rounds=10, repair=True, **over):
     """Wall time from the first dual iteration until a rounding reaches a
     primal-dual gap <= 1e-2 (roundings and bound checks included; build
     excluded), for one of the three forms on one pair:
@@ -255,7 +255,9 @@ def time_to_gap(cfg, seed, form="plain_fp32", check_every=10, max_iters=3000, sm
     Every ``check_every`` Jacobi iterations (solver "jacobi") or
     ``qn_check_every`` quasi-Newton iterations (solver "lbfgs", the search
     state resumed between checks) the multipliers are rounded with ``rounds``
-    perturbation rounds.  The bound is certified: the FP64 dual objective at
+    perturbation rounds; with ``repair``, a rounding that leaves rows violated
+    is followed by the local exact repair (dm_repair_primal, at most 8
+    steps), whose time is included.  The bound is certified: the FP64 dual objective at
     the FP32 multipliers re-projected onto dual feasibility with the FP64
     costs (Eq. (D) holds at any feasible multipliers), maximised over the
     checks; d_max and p are both in FP64."""
@@ -279,6 +281,7 @@ def time_to_gap(cfg, seed, form="plain_fp32", check_every=10, max_iters=3000, sm
     dmax = -float("inf")
     it = 0
     best = None
+    repaired = 0
     cap = qn_max_iters if solver == "lbfgs" else max_iters
     while it < cap:
         if solver == "lbfgs":
@@ -288,16 +291,20 @@ def time_to_gap(cfg, seed, form="plain_fp32", check_every=10, max_iters=3000, sm
             lam, _ = c.dual_solve(lam, check_every, w.spec.omega, 0.0, trace=False)
             it += check_every
         dmax = max(dmax, c.lower_bound(lam.double()))
-        _, pobj, feas, _ = c.round_primal(lam, rounds=rounds, seed=0)
+        x, pobj, feas, _ = c.round_primal(lam, rounds=rounds, seed=0)
+        if not feas and repair:
+            _, pobj, feas, _, _ = c.repair_primal(x, max_hops=8)
+            repaired += bool(feas)
         if feas:
             g = (pobj - dmax) / pobj
             best = g if best is None else min(best, g)
             if g <= 1e-2:
                 torch.cuda.synchronize()
-                out.update(seconds=round(time.perf_counter() - t0, 6), iters=it, gap=g, bound=dmax, primal=pobj)
+                out.update(seconds=round(time.perf_counter() - t0, 6), iters=it, gap=g, bound=dmax, primal=pobj,
+                           repaired_checks=repaired)
                 return out
     torch.cuda.synchronize()
-    out.update(seconds=None, iters=it, gap=None, best_gap=best, bound=dmax,
+    out.update(seconds=None, iters=it, gap=None, best_gap=best, bound=dmax, repaired_checks=repaired,
                note="1% gap not reached within the iteration cap")
     return out
 
@@ -307,7 +314,8 @@ def pipeline_run(cfg=5, seed=0, iters=None, T=0.1):
     after each stage: BF16 candidates, product space + presolve, BF16 costs,
     FP32 Jacobi iterations with the FP64 bound trace, the certified FP64
     bound, rounding, and the smoothed backward pass (one soft sweep at the
-    final multipliers and the chain to both descriptor sets)."""
+    final multipliers and the chain to both descriptor sets).  A rounding
+    that leaves rows violated is followed by the local exact repair."""
     import torch
     w = Workload(cfg, seed, iters)
     c = w.ctx
@@ -333,11 +341,16 @@ def pipeline_run(cfg=5, seed=0, iters=None, T=0.1):
     t = mark("certified_bound_fp64", t)
     x, pobj, feas, _ = c.round_primal(lam, seed=0)
     t = mark("rounding", t)
+    rounded_feasible = feas
+    if not feas:   # local exact repair around the violated rows
+        x, pobj, feas, hops, nfree = c.repair_primal(x, max_hops=8)
+        t = mark("repair", t)
     _, gX, gY, LT = c.smoothed_backward(lam, T, w.DX, w.DY)
     t = mark("smoothed_backward", t)
     return {"pair": f"{w.spec.faces_x}/{w.spec.faces_y} faces, K={w.spec.k}, D={w.spec.dim}, seed {seed}",
             "nnz": info["nnz"], "jacobi_iters": w.iters, "seconds": round(t - t0, 6), "stages": stages,
             "bound_certified": lb, "bound_trace_max": float(tr.max()), "primal": pobj, "feasible": feas,
+            "rounding_feasible": rounded_feasible,
             "gap": (pobj - lb) / pobj if feas and pobj else None, "L_T": LT,
             "grad_finite": bool(torch.isfinite(gX).all() and torch.isfinite(gY).all())}
 
@@ -609,14 +622,15 @@ def main():
         seeds = [int(x) for x in a.gap_seeds.split(",")]
         # the three forms on the same pairs: the 1000-face pair (Jacobi) and
         # the largest pair (Jacobi and quasi-Newton)
-        runs = [(3, "jacobi"), (5, "jacobi"), (5, "lbfgs")]
-        for cfg, solver in runs:
-            for form in FORMS:
-                key = f"config_{cfg}_{form}_{solver}"
+        runs = [(3, "jacobi", FORMS, True), (5, "jacobi", FORMS, True), (5, "lbfgs", FORMS, True),
+                (5, "jacobi", ("mixed_bf16",), False)]   # the last: rounding alone, for comparison
+        for cfg, solver, forms, repair in runs:
+            for form in forms:
+                key = f"config_{cfg}_{form}_{solver}" + ("" if repair else "_rounding_only")
                 per_seed = {}
                 for sd in seeds:
                     log(f"[bench] time-to-1%-gap {key}, seed {sd}")
-                    kw = dict(form=form, solver=solver, check_every=10, qn_check_every=10)
+                    kw = dict(form=form, solver=solver, check_every=10, qn_check_every=10, repair=repair)
                     try:
                         if sd == seeds[0]:
                             time_to_gap(cfg, sd, max_iters=10, qn_max_iters=10, **kw)   # untimed: loads the kernels

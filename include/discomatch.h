@@ -449,7 +449,8 @@ dm_status dm_exact_search(dm_ctx* ctx, const dm_search_params* params, const int
  * neighbourhood grows by one step, up to max_hops steps.  A feasible x is
  * returned unchanged with its objective.  The problem the context held
  * before the call (with any dm_fix_variables fixings) is in place afterwards,
- * so its multiplier arrays stay valid.
+ * rebuilt identically, so its multiplier arrays stay valid and a
+ * dm_lbfgs_solve session on it can be resumed.
  *  x [device] uint8 [n_prod_tri] in/out: the repaired assignment when one is
  *  found, else unchanged; *primal_obj [host] (+inf if none), *feasible
  *  [host], *hops_used [host] (steps of the last neighbourhood searched, 0 if

@@ -156,7 +156,7 @@ class Context:
             pass
 
     _CHANGES_PROBLEM = frozenset(("dm_build_product_space", "dm_build_ilp", "dm_build_costs", "dm_set_costs",
-                                  "dm_fix_variables", "dm_exact_search", "dm_repair_primal"))
+                                  "dm_fix_variables", "dm_exact_search"))
 
     def _call(self, name, *args):
         if name in self._CHANGES_PROBLEM:

@@ -332,6 +332,7 @@ static dm_status repair_primal(dm_ctx* ctx, const dm_search_params& P, int32_t m
                                double* primal_obj, int32_t* feasible, int32_t* hops_used, int64_t* n_free) {
   hipStream_t st = ctx->stream;
   const int64_t nP = ctx->nP, nrows = ctx->n_rows_full, nc = ctx->n_closed_full;
+  const int64_t generation = ctx->cost_generation;
   *feasible = 0;
   *hops_used = 0;
   *n_free = 0;
@@ -395,7 +396,9 @@ static dm_status repair_primal(dm_ctx* ctx, const dm_search_params& P, int32_t m
     return result != DM_OK ? result : rs;
   }
   if (ctx->has_cost) DM_TRY(cost_offset(ctx));
-  ++ctx->cost_generation;
+  // the same problem as before the call (presolve from its own fixpoint
+  // rebuilds the same reduced arrays): solver sessions on it stay valid
+  ctx->cost_generation = generation;
   ctx->err = msg;
   DM_HIP(ctx, hipStreamSynchronize(st));
   return result;

@@ -11,6 +11,7 @@ import torch
 
 from gpu_common import both, dm, np_, say
 from helpers import matching_violations
+from oracle import oracle as O
 from synth import make_pair
 
 pytestmark = pytest.mark.gpu
@@ -144,3 +145,24 @@ def test_repair_at_the_largest_pair():
         say(f"  HiGHS on the neighbourhood ({int(free.sum())} free): {ref}")
         if ref is not None:
             assert pr >= ref - 1e-6 * abs(ref)
+
+
+def test_quasi_newton_resumes_across_a_repair():
+    """The repair rebuilds the problem it found, so a quasi-Newton session
+    resumes after it exactly as without it."""
+    p = make_pair(1, 0, desc_noise=1.0)
+    S, ctx = both(p, 16, "fp32")
+    ref = dm().Context(0)
+    ref.build_product_space(p.VX, p.FX, p.VY, p.FY, *O.knn(p.DX, p.DY, 16))
+    ref.build_costs(torch.from_numpy(p.DX), torch.from_numpy(p.DY), "fp32")
+    a = ctx.lbfgs_solve(ctx.init_lambda("fp32"), 10)[0]
+    b = ref.lbfgs_solve(ref.init_lambda("fp32"), 10)[0]
+    assert torch.equal(a, b)
+    x, _, feas, _ = ctx.round_primal(a, seed=0)
+    xd = np_(x).copy()
+    xd[np.nonzero(xd)[0][:2]] = 0   # a damaged primal to repair
+    _, pr, fr, hops, _ = ctx.repair_primal(torch.from_numpy(xd), max_hops=4)
+    say(f"  repair between the solves: feasible {fr}, {hops} steps")
+    a2, tra = ctx.lbfgs_solve(a, 10, resume=True)[:2]
+    b2, trb = ref.lbfgs_solve(b, 10, resume=True)[:2]
+    assert torch.equal(a2, b2) and torch.equal(tra, trb)
