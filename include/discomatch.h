@@ -445,7 +445,8 @@ dm_status dm_exact_search(dm_ctx* ctx, const dm_search_params* params, const int
  * neighbourhood (projection rows, which span a face's candidates, are not
  * followed).  Every element outside the neighbourhood keeps its value in x
  * (elements fixed by presolve keep theirs), and dm_exact_search with params
- * solves the neighbourhood; when it has no feasible completion the
+ * searches the neighbourhood (to optimality, or its best primal when it
+ * stops at params->max_nodes); when it finds no feasible completion the
  * neighbourhood grows by one step, up to max_hops steps.  A feasible x is
  * returned unchanged with its objective.  The problem the context held
  * before the call (with any dm_fix_variables fixings) is in place afterwards,
