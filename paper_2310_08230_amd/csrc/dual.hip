@@ -137,14 +137,43 @@ __device__ inline R min_dpp(R v) {
   return fmin(v, dpp_move<CTRL, R>(v) + R(0));
 }
 
+// FP32 values as integers of the same order (the sign-magnitude bits with
+// the magnitude flipped for negative values; every non-NaN value, infinities
+// included, keeps its place), so a segment minimum runs on integer DPP mins,
+// which need no NaN canonicalisation of the moved operand
+__device__ inline int32_t ordered_bits(float f) {
+  const int32_t i = __float_as_int(f);
+  return i ^ ((i >> 31) & 0x7FFFFFFF);
+}
+__device__ inline float from_ordered_bits(int32_t k) { return __int_as_float(k ^ ((k >> 31) & 0x7FFFFFFF)); }
+
+template <int CTRL>
+__device__ inline int32_t imin_dpp(int32_t v) {
+  const int32_t o = __builtin_amdgcn_mov_dpp(v, CTRL, 0xF, 0xF, true);
+  return o < v ? o : v;
+}
+
 template <int W, typename R>
 __device__ inline R seg_min(R v) {
-  v = min_dpp<0xB1>(v);
-  v = min_dpp<0x4E>(v);
-  v = min_dpp<0x141>(v);
-  if constexpr (W >= 16) v = min_dpp<0x140>(v);
-  if constexpr (W == 32) v = fmin(v, __shfl_xor(v, 16, 32) + R(0));
-  return v;
+  if constexpr (sizeof(R) == 4) {
+    int32_t k = ordered_bits(v);
+    k = imin_dpp<0xB1>(k);
+    k = imin_dpp<0x4E>(k);
+    k = imin_dpp<0x141>(k);
+    if constexpr (W >= 16) k = imin_dpp<0x140>(k);
+    if constexpr (W == 32) {
+      const int32_t o = __shfl_xor(k, 16, 32);
+      k = o < k ? o : k;
+    }
+    return from_ordered_bits(k);
+  } else {
+    v = min_dpp<0xB1>(v);
+    v = min_dpp<0x4E>(v);
+    v = min_dpp<0x141>(v);
+    if constexpr (W >= 16) v = min_dpp<0x140>(v);
+    if constexpr (W == 32) v = fmin(v, __shfl_xor(v, 16, 32) + R(0));
+    return v;
+  }
 }
 
 template <int W, typename R>
