@@ -103,9 +103,11 @@ struct SoftUnits<double> {
 // E(-inf) = 0 and the result is the smaller value (inf when both are inf)
 template <typename R>
 __device__ inline R smin2u(R a, R b) {
-  const R m = a < b ? a : b, M = a < b ? b : a;
-  const R mc = m < SoftUnits<R>::big ? m : SoftUnits<R>::big;
-  return m - SoftUnits<R>::L1p(SoftUnits<R>::E(mc - M));
+  // with both operands clamped to the largest finite value, -|a - b| is the
+  // exponent m - M of two finite values, -huge when one is infinite and 0
+  // when both are (then m is inf and so is the result)
+  const R ac = fmin(a, SoftUnits<R>::big), bc = fmin(b, SoftUnits<R>::big);
+  return fmin(a, b) - SoftUnits<R>::L1p(SoftUnits<R>::E(-fabs(ac - bc)));
 }
 
 // One DPP lane move (a VALU operation): ctrl 0xB1 swaps neighbours (quad
@@ -153,19 +155,25 @@ __device__ inline int32_t imin_dpp(int32_t v) {
   return o < v ? o : v;
 }
 
+// ordered bits of the FP32 segment minimum
+template <int W>
+__device__ inline int32_t seg_min_bits(float v) {
+  int32_t k = ordered_bits(v);
+  k = imin_dpp<0xB1>(k);
+  k = imin_dpp<0x4E>(k);
+  k = imin_dpp<0x141>(k);
+  if constexpr (W >= 16) k = imin_dpp<0x140>(k);
+  if constexpr (W == 32) {
+    const int32_t o = __shfl_xor(k, 16, 32);
+    k = o < k ? o : k;
+  }
+  return k;
+}
+
 template <int W, typename R>
 __device__ inline R seg_min(R v) {
   if constexpr (sizeof(R) == 4) {
-    int32_t k = ordered_bits(v);
-    k = imin_dpp<0xB1>(k);
-    k = imin_dpp<0x4E>(k);
-    k = imin_dpp<0x141>(k);
-    if constexpr (W >= 16) k = imin_dpp<0x140>(k);
-    if constexpr (W == 32) {
-      const int32_t o = __shfl_xor(k, 16, 32);
-      k = o < k ? o : k;
-    }
-    return from_ordered_bits(k);
+    return from_ordered_bits(seg_min_bits<W>(v));
   } else {
     v = min_dpp<0xB1>(v);
     v = min_dpp<0x4E>(v);
@@ -194,8 +202,12 @@ __device__ inline R seg_sum(R v) {
 // gives L(0) = -inf, so inf.
 template <int W, typename R>
 __device__ inline void seg_softmin_parts(R x, R& mc, R& e) {
-  const R m = seg_min<W, R>(x);
-  mc = m < SoftUnits<R>::big ? m : SoftUnits<R>::big;
+  if constexpr (sizeof(R) == 4) {   // the clamp on the ordered bits: no NaN canonicalisation
+    mc = from_ordered_bits(min(seg_min_bits<W>(x), ordered_bits(SoftUnits<R>::big)));
+  } else {
+    const R m = seg_min<W, R>(x);
+    mc = m < SoftUnits<R>::big ? m : SoftUnits<R>::big;
+  }
   e = seg_sum<W, R>(SoftUnits<R>::E(mc - x));
 }
 
