@@ -50,7 +50,7 @@ def parse():
     ap.add_argument("--no-gap", action="store_true")
     ap.add_argument("--no-pairs", action="store_true", help="skip the per-pair sweep rooflines")
     ap.add_argument("--no-search", action="store_true", help="skip the exact-search timing")
-    ap.add_argument("--cpu-sample-iters", type=int, default=20)
+    ap.add_argument("--cpu-sample-iters", type=int, default=80)
     ap.add_argument("--gap-seeds", default="0,1,2", help="seeds of the time-to-1%%-gap runs (median reported)")
     return ap.parse_args()
 
