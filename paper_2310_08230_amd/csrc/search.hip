@@ -113,6 +113,8 @@ __global__ void k_repair_fix(const int8_t* state, const uint8_t* eflag, const ui
   if (free_) atomicAdd(nfree, 1);
 }
 
+__global__ void k_set_fix(int8_t* fix, int32_t elem, int32_t value) { fix[elem] = int8_t(value); }
+
 struct Decision {
   int32_t elem, value;
 };
@@ -175,6 +177,9 @@ dm_status search_impl(dm_ctx* ctx, const dm_search_params& P, const int8_t* base
   DArr<uint8_t> xnode;
   DArr<int32_t> path_dev;
   DArr<unsigned char> lam_buf;
+  // presolve fixpoint of the last node that branched, for its preferred child
+  DArr<int8_t> parent_state;
+  bool parent_ready = false;
   DM_ALLOC(ctx, fix, size_t(std::max<int64_t>(nP, 1)));
   DM_ALLOC(ctx, xnode, size_t(std::max<int64_t>(nP, 1)));
   double incumbent = std::numeric_limits<double>::infinity();
@@ -193,12 +198,24 @@ dm_status search_impl(dm_ctx* ctx, const dm_search_params& P, const int8_t* base
     std::vector<Decision> path = std::move(stack.back());
     stack.pop_back();
     ++nodes;
-    // node fixings: the base ones plus the path
-    if (base_fix)
+    // The preferred child is popped right after its parent: its fixings are
+    // the parent's presolve fixpoint plus the new decision, the same
+    // fixpoint as the base fixings plus the whole path (unit propagation is
+    // monotone), reached in fewer propagation rounds.  Every node's
+    // multipliers start from c / |J|: starting a child from its parent's
+    // multipliers took the 80-face test pair with an integrality gap past
+    // 3000 nodes without a proof, where the cold start proves it in 897.
+    const bool from_parent = parent_ready;
+    parent_ready = false;
+    if (from_parent) {
+      DM_HIP(ctx, hipMemcpyAsync(fix.p, parent_state.p, size_t(nP), hipMemcpyDeviceToDevice, st));
+      k_set_fix<<<1, 1, 0, st>>>(fix.p, path.back().elem, path.back().value);
+      DM_LAUNCH_CHECK(ctx);
+    } else if (base_fix)
       DM_HIP(ctx, hipMemcpyAsync(fix.p, base_fix, size_t(nP), hipMemcpyDeviceToDevice, st));
     else
       DM_HIP(ctx, hipMemsetAsync(fix.p, 0xFF, size_t(nP), st));
-    if (!path.empty()) {
+    if (!from_parent && !path.empty()) {
       std::vector<int32_t> flat;
       for (const Decision& d : path) {
         flat.push_back(d.elem);
@@ -255,7 +272,11 @@ dm_status search_impl(dm_ctx* ctx, const dm_search_params& P, const int8_t* base
       DM_HIP(ctx, hipMemcpyAsync(x, xnode.p, size_t(nP), hipMemcpyDeviceToDevice, st));
     }
     if (!branch || lb >= incumbent - P.rel_tol * std::max(1.0, std::fabs(incumbent))) continue;
-    // children: the preferred value is explored first (pushed last)
+    // children: the preferred value is explored first (pushed last); keep
+    // this node's fixpoint for it
+    DM_ALLOC(ctx, parent_state, size_t(std::max<int64_t>(nP, 1)));
+    DM_HIP(ctx, hipMemcpyAsync(parent_state.p, ctx->state.p, size_t(nP), hipMemcpyDeviceToDevice, st));
+    parent_ready = true;
     std::vector<Decision> other = path, pref = std::move(path);
     other.push_back({choice.elem, 1 - choice.value});
     pref.push_back(choice);
