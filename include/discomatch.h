@@ -129,8 +129,8 @@ dm_status dm_set_workspace(dm_ctx* ctx, int32_t stage, void* ptr, size_t bytes);
  * here is the library's.
  *  FX [device] float32 [nvx*D] row-major; FY [device] float32 [nvy*D];
  *  cand_xy [device] int32 [nvx*K] out; cand_yx [device] int32 [nvy*K] out.
- *  The K nearest are selected exactly at any size (rows longer than 4096
- *  are processed in chunks that keep the best K so far).
+ *  The K nearest are selected exactly at any size (a radix selection of
+ *  the (distance, index) keys for K <= 2048, a full sort otherwise).
  *  Errors: K < 1, K > nvx or nvy, K > 2048 when nvx or nvy exceeds 4096,
  *  nvx or nvy > 2^21, D < 1. */
 dm_status dm_knn_candidates(dm_ctx* ctx, const float* FX, int32_t nvx, const float* FY,

@@ -140,39 +140,112 @@ __device__ void bitonic_lds(uint64_t* keys, int32_t np2) {
   }
 }
 
-// one block per query vertex: (squared distance, index) keys sorted in LDS,
-// first K indices out.  dir 0: rows of d2 (X queries), 1: columns.  A row of
-// at most TOPK_MAX keys is sorted whole.  A longer row goes through the table
-// in chunks: the K best keys so far stay in front, the rest of the table
-// takes the next keys of the row, and the table is sorted again (the caller
-// checks K <= TOPK_MAX / 2), so the result is the same K smallest keys.
+// one block per query vertex, K > TOPK_MAX / 2 (then the row has at most
+// TOPK_MAX keys): (squared distance, index) keys sorted whole in LDS, first K
+// indices out.  dir 0: rows of d2 (X queries), 1: columns.
 __global__ __launch_bounds__(256) void k_topk(const float* d2, int32_t nvx, int32_t nvy, int dir,
                                               int32_t K, int32_t* out) {
   __shared__ uint64_t keys[TOPK_MAX];
   const int32_t q = blockIdx.x;
   const int32_t n = dir == 0 ? nvy : nvx;
+  int32_t np2 = 1;
+  while (np2 < n) np2 <<= 1;
+  for (int32_t i = threadIdx.x; i < np2; i += blockDim.x) {
+    uint64_t key = ~uint64_t(0);
+    if (i < n) {
+      const float v = dir == 0 ? d2[int64_t(q) * nvy + i] : d2[int64_t(i) * nvy + q];
+      key = (uint64_t(__float_as_uint(v + 0.0f)) << 32) | uint32_t(i);
+    }
+    keys[i] = key;
+  }
+  __syncthreads();
+  bitonic_lds(keys, np2);
+  for (int32_t k = threadIdx.x; k < K; k += blockDim.x) out[int64_t(q) * K + k] = int32_t(keys[k] & 0xFFFFFFFFu);
+}
+
+// one block per query vertex, K <= TOPK_MAX / 2, any row length: the keys
+// (squared distance bits << 32 | index; distances are >= 0, so the bits
+// order like the values, and the index makes every key unique) are not
+// stored.  A radix selection finds the K-th smallest key digit by digit
+// (six digits of 11, 11, 10, 11, 11 and 10 bits, high to low): a histogram
+// of the digit over the keys that share the digits found so far, and the
+// digit whose cumulative count reaches the rank sought.  The K keys up to
+// that one are then gathered and sorted in LDS, so the result is the same
+// ordered list as a full sort's first K.
+__global__ __launch_bounds__(256) void k_topk_select(const float* d2, int32_t nvx, int32_t nvy, int dir,
+                                                     int32_t K, int32_t* out) {
+  __shared__ uint32_t hist[2048];
+  __shared__ uint32_t part[256];
+  __shared__ uint64_t keys[TOPK_MAX / 2];
+  __shared__ uint32_t sh_digit, sh_rank, sh_count;
+  const int32_t q = blockIdx.x;
+  const int32_t n = dir == 0 ? nvy : nvx;
+  const int t = threadIdx.x;
   auto key = [&](int32_t i) -> uint64_t {
-    if (i >= n) return ~uint64_t(0);
     const float v = dir == 0 ? d2[int64_t(q) * nvy + i] : d2[int64_t(i) * nvy + q];
     return (uint64_t(__float_as_uint(v + 0.0f)) << 32) | uint32_t(i);
   };
-  if (n <= TOPK_MAX) {
-    int32_t np2 = 1;
-    while (np2 < n) np2 <<= 1;
-    for (int32_t i = threadIdx.x; i < np2; i += blockDim.x) keys[i] = key(i);
+  uint64_t prefix = 0;   // the digits found so far, in place
+  int known = 0;         // bits found so far
+  uint32_t rank = uint32_t(K);   // 1-based rank sought among the keys with that prefix
+  for (int pass = 0; pass < 6; ++pass) {   // uniform across the block
+    const int width = pass % 3 == 2 ? 10 : 11;
+    const int shift = 64 - known - width;
+    const uint32_t mask = (1u << width) - 1u;
+    for (int b = t; b < 2048; b += 256) hist[b] = 0u;
     __syncthreads();
-    bitonic_lds(keys, np2);
-  } else {
-    int32_t next = 0, kept = 0;   // uniform across the block
-    while (next < n) {
-      for (int32_t i = kept + int32_t(threadIdx.x); i < TOPK_MAX; i += blockDim.x) keys[i] = key(next + i - kept);
+    for (int32_t i = t; i < n; i += 256) {
+      const uint64_t k = key(i);
+      if (known == 0 || (k >> (64 - known)) == (prefix >> (64 - known)))
+        atomicAdd(&hist[uint32_t(k >> shift) & mask], 1u);
+    }
+    __syncthreads();
+    // counts of the eight bins of this thread, then an exclusive scan of
+    // the 256 partial counts (fixed order, in LDS)
+    uint32_t loc = 0;
+    for (int j = 0; j < 8; ++j) loc += hist[8 * t + j];
+    part[t] = loc;
+    __syncthreads();
+    for (int off = 1; off < 256; off <<= 1) {
+      const uint32_t add = t >= off ? part[t - off] : 0u;
       __syncthreads();
-      bitonic_lds(keys, TOPK_MAX);
-      next += TOPK_MAX - kept;
-      kept = K;
+      part[t] += add;
+      __syncthreads();
+    }
+    uint32_t below = part[t] - loc;   // keys in the bins before this thread's
+    if (below < rank && rank <= below + loc) {   // exactly one thread
+      for (int j = 0; j < 8; ++j) {
+        const uint32_t c = hist[8 * t + j];
+        if (rank <= below + c) {
+          sh_digit = uint32_t(8 * t + j);
+          sh_rank = rank - below;
+          break;
+        }
+        below += c;
+      }
+    }
+    __syncthreads();
+    prefix |= uint64_t(sh_digit) << shift;
+    rank = sh_rank;
+    known += width;
+    __syncthreads();
+  }
+  // prefix is now the K-th smallest key: exactly K keys are <= it
+  if (t == 0) sh_count = 0u;
+  __syncthreads();
+  for (int32_t i = t; i < n; i += 256) {
+    const uint64_t k = key(i);
+    if (k <= prefix) {
+      const uint32_t pos = atomicAdd(&sh_count, 1u);
+      if (pos < uint32_t(TOPK_MAX / 2)) keys[pos] = k;   // exactly K < TOPK_MAX / 2 + 1 of them
     }
   }
-  for (int32_t k = threadIdx.x; k < K; k += blockDim.x) out[int64_t(q) * K + k] = int32_t(keys[k] & 0xFFFFFFFFu);
+  int32_t np2 = 1;
+  while (np2 < K) np2 <<= 1;
+  for (int32_t i = K + t; i < np2; i += 256) keys[i] = ~uint64_t(0);
+  __syncthreads();
+  bitonic_lds(keys, np2);
+  for (int32_t k = t; k < K; k += 256) out[int64_t(q) * K + k] = int32_t(keys[k] & 0xFFFFFFFFu);
 }
 
 __global__ void k_zero_i32(int* p) { *p = 0; }
@@ -275,8 +348,13 @@ dm_status knn_check_args(dm_ctx* ctx, const char* name, const float* FX, int32_t
 dm_status knn_run(dm_ctx* ctx, const float* FX, int32_t nvx, const float* FY, int32_t nvy, int32_t D, int32_t K,
                   int32_t prec, int32_t* cand_xy, int32_t* cand_yx, const KnnBufs& w) {
   DM_TRY(distances_into(ctx, FX, nvx, FY, nvy, D, prec, w, w.d2));
-  k_topk<<<nvx, 256, 0, ctx->stream>>>(w.d2, nvx, nvy, 0, K, cand_xy);
-  k_topk<<<nvy, 256, 0, ctx->stream>>>(w.d2, nvx, nvy, 1, K, cand_yx);
+  if (K <= TOPK_MAX / 2) {
+    k_topk_select<<<nvx, 256, 0, ctx->stream>>>(w.d2, nvx, nvy, 0, K, cand_xy);
+    k_topk_select<<<nvy, 256, 0, ctx->stream>>>(w.d2, nvx, nvy, 1, K, cand_yx);
+  } else {   // then both sides have at most TOPK_MAX vertices (checked above)
+    k_topk<<<nvx, 256, 0, ctx->stream>>>(w.d2, nvx, nvy, 0, K, cand_xy);
+    k_topk<<<nvy, 256, 0, ctx->stream>>>(w.d2, nvx, nvy, 1, K, cand_yx);
+  }
   DM_LAUNCH_CHECK(ctx);
   return DM_OK;
 }
