@@ -102,8 +102,9 @@ def c2f_run(seed=0, levels=(500, 1000, 2000, 4000), K0=32, qn_iters=60, rings=2)
     at 500 -> 1000 -> 2000 -> 4000 faces: the coarsest level takes K0 nearest
     candidates, every finer one the ring candidates of the previous level's
     matching; each level runs qn_iters quasi-Newton iterations and one
-    rounding.  Wall time per level (candidates, build, costs, solve,
-    rounding), sizes and gap."""
+    rounding, followed by the local repair if it leaves rows violated.
+    Wall time per level (candidates, build, costs, solve, rounding), sizes
+    and gap."""
     import numpy as np
     import torch
 
@@ -129,6 +130,8 @@ def c2f_run(seed=0, levels=(500, 1000, 2000, 4000), K0=32, qn_iters=60, rings=2)
         ctx.build_costs(DX, DY, "fp32")
         lam, tr = ctx.lbfgs_solve(ctx.init_lambda("fp32"), qn_iters)[:2]
         x, pobj, feas, _ = ctx.round_primal(lam)
+        if not feas:   # local exact repair around the violated rows
+            x, pobj, feas, _, _ = ctx.repair_primal(x, max_hops=8)
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
         total += dt
