@@ -97,6 +97,14 @@ extern "C" const char* dm_version(void) { return "discomatch-gfx950 0.1"; }
 // ---------------------------------------------------------------------------
 // rocPRIM wrappers (stable radix sort of key/value pairs, exclusive scans)
 // ---------------------------------------------------------------------------
+// Every sort above one block takes the onesweep (LSD radix) algorithm, whose
+// passes follow the key bits actually used; rocPRIM's default sends sizes up
+// to 2^20 to a block sort plus merge rounds, whose count grows with the size
+// instead (the 64-bit edge-key sort of a 500-face pair: 16 merge kernels).
+// Both are stable, so the sorted order is the same.
+using SortConfig = rocprim::radix_sort_config<rocprim::default_config, rocprim::default_config,
+                                              rocprim::default_config, 0>;
+
 template <typename K>
 static dm_status sort_pairs_impl(dm_ctx* ctx, K* keys, int32_t* vals, size_t n, int end_bit) {
   if (n <= 1) return DM_OK;
@@ -105,12 +113,12 @@ static dm_status sort_pairs_impl(dm_ctx* ctx, K* keys, int32_t* vals, size_t n, 
   DM_ALLOC(ctx, k2, n);
   DM_ALLOC(ctx, v2, n);
   size_t temp = 0;
-  DM_HIP(ctx, rocprim::radix_sort_pairs(nullptr, temp, keys, k2.p, vals, v2.p, n, 0u,
-                                        unsigned(end_bit), ctx->stream));
+  DM_HIP(ctx, rocprim::radix_sort_pairs<SortConfig>(nullptr, temp, keys, k2.p, vals, v2.p, n, 0u,
+                                                    unsigned(end_bit), ctx->stream));
   DArr<unsigned char> tmp;
   DM_ALLOC(ctx, tmp, temp + 16);
-  DM_HIP(ctx, rocprim::radix_sort_pairs(tmp.p, temp, keys, k2.p, vals, v2.p, n, 0u,
-                                        unsigned(end_bit), ctx->stream));
+  DM_HIP(ctx, rocprim::radix_sort_pairs<SortConfig>(tmp.p, temp, keys, k2.p, vals, v2.p, n, 0u,
+                                                    unsigned(end_bit), ctx->stream));
   DM_HIP(ctx, hipMemcpyAsync(keys, k2.p, n * sizeof(K), hipMemcpyDeviceToDevice, ctx->stream));
   DM_HIP(ctx, hipMemcpyAsync(vals, v2.p, n * sizeof(int32_t), hipMemcpyDeviceToDevice, ctx->stream));
   return DM_OK;   // temporaries are freed in stream order: no wait needed

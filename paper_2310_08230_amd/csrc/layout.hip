@@ -103,6 +103,12 @@ __global__ void k_fill_i32(int32_t* a, int64_t n, int32_t v) {
   if (i < n) a[i] = v;
 }
 
+// empty key ranges of the NREG regions: (INT32_MAX, -1) pairs, one launch
+__global__ void k_bounds_init(int32_t* bounds) {
+  const int t = int(threadIdx.x);
+  if (t < 2 * NREG) bounds[t] = (t & 1) ? -1 : INT32_MAX;
+}
+
 // key of every free variable: the rank of its X element's owner face
 __global__ void k_var_key_mesh(const int32_t* free_var, const int32_t* code, const int32_t* frank,
                                const int32_t* erank, const int32_t* vrank, int64_t n, int32_t* vkey) {
@@ -152,15 +158,22 @@ __device__ inline int32_t region_of(const int32_t* pre, const int32_t* w, int32_
   return int32_t(r < 0 ? 0 : (r >= NREG ? NREG - 1 : r));
 }
 
-// smallest and largest key of every region (bounds[2r], bounds[2r+1])
+// smallest and largest key of every region (bounds[2r], bounds[2r+1]; an
+// empty region keeps the pair k_bounds_init wrote).  region_of never
+// decreases with k (the prefix sums only grow), so a region's keys are one
+// range and its ends are the keys where the region changes.
 __global__ void k_region_bounds(const int32_t* pre, const int32_t* w, int32_t nkeys, int64_t total,
                                 int32_t* bounds) {
   const int32_t k = int32_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (k >= nkeys) return;
   const int32_t r = region_of(pre, w, k, total);
-  atomicMin(&bounds[2 * r], k);
-  atomicMax(&bounds[2 * r + 1], k);
+  if (k == 0 || region_of(pre, w, k - 1, total) != r) bounds[2 * r] = k;
+  if (k == nkeys - 1 || region_of(pre, w, k + 1, total) != r) bounds[2 * r + 1] = k;
 }
+
+// entries per batch of loads in the one-thread-per-row kernels below (indices
+// clamped to the row: no branch, all loads of a batch in flight together)
+constexpr int ROW_BATCH = 8;
 
 // key of every row: the smallest key of its entries; short rows one thread
 // each, projection rows one wave each
@@ -169,7 +182,14 @@ __global__ void k_row_keys(const int32_t* rrow_ptr, const uint32_t* word, const 
   const int64_t j = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (j >= n_rows) return;
   int32_t m = INT32_MAX;
-  for (int32_t e = rrow_ptr[j]; e < rrow_ptr[j + 1]; ++e) m = min(m, vkey[word[e] & W_VAR_MASK]);
+  const int32_t s = rrow_ptr[j], t = rrow_ptr[j + 1];
+  for (int32_t e0 = s; e0 < t; e0 += ROW_BATCH) {   // the loads of a batch go out together
+    uint32_t w[ROW_BATCH];
+#pragma unroll
+    for (int u = 0; u < ROW_BATCH; ++u) w[u] = word[e0 + u < t ? e0 + u : e0];
+#pragma unroll
+    for (int u = 0; u < ROW_BATCH; ++u) m = min(m, vkey[w[u] & W_VAR_MASK]);   // repeats of e0 change nothing
+  }
   rkey[j] = m == INT32_MAX ? 0 : m;
 }
 
@@ -205,11 +225,16 @@ __global__ void k_short_sort_keys(const int32_t* rkey, const int32_t* rrow_ptr, 
                                   int32_t* n_tile_rows /* [2]: rows, entries */) {
   const int64_t j = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (j >= n_short) return;
-  int32_t np = 0, nq = 0;
-  for (int32_t e = rrow_ptr[j]; e < rrow_ptr[j + 1]; ++e) {
-    if (word[e] & W_NEG) ++nq;
-    else ++np;
+  const int32_t s = rrow_ptr[j], t = rrow_ptr[j + 1];
+  int32_t nq = 0;
+  for (int32_t e0 = s; e0 < t; e0 += ROW_BATCH) {   // the loads of a batch go out together
+    uint32_t w[ROW_BATCH];
+#pragma unroll
+    for (int u = 0; u < ROW_BATCH; ++u) w[u] = word[e0 + u < t ? e0 + u : e0];
+#pragma unroll
+    for (int u = 0; u < ROW_BATCH; ++u) nq += (e0 + u < t && (w[u] & W_NEG)) ? 1 : 0;
   }
+  const int32_t np = (t - s) - nq;
   const bool tile = tiles_on && rrow_b[j] == 0 && np <= TILE_HALF && nq <= TILE_HALF;
   key[j] = (tile ? 0u : (1u << kbits)) | uint32_t(rkey[j]);
   val[j] = int32_t(j);
@@ -477,10 +502,7 @@ dm_status sweep_layout(dm_ctx* ctx) {
   }
   DM_LAUNCH_CHECK(ctx);
   DM_TRY(scan_i32(ctx, wcount.p, wpre.p, size_t(nkeys)));
-  for (int r = 0; r < NREG; ++r) {
-    k_fill_i32<<<1, 1, 0, st>>>(bounds.p + 2 * r, 1, INT32_MAX);
-    k_fill_i32<<<1, 1, 0, st>>>(bounds.p + 2 * r + 1, 1, -1);
-  }
+  k_bounds_init<<<1, 64, 0, st>>>(bounds.p);
   k_region_bounds<<<grid_for(nkeys, 256), 256, 0, st>>>(wpre.p, wcount.p, nkeys, rnnz, bounds.p);
   DM_ALLOC(ctx, rkey, size_t(std::max<int64_t>(nr, 1)));
   if (nshort > 0)

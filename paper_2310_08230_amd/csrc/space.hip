@@ -271,17 +271,15 @@ __global__ void k_yproj(const int32_t* yptr, const int32_t* val, const int32_t* 
 __global__ void k_set_i32(int32_t* a, int64_t i, int32_t v) { a[i] = v; }
 
 // ---------------------------------------------------------------- presolve
-// one atomic OR per wave: the lowest lane with the condition set does it
-__device__ inline void wave_flag(bool cond, int* flag) {
-  const unsigned long long m = __ballot(cond);
-  if (m && int(threadIdx.x & 63) == __ffsll(static_cast<long long>(m)) - 1) atomicOr(flag, 1);
-}
-
 // A presolve round does nothing once the round before it changed nothing or
 // found the system infeasible (prev: that round's flags, or NULL).
 __device__ inline bool presolve_done(const int* prev) {
   return prev && (prev[0] == 0 || prev[1] != 0);
 }
+
+// A row's entries are read PS_BATCH at a time, with indices clamped to the
+// row, so that the loads of a batch go out together and need no branch.
+constexpr int PS_BATCH = 8;
 
 __global__ void k_presolve_rows(const int32_t* row_ptr, const int32_t* ent_var, const int8_t* ent_coef,
                                 const int32_t* row_b, int64_t nrows, const int8_t* state,
@@ -289,51 +287,85 @@ __global__ void k_presolve_rows(const int32_t* row_ptr, const int32_t* ent_var, 
   if (presolve_done(prev)) return;   // uniform across the grid
   int64_t j = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (j >= nrows) return;
-  int32_t s = row_ptr[j], e = row_ptr[j + 1];
+  const int32_t s = row_ptr[j], e = row_ptr[j + 1];
   int32_t r = row_b[j], P = 0, N = 0;
-  for (int32_t i = s; i < e; ++i) {
-    int8_t st = state[ent_var[i]];
-    int a = ent_coef[i];
-    if (st == 1) r -= a;
-    else if (st < 0) {
-      if (a > 0) ++P;
-      else ++N;
+  for (int32_t i0 = s; i0 < e; i0 += PS_BATCH) {
+    int32_t v[PS_BATCH];
+    int a[PS_BATCH];
+#pragma unroll
+    for (int u = 0; u < PS_BATCH; ++u) {
+      const int32_t i = i0 + u < e ? i0 + u : i0;
+      v[u] = ent_var[i];
+      a[u] = ent_coef[i];
+    }
+    int8_t st[PS_BATCH];
+#pragma unroll
+    for (int u = 0; u < PS_BATCH; ++u) st[u] = state[v[u]];
+#pragma unroll
+    for (int u = 0; u < PS_BATCH; ++u) {
+      if (i0 + u >= e) continue;
+      if (st[u] == 1) r -= a[u];
+      else if (st[u] < 0) {
+        if (a[u] > 0) ++P;
+        else ++N;
+      }
     }
   }
   if (r < -N || r > P) {
     atomicOr(&flags[1], 1);
     return;
   }
-  for (int32_t i = s; i < e; ++i) {
-    int32_t v = ent_var[i];
-    if (state[v] >= 0) continue;
-    int a = ent_coef[i];
-    int32_t Pr = P - (a > 0 ? 1 : 0), Nr = N - (a < 0 ? 1 : 0);
-    bool one_ok = (r - a >= -Nr) && (r - a <= Pr);
-    bool zero_ok = (r >= -Nr) && (r <= Pr);
-    if (!one_ok && !zero_ok) atomicOr(&flags[1], 1);
-    else if (!one_ok) atomicOr(&force[v], 1u);
-    else if (!zero_ok) atomicOr(&force[v], 2u);
+  for (int32_t i0 = s; i0 < e; i0 += PS_BATCH) {
+    int32_t v[PS_BATCH];
+    int a[PS_BATCH];
+#pragma unroll
+    for (int u = 0; u < PS_BATCH; ++u) {
+      const int32_t i = i0 + u < e ? i0 + u : i0;
+      v[u] = ent_var[i];
+      a[u] = ent_coef[i];
+    }
+    int8_t st[PS_BATCH];
+#pragma unroll
+    for (int u = 0; u < PS_BATCH; ++u) st[u] = state[v[u]];
+#pragma unroll
+    for (int u = 0; u < PS_BATCH; ++u) {
+      if (i0 + u >= e || st[u] >= 0) continue;
+      const int32_t Pr = P - (a[u] > 0 ? 1 : 0), Nr = N - (a[u] < 0 ? 1 : 0);
+      const bool one_ok = (r - a[u] >= -Nr) && (r - a[u] <= Pr);
+      const bool zero_ok = (r >= -Nr) && (r <= Pr);
+      if (!one_ok && !zero_ok) atomicOr(&flags[1], 1);
+      else if (!one_ok) atomicOr(&force[v[u]], 1u);
+      else if (!zero_ok) atomicOr(&force[v[u]], 2u);
+    }
   }
 }
 
-__global__ void k_presolve_vars(int64_t nP, int8_t* state, uint32_t* force, int* flags, const int* prev) {
+// The round's (changed, clash) flags: one atomic OR per block and flag (the
+// block's threads first meet in LDS), not one per wave on a single word.
+__global__ __launch_bounds__(256) void k_presolve_vars(int64_t nP, int8_t* state, uint32_t* force, int* flags,
+                                                       const int* prev) {
+  __shared__ int any[2];
   if (presolve_done(prev)) return;   // uniform across the grid
-  int64_t p = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (p >= nP) return;
-  const uint32_t f = force[p];
-  bool changed = false, clash = false;
-  if (f) {
-    force[p] = 0;
-    if (f == 3u) {
-      clash = true;
-    } else if (state[p] < 0) {
-      state[p] = (f == 2u) ? 1 : 0;
-      changed = true;
+  if (threadIdx.x < 2) any[threadIdx.x] = 0;
+  __syncthreads();
+  const int64_t p = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (p < nP) {
+    const uint32_t f = force[p];
+    if (f) {
+      force[p] = 0;
+      if (f == 3u) {
+        any[1] = 1;
+      } else if (state[p] < 0) {
+        state[p] = (f == 2u) ? 1 : 0;
+        any[0] = 1;
+      }
     }
   }
-  wave_flag(changed, &flags[0]);
-  wave_flag(clash, &flags[1]);
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    if (any[0]) atomicOr(&flags[0], 1);
+    if (any[1]) atomicOr(&flags[1], 1);
+  }
 }
 
 __global__ void k_fix_state(const int8_t* fix, int64_t nP, int8_t* state) {
