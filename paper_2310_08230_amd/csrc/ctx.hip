@@ -101,7 +101,9 @@ extern "C" const char* dm_version(void) { return "discomatch-gfx950 0.1"; }
 // passes follow the key bits actually used; rocPRIM's default sends sizes up
 // to 2^20 to a block sort plus merge rounds, whose count grows with the size
 // instead (the 64-bit edge-key sort of a 500-face pair: 16 merge kernels).
-// Both are stable, so the sorted order is the same.
+// Both are stable, so the sorted order is the same.  The double-buffer form
+// ping-pongs between the caller's arrays and one pair of temporaries, so the
+// result needs copying back only when it ends in the temporaries.
 using SortConfig = rocprim::radix_sort_config<rocprim::default_config, rocprim::default_config,
                                               rocprim::default_config, 0>;
 
@@ -112,15 +114,17 @@ static dm_status sort_pairs_impl(dm_ctx* ctx, K* keys, int32_t* vals, size_t n, 
   DArr<int32_t> v2;
   DM_ALLOC(ctx, k2, n);
   DM_ALLOC(ctx, v2, n);
+  rocprim::double_buffer<K> kb(keys, k2.p);
+  rocprim::double_buffer<int32_t> vb(vals, v2.p);
   size_t temp = 0;
-  DM_HIP(ctx, rocprim::radix_sort_pairs<SortConfig>(nullptr, temp, keys, k2.p, vals, v2.p, n, 0u,
-                                                    unsigned(end_bit), ctx->stream));
+  DM_HIP(ctx, rocprim::radix_sort_pairs<SortConfig>(nullptr, temp, kb, vb, n, 0u, unsigned(end_bit), ctx->stream));
   DArr<unsigned char> tmp;
   DM_ALLOC(ctx, tmp, temp + 16);
-  DM_HIP(ctx, rocprim::radix_sort_pairs<SortConfig>(tmp.p, temp, keys, k2.p, vals, v2.p, n, 0u,
-                                                    unsigned(end_bit), ctx->stream));
-  DM_HIP(ctx, hipMemcpyAsync(keys, k2.p, n * sizeof(K), hipMemcpyDeviceToDevice, ctx->stream));
-  DM_HIP(ctx, hipMemcpyAsync(vals, v2.p, n * sizeof(int32_t), hipMemcpyDeviceToDevice, ctx->stream));
+  DM_HIP(ctx, rocprim::radix_sort_pairs<SortConfig>(tmp.p, temp, kb, vb, n, 0u, unsigned(end_bit), ctx->stream));
+  if (kb.current() != keys)
+    DM_HIP(ctx, hipMemcpyAsync(keys, kb.current(), n * sizeof(K), hipMemcpyDeviceToDevice, ctx->stream));
+  if (vb.current() != vals)
+    DM_HIP(ctx, hipMemcpyAsync(vals, vb.current(), n * sizeof(int32_t), hipMemcpyDeviceToDevice, ctx->stream));
   return DM_OK;   // temporaries are freed in stream order: no wait needed
 }
 
