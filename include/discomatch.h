@@ -86,8 +86,9 @@ typedef struct {
  * context's later calls and leaves the device's default pool untouched.  The
  * context also keeps up to 4 GiB of the blocks it frees, by size, and hands
  * them to its later allocations of the same size without a runtime call
- * (dm_set_stream to another stream, and dm_destroy, return them to the
- * pool).  The stream must stay valid until dm_destroy.  Errors: DM_ERR_INVALID_ARG (no
+ * (dm_set_stream to another stream, an allocation that finds the pool out of
+ * memory, and dm_destroy return them to the pool).  The stream must stay
+ * valid until dm_destroy.  Errors: DM_ERR_INVALID_ARG (no
  * such device), DM_ERR_HIP (the pool or pinned host slots could not be
  * created). */
 dm_status dm_create(int32_t device, void* hip_stream, dm_ctx** out);

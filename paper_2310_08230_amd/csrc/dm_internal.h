@@ -43,7 +43,8 @@ dm_status dm_fail(dm_ctx* ctx, dm_status code, const char* fmt, ...);
 // stream, so stream order alone makes the reuse safe: a block is taken only
 // by work ordered after everything that used it before.  The cache holds at
 // most MAX_BYTES; blocks beyond that, and every block when the context's
-// stream changes or the context is destroyed, go back to the pool.
+// stream changes, when an allocation finds the pool out of memory, or when
+// the context is destroyed, go back to the pool.
 // ---------------------------------------------------------------------------
 struct BlockCache {
   static constexpr size_t MAX_BYTES = size_t(4) << 30;
@@ -110,7 +111,16 @@ struct DArr {
     const size_t c = BlockCache::size_class(count * sizeof(T));
     void* q = (bc && bc->stream == stream) ? bc->take(c) : nullptr;
     if (!q) {
-      const hipError_t e = hipMallocFromPoolAsync(&q, c, pool, stream);
+      hipError_t e = hipMallocFromPoolAsync(&q, c, pool, stream);
+      if (e != hipSuccess && bc && bc->bytes > 0) {
+        // out of memory while the cache holds idle blocks: give them back
+        // to the pool (stream-ordered, so the retry on the same stream may
+        // reuse them) and try once more
+        (void)hipGetLastError();
+        bc->release_all();
+        e = hipMallocFromPoolAsync(&q, c, pool, stream);
+        if (e == hipSuccess) (void)hipGetLastError();
+      }
       if (e != hipSuccess) return e;
     }
     p = static_cast<T*>(q);

@@ -349,10 +349,41 @@ extern "C" dm_status dm_exact_search(dm_ctx* ctx, const dm_search_params* params
 // other element keeps its value in x (or its presolve value), and the exact
 // search solves the neighbourhood; a neighbourhood without a feasible
 // completion grows by one step, up to max_hops.
+// One neighbourhood of h steps around the violated rows (grown from the
+// previous one's marks): fix every element outside it at its value in x and
+// search the rest exactly; on success x holds the repaired primal.  The
+// search leaves its base problem in place, which the caller restores.
+static dm_status repair_hop(dm_ctx* ctx, const dm_search_params& P, int32_t h, uint8_t* x, uint8_t* rflag,
+                            uint8_t* eflag, int8_t* fix, uint8_t* xbest, int* cnt, double* primal_obj,
+                            int32_t* feasible, int64_t* n_free) {
+  hipStream_t st = ctx->stream;
+  const int64_t nP = ctx->nP, nrows = ctx->n_rows_full, nc = ctx->n_closed_full;
+  if (h > 1)
+    k_mark_rows<<<grid_for(std::max<int64_t>(nc, 1), 256), 256, 0, st>>>(ctx->row_ptr.p, ctx->ent_var.p, nc,
+                                                                         eflag, rflag);
+  k_mark_elems<<<grid_for(std::max<int64_t>(nrows, 1), 256), 256, 0, st>>>(ctx->row_ptr.p, ctx->ent_var.p, nrows,
+                                                                           rflag, eflag);
+  DM_HIP(ctx, hipMemsetAsync(cnt + 1, 0, sizeof(int), st));
+  k_repair_fix<<<grid_for(nP, 256), 256, 0, st>>>(ctx->state.p, eflag, x, nP, fix, cnt + 1);
+  DM_LAUNCH_CHECK(ctx);
+  int32_t nf = 0;
+  DM_TRY(read_i32(ctx, cnt + 1, &nf));
+  *n_free = nf;
+  double pobj = 0.0, bound = 0.0;
+  int32_t nodes = 0, status = 0;
+  DM_TRY(exact_search(ctx, &P, fix, xbest, &pobj, &bound, &nodes, &status));
+  if (std::isfinite(pobj)) {
+    DM_HIP(ctx, hipMemcpyAsync(x, xbest, size_t(nP), hipMemcpyDeviceToDevice, st));
+    *primal_obj = pobj;
+    *feasible = 1;
+  }
+  return DM_OK;
+}
+
 static dm_status repair_primal(dm_ctx* ctx, const dm_search_params& P, int32_t max_hops, uint8_t* x,
                                double* primal_obj, int32_t* feasible, int32_t* hops_used, int64_t* n_free) {
   hipStream_t st = ctx->stream;
-  const int64_t nP = ctx->nP, nrows = ctx->n_rows_full, nc = ctx->n_closed_full;
+  const int64_t nP = ctx->nP, nrows = ctx->n_rows_full;
   const int64_t generation = ctx->cost_generation;
   *feasible = 0;
   *hops_used = 0;
@@ -384,30 +415,12 @@ static dm_status repair_primal(dm_ctx* ctx, const dm_search_params& P, int32_t m
   DM_ALLOC(ctx, held, size_t(std::max<int64_t>(nP, 1)));
   DM_HIP(ctx, hipMemcpyAsync(held.p, ctx->state.p, size_t(nP), hipMemcpyDeviceToDevice, st));
   DM_HIP(ctx, hipMemsetAsync(eflag.p, 0, size_t(nP), st));
+  // every failure from here on still restores the held problem below
   dm_status result = DM_OK;
-  for (int32_t h = 1; h <= max_hops; ++h) {
-    if (h > 1)
-      k_mark_rows<<<grid_for(std::max<int64_t>(nc, 1), 256), 256, 0, st>>>(ctx->row_ptr.p, ctx->ent_var.p, nc,
-                                                                           eflag.p, rflag.p);
-    k_mark_elems<<<grid_for(std::max<int64_t>(nrows, 1), 256), 256, 0, st>>>(ctx->row_ptr.p, ctx->ent_var.p, nrows,
-                                                                             rflag.p, eflag.p);
-    DM_HIP(ctx, hipMemsetAsync(cnt.p + 1, 0, sizeof(int), st));
-    k_repair_fix<<<grid_for(nP, 256), 256, 0, st>>>(ctx->state.p, eflag.p, x, nP, fix.p, cnt.p + 1);
-    DM_LAUNCH_CHECK(ctx);
-    int32_t nf = 0;
-    DM_TRY(read_i32(ctx, cnt.p + 1, &nf));
+  for (int32_t h = 1; h <= max_hops && !*feasible; ++h) {
     *hops_used = h;
-    *n_free = nf;
-    double pobj = 0.0, bound = 0.0;
-    int32_t nodes = 0, status = 0;
-    result = exact_search(ctx, &P, fix.p, xbest.p, &pobj, &bound, &nodes, &status);
+    result = repair_hop(ctx, P, h, x, rflag.p, eflag.p, fix.p, xbest.p, cnt.p, primal_obj, feasible, n_free);
     if (result != DM_OK) break;
-    if (std::isfinite(pobj)) {
-      DM_HIP(ctx, hipMemcpyAsync(x, xbest.p, size_t(nP), hipMemcpyDeviceToDevice, st));
-      *primal_obj = pobj;
-      *feasible = 1;
-      break;
-    }
   }
   // back to the problem the context held (the search leaves its base in place)
   const std::string msg = ctx->err;
