@@ -341,14 +341,6 @@ extern "C" dm_status dm_exact_search(dm_ctx* ctx, const dm_search_params* params
   return s;
 }
 
-// Local repair of a primal (Appendix "Coarse-to-fine solving strategy": the
-// confident part of an assignment stays fixed and the rest is solved
-// exactly).  The neighbourhood of the rows x violates is freed step by step:
-// step 1 frees every element of the violated rows; each further step frees
-// the elements of the closedness rows that touch the neighbourhood.  Every
-// other element keeps its value in x (or its presolve value), and the exact
-// search solves the neighbourhood; a neighbourhood without a feasible
-// completion grows by one step, up to max_hops.
 // One neighbourhood of h steps around the violated rows (grown from the
 // previous one's marks): fix every element outside it at its value in x and
 // search the rest exactly; on success x holds the repaired primal.  The
@@ -380,6 +372,14 @@ static dm_status repair_hop(dm_ctx* ctx, const dm_search_params& P, int32_t h, u
   return DM_OK;
 }
 
+// Local repair of a primal (Appendix "Coarse-to-fine solving strategy": the
+// confident part of an assignment stays fixed and the rest is solved
+// exactly).  The neighbourhood of the rows x violates is freed step by step:
+// step 1 frees every element of the violated rows; each further step frees
+// the elements of the closedness rows that touch the neighbourhood.  Every
+// other element keeps its value in x (or its presolve value), and the exact
+// search solves the neighbourhood; a neighbourhood without a feasible
+// completion grows by one step, up to max_hops.
 static dm_status repair_primal(dm_ctx* ctx, const dm_search_params& P, int32_t max_hops, uint8_t* x,
                                double* primal_obj, int32_t* feasible, int32_t* hops_used, int64_t* n_free) {
   hipStream_t st = ctx->stream;
