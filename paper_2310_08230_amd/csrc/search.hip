@@ -189,15 +189,10 @@ dm_status search_impl(dm_ctx* ctx, const dm_search_params& P, const int8_t* base
   // depth-first: every stack entry is a full path of decisions
   std::vector<std::vector<Decision>> stack;
   stack.emplace_back();
-  dm_status result = DM_OK;
-  while (!stack.empty()) {
-    if (nodes >= P.max_nodes) {
-      limit_hit = true;
-      break;
-    }
-    std::vector<Decision> path = std::move(stack.back());
-    stack.pop_back();
-    ++nodes;
+  // One node: its fixings, presolve, bound, primal and children.  A failing
+  // call's early return leaves only this function, so every failure still
+  // reaches the restore of the base problem after the loop.
+  auto visit = [&](std::vector<Decision>& path) -> dm_status {
     // The preferred child is popped right after its parent: its fixings are
     // the parent's presolve fixpoint plus the new decision, the same
     // fixpoint as the base fixings plus the whole path (unit propagation is
@@ -235,23 +230,20 @@ dm_status search_impl(dm_ctx* ctx, const dm_search_params& P, const int8_t* base
         root_done = true;
         root_lb = std::numeric_limits<double>::infinity();
       }
-      continue;
+      return DM_OK;
     }
-    if (ps != DM_OK) {
-      result = ps;
-      break;
-    }
-    if ((result = cost_offset(ctx)) != DM_OK) break;
+    if (ps != DM_OK) return ps;
+    DM_TRY(cost_offset(ctx));
     double lb = 0.0;
     bool branch = false;
     Decision choice{0, 0};
-    if ((result = node_bound_and_branch<R>(ctx, P, lam_buf, &lb, &branch, &choice)) != DM_OK) break;
+    DM_TRY(node_bound_and_branch<R>(ctx, P, lam_buf, &lb, &branch, &choice));
     if (!root_done) {
       root_done = true;
       root_lb = lb;
     }
     const double tol = P.rel_tol * std::max(1.0, std::fabs(incumbent));
-    if (lb >= incumbent - tol) continue;   // cannot improve on the incumbent
+    if (lb >= incumbent - tol) return DM_OK;   // cannot improve on the incumbent
     // a primal at this node
     double pobj = 0.0;
     int32_t feas = 0, used = 0;
@@ -259,19 +251,19 @@ dm_status search_impl(dm_ctx* ctx, const dm_search_params& P, const int8_t* base
       k_state_to_x<<<grid_for(nP, 256), 256, 0, st>>>(ctx->state.p, nP, xnode.p);
       DM_LAUNCH_CHECK(ctx);
       int64_t viol = 0;
-      if ((result = dm_check_primal(ctx, xnode.p, &viol)) != DM_OK) break;
+      DM_TRY(dm_check_primal(ctx, xnode.p, &viol));
       feas = viol == 0;
       pobj = ctx->offset;
     } else {
       dm_round_params rp = P.round;
       rp.msg_prec = sizeof(R) == 4 ? DM_PREC_FP32 : DM_PREC_FP64;
-      if ((result = dm_round_primal(ctx, &rp, lam_buf.p, xnode.p, &pobj, &feas, &used)) != DM_OK) break;
+      DM_TRY(dm_round_primal(ctx, &rp, lam_buf.p, xnode.p, &pobj, &feas, &used));
     }
     if (feas && pobj < incumbent) {
       incumbent = pobj;
       DM_HIP(ctx, hipMemcpyAsync(x, xnode.p, size_t(nP), hipMemcpyDeviceToDevice, st));
     }
-    if (!branch || lb >= incumbent - P.rel_tol * std::max(1.0, std::fabs(incumbent))) continue;
+    if (!branch || lb >= incumbent - P.rel_tol * std::max(1.0, std::fabs(incumbent))) return DM_OK;
     // children: the preferred value is explored first (pushed last); keep
     // this node's fixpoint for it
     DM_ALLOC(ctx, parent_state, size_t(std::max<int64_t>(nP, 1)));
@@ -282,6 +274,18 @@ dm_status search_impl(dm_ctx* ctx, const dm_search_params& P, const int8_t* base
     pref.push_back(choice);
     stack.push_back(std::move(other));
     stack.push_back(std::move(pref));
+    return DM_OK;
+  };
+  dm_status result = DM_OK;
+  while (!stack.empty()) {
+    if (nodes >= P.max_nodes) {
+      limit_hit = true;
+      break;
+    }
+    std::vector<Decision> path = std::move(stack.back());
+    stack.pop_back();
+    ++nodes;
+    if ((result = visit(path)) != DM_OK) break;
   }
   // back to the problem with the base fixings only
   const std::string msg = ctx->err;
