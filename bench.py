@@ -11,7 +11,8 @@ objective at the multipliers re-projected onto dual feasibility.
 
 Also reported (same JSON line): the dominant kernel's roofline (the sweep
 kernel: algorithmic bytes per launch / its average launch duration from HIP
-events around each launch), the sweep at the other pairs, time-to-1%-gap of
+events around each launch), the sweep at the other pairs (the smoothed
+sweep against the VALU issue peak), time-to-1%-gap of
 the plain FP32, mixed (BF16 costs) and differentiable (smoothed T = 0.1 with
 the backward pass) forms on the same pairs, the largest pair's full pipeline
 timed end to end, a plain copy's bandwidth against the HBM peak, and the
@@ -29,6 +30,9 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+# VALU issue peak: a wave64 VALU instruction holds its SIMD's issue port for
+# 4 cycles, so 256 CUs x 4 SIMDs x 2.4 GHz / 4 = 614.4 G wave-instructions/s
+VALU_ISSUE_PEAK_G = 256 * 4 * 2.4 / 4
 BYTES_PER_NNZ = 12     # read lambda 4 + write lambda 4 + one int32 routing word 4
 BYTES_PER_ROW = 4      # row pointer
 
@@ -206,7 +210,9 @@ def sweep_roofline(cfg, seed, iters=200, temperature=0.0, **over):
     over ``iters`` Jacobi iterations: microseconds per launch and algorithmic
     GB/s (12 B per nonzero + 4 B per row) against the HBM peak.  With a
     temperature the smoothed sweep is timed instead; its partial-sum
-    recursion is bound by vector arithmetic, so only the time is reported.
+    recursion is bound by vector-instruction issue, so on the 1000-face pair
+    at T = 0.1 (seed 0) its instructions per launch, from the committed SQ
+    counter summary, are set against the VALU issue peak.
     ``over`` changes the pair's spec (e.g. ``k=96``).  The working set is the
     two record buffers, the routing words and the row pointers."""
     w = Workload(cfg, seed, **over)
@@ -222,8 +228,17 @@ def sweep_roofline(cfg, seed, iters=200, temperature=0.0, **over):
     c.timing(False)
     us = ms * 1e3 / max(n, 1)
     if temperature > 0:
-        return {"pair": f"{w.spec.faces_x}/{w.spec.faces_y} faces", "temperature": temperature,
-                "nnz": info["nnz"], "rows": info["n_rows"], "avg_launch_us": round(us, 2), "bound": "alu"}
+        out = {"pair": f"{w.spec.faces_x}/{w.spec.faces_y} faces", "temperature": temperature,
+               "nnz": info["nnz"], "rows": info["n_rows"], "avg_launch_us": round(us, 2), "bound": "alu"}
+        valu = _smoothed_valu() if (cfg, seed, temperature, not over) == (4, 0, 0.1, True) else None
+        if valu:
+            # instructions per launch from the committed SQ counter summary,
+            # over this run's launch time, against the VALU issue peak
+            g = valu["valu_insts_per_launch"] / (us * 1e-6) / 1e9
+            out.update(achieved=round(g, 1), peak=VALU_ISSUE_PEAK_G, unit="G VALU wave-instructions/s",
+                       frac=round(g / VALU_ISSUE_PEAK_G, 4), valu_insts_per_launch=valu["valu_insts_per_launch"],
+                       trans_insts_per_launch=valu["trans_insts_per_launch"])
+        return out
     nbytes = BYTES_PER_NNZ * info["nnz"] + BYTES_PER_ROW * info["n_rows"]
     gbs = nbytes / (us * 1e-6) / 1e9
     rec_bytes = 4 if w.msg == "fp32" else 8
@@ -397,6 +412,49 @@ def _traffic(n_launch_bytes_note=None):
     return rec.get("bytes_per_launch")
 
 
+def _smoothed_valu():
+    """VALU and transcendental wave-instructions per launch of the smoothed
+    sweep on the 1000-face pair at T = 0.1, from the committed rocprofv3 SQ
+    counter summary, used only while the sweep source is the one that was
+    profiled; otherwise None."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "sweep_smoothed_t0.1_1000_valu.json")
+    src = os.path.join(ROOT, "paper_2310_08230_amd", "csrc", "dual.hip")
+    if not os.path.exists(path):
+        return None
+    rec = json.load(open(path))
+    if rec.get("dual_hip_sha256") != hashlib.sha256(open(src, "rb").read()).hexdigest():
+        return None
+    return rec
+
+
+def summarize_valu(counter_csv, out_json, workload, command=""):
+    """Median SQ_INSTS_VALU and SQ_INSTS_VALU_TRANS_F32 per dispatch of the
+    smoothed FP32 update sweep (k_sweep<float, true, 0, ...>) from a
+    rocprofv3 --pmc collection; writes the summary the smoothed entry's
+    roofline reads."""
+    import csv
+    import hashlib
+    import statistics
+    rows = [r for r in csv.DictReader(open(counter_csv)) if "k_sweep<float, true, 0" in r["Kernel_Name"]]
+
+    def med(counter):
+        v = [float(r["Counter_Value"]) for r in rows if r["Counter_Name"] == counter]
+        return statistics.median(v), len(v)
+
+    valu, n = med("SQ_INSTS_VALU")
+    trans, _ = med("SQ_INSTS_VALU_TRANS_F32")
+    waves, _ = med("SQ_WAVES")
+    src = os.path.join(ROOT, "paper_2310_08230_amd", "csrc", "dual.hip")
+    rec = {"kernel": sorted({r["Kernel_Name"].strip() for r in rows})[0] if rows else "", "workload": workload,
+           "dispatches": n, "waves_per_launch": waves, "valu_insts_per_launch": valu,
+           "trans_insts_per_launch": trans, "valu_issue_peak_G_per_s": VALU_ISSUE_PEAK_G, "commands": command,
+           "dual_hip_sha256": hashlib.sha256(open(src, "rb").read()).hexdigest()}
+    with open(out_json, "w") as fh:
+        json.dump(rec, fh, indent=1)
+    print(json.dumps(rec, indent=1))
+
+
 def cpu_baseline(cfg, seed, iters, runs=3, gap_cap_s=3600.0, check_every=10, rounds=10):
     """The FP64 oracle (single thread, its build excluded) on the same pair:
     seconds per Jacobi iteration as the median of ``runs`` runs of ``iters``
@@ -534,6 +592,10 @@ def main():
         return
     if len(sys.argv) > 1 and sys.argv[1] == "--copy-calibration":
         copy_calibration(int(sys.argv[2]))
+        return
+    if len(sys.argv) > 1 and sys.argv[1] == "--summarize-valu":
+        # counter_csv out_json workload command...
+        summarize_valu(sys.argv[2], sys.argv[3], sys.argv[4], " ".join(sys.argv[5:]))
         return
     if len(sys.argv) > 1 and sys.argv[1] == "--summarize-trace":
         summarize_trace(sys.argv[2], sys.argv[3], " ".join(sys.argv[4:]))

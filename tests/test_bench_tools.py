@@ -64,3 +64,37 @@ def test_host_cpu_names_model_and_cores():
     h = bench.host_cpu()
     assert isinstance(h["cpu_model"], str) and h["cpu_model"]
     assert h["cores_available"] >= 1
+
+
+SOFT = "void (anonymous namespace)::k_sweep<float, true, 0, 0>((anonymous namespace)::SweepArgs, float const*)"
+SOFT_BOUND = "void (anonymous namespace)::k_sweep<float, true, 2, 0>((anonymous namespace)::SweepArgs, float const*)"
+
+
+def test_valu_summary_takes_the_smoothed_update_sweep(tmp_path):
+    # medians per dispatch of the smoothed update sweep only: the hard sweep
+    # and the smoothed bound-only launch must not enter them
+    path = tmp_path / "c.csv"
+    with open(path, "w", newline="") as f:
+        w = csv.DictWriter(f, fieldnames=FIELDS)
+        w.writeheader()
+        rows = [(SOFT, "SQ_INSTS_VALU", v) for v in (70.0e6, 71.0e6, 90.0e6)]
+        rows += [(SOFT, "SQ_INSTS_VALU_TRANS_F32", v) for v in (4.1e6, 4.2e6, 4.3e6)]
+        rows += [(SOFT, "SQ_WAVES", 68800.0)] * 3
+        rows += [(SWEEP, "SQ_INSTS_VALU", 1e9), (SOFT_BOUND, "SQ_INSTS_VALU", 1e9)]
+        for i, (name, counter, v) in enumerate(rows):
+            w.writerow({"Dispatch_Id": i, "Kernel_Name": name, "Counter_Name": counter, "Counter_Value": v})
+    out = tmp_path / "v.json"
+    bench.summarize_valu(str(path), str(out), "w", "cmd")
+    rec = json.load(open(out))
+    assert rec["dispatches"] == 3
+    assert rec["valu_insts_per_launch"] == 71.0e6 and rec["trans_insts_per_launch"] == 4.2e6
+    assert rec["waves_per_launch"] == 68800.0
+    assert abs(rec["valu_issue_peak_G_per_s"] - 614.4) < 1e-9
+    assert len(rec["dual_hip_sha256"]) == 64
+
+
+def test_committed_valu_summary_matches_the_sweep_source():
+    # the smoothed entry's roofline is reported only while the summary
+    # describes the current source; the committed one must
+    rec = bench._smoothed_valu()
+    assert rec is not None and rec["valu_insts_per_launch"] > 0
