@@ -243,10 +243,18 @@ def sweep_roofline(cfg, seed, iters=200, temperature=0.0, **over):
     gbs = nbytes / (us * 1e-6) / 1e9
     rec_bytes = 4 if w.msg == "fp32" else 8
     working_set = 2 * 8 * rec_bytes * info["n_free"] + 4 * info["nnz"] + 4 * (info["n_rows"] + 1)
-    return {"pair": f"{w.spec.faces_x}/{w.spec.faces_y} faces, K={w.spec.k}", "nnz": info["nnz"],
-            "rows": info["n_rows"], "working_set_bytes": working_set,
-            "avg_launch_us": round(us, 2), "bytes_per_launch": nbytes, "achieved_GBps": round(gbs, 1),
-            "frac": round(gbs / HBM_PEAK_GBS, 4)}
+    out = {"pair": f"{w.spec.faces_x}/{w.spec.faces_y} faces, K={w.spec.k}", "nnz": info["nnz"],
+           "rows": info["n_rows"], "working_set_bytes": working_set,
+           "avg_launch_us": round(us, 2), "bytes_per_launch": nbytes, "achieved_GBps": round(gbs, 1),
+           "frac": round(gbs / HBM_PEAK_GBS, 4)}
+    prof = TRAFFIC_PROFILES.get((cfg, seed, tuple(sorted(over.items()))))
+    traffic = _traffic(prof) if prof and w.msg == "fp32" else None
+    if traffic:
+        # bytes through the L2s per launch (counters, copy-calibrated) over
+        # this run's launch time, and their ratio to the algorithmic bytes
+        out.update(traffic=traffic, traffic_GBps=round(traffic / (us * 1e-6) / 1e9, 1),
+                   traffic_over_algorithmic=round(traffic / nbytes, 2))
+    return out
 
 
 FORMS = {
@@ -395,13 +403,19 @@ def copy_bandwidth(nbytes=1 << 31, reps=10):
             "frac": round(gbs / HBM_PEAK_GBS, 4)}
 
 
-def _traffic(n_launch_bytes_note=None):
-    """HBM bytes per sweep launch from the committed rocprofv3 counter summary
+# committed FETCH/WRITE summaries per sweep workload: (config, seed, spec changes) -> file
+TRAFFIC_PROFILES = {(2, 0, ()): "sweep_plain_fp32_500_hbm_traffic.json",
+                    (5, 0, ()): "sweep_largest_2000x3000_hbm_traffic.json",
+                    (5, 0, (("k", 144),)): "sweep_k144_hbm_point_hbm_traffic.json"}
+
+
+def _traffic(name="sweep_plain_fp32_500_hbm_traffic.json"):
+    """HBM bytes per sweep launch from a committed rocprofv3 counter summary
     (FETCH_SIZE and WRITE_SIZE per dispatch, each scaled by its reading on a
     plain copy kernel), used only while the sweep source is the one that was
     profiled; otherwise None."""
     import hashlib
-    path = os.path.join(ROOT, "profiles", "sweep_plain_fp32_500_hbm_traffic.json")
+    path = os.path.join(ROOT, "profiles", name)
     src = os.path.join(ROOT, "paper_2310_08230_amd", "csrc", "dual.hip")
     if not os.path.exists(path):
         return None

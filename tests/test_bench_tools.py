@@ -98,3 +98,10 @@ def test_committed_valu_summary_matches_the_sweep_source():
     # describes the current source; the committed one must
     rec = bench._smoothed_valu()
     assert rec is not None and rec["valu_insts_per_launch"] > 0
+
+
+def test_committed_traffic_summaries_match_the_sweep_source():
+    # every per-pair traffic figure the bench line can carry comes from a
+    # summary taken on the current sweep source
+    for name in bench.TRAFFIC_PROFILES.values():
+        assert bench._traffic(name) > 0, name
