@@ -335,11 +335,12 @@ def time_to_gap(cfg, seed, form="plain_fp32", check_every=10, max_iters=3000, sm
     return out
 
 
-def pipeline_run(cfg=5, seed=0, iters=None, T=0.1):
+def pipeline_run(cfg=5, seed=0, iters=None, T=0.1, rounds=10):
     """The full pipeline on one pair, timed end to end with a synchronisation
     after each stage: BF16 candidates, product space + presolve, BF16 costs,
     FP32 Jacobi iterations with the FP64 bound trace, the certified FP64
-    bound, rounding, and the smoothed backward pass (one soft sweep at the
+    bound, rounding (at most ``rounds`` perturbation rounds, as at every
+    time-to-gap check), and the smoothed backward pass (one soft sweep at the
     final multipliers and the chain to both descriptor sets).  A rounding
     that leaves rows violated is followed by the local exact repair."""
     import torch
@@ -365,7 +366,7 @@ def pipeline_run(cfg=5, seed=0, iters=None, T=0.1):
     t = mark("jacobi_fp32", t)
     lb = c.lower_bound(lam.double())
     t = mark("certified_bound_fp64", t)
-    x, pobj, feas, _ = c.round_primal(lam, seed=0)
+    x, pobj, feas, _ = c.round_primal(lam, rounds=rounds, seed=0)
     t = mark("rounding", t)
     rounded_feasible = feas
     if not feas:   # local exact repair around the violated rows
